@@ -1,0 +1,218 @@
+/*
+ * spcn.h -- C ABI of libspcn: structure-preserving color normalization (SPCN) on MI355X (gfx950).
+ *
+ * Method (arXiv 1901.03088, Sec. 2.1 and Sec. 3):
+ *   Eq. (1)  optical density  v_c = log(i0_c / I_c) per channel and pixel;
+ *   Eq. (2)  sparse NMF  min ||V - W H||_F^2 + lambda sum_j ||H(j,:)||_1 with W, H >= 0 and unit
+ *            columns of W; with W fixed, H is found pixel by pixel (here: the exact non-negative
+ *            lasso of each pixel, in closed form);
+ *   Eq. (3)  V' = P99(H_tgt) / P99(H_src) * W_tgt H_src;
+ *   Eq. (4)  I'_c = i0 exp(-V'_c);
+ *   Sec. 3.1 item 2: the basis is fitted on sampled non-white pixels and the percentile is taken
+ *   over non-white pixels only; Sec. 3.1 item 3: stains ordered by red-minus-blue OD.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless marked "host".  The
+ *     library never allocates or frees caller-visible memory.  Scratch memory comes from the
+ *     caller's workspace `ws` (size from spcn_workspace_size); it needs no initialisation.
+ *   - uint8 images are interleaved RGB (HWC), contiguous, 3 bytes per pixel, 4-byte aligned.
+ *   - A stain basis W is 6 floats, 3x2 column-major: W[c + 3*j], c = R,G,B, j = 0 (hematoxylin),
+ *     1 (eosin).  Columns should be non-negative and non-parallel (unit norm is not required).
+ *   - Densities are planar FP32: H[j*n_px + i].
+ *   - lambda follows Eq. (2) literally (no 1/2 on the squared error): a per-pixel penalty
+ *     lambda*(h0 + h1) against ||v - W h||^2.
+ *   - All work is enqueued on `stream`; nothing synchronises the host, allocates, or records a
+ *     memset, so every entry point may be captured into a hipGraph.
+ *   - Argument errors are detected on the host before anything is enqueued and returned as a
+ *     status; spcn_last_error() then describes the problem (thread-local).  Conditions that depend
+ *     on device data (no tissue, percentile in the overflow bin, degenerate basis) never abort:
+ *     they are written as SPCN_FLAG_* bits into the caller's device `flags` words.
+ *   - Nothing throws across this ABI and the library never prints.
+ */
+#ifndef SPCN_H
+#define SPCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPCN_OK = 0,
+    SPCN_E_ARG = 1,          /* invalid argument: null pointer, size, range, alignment          */
+    SPCN_E_WORKSPACE = 2,    /* workspace missing or smaller than spcn_workspace_size()         */
+    SPCN_E_HIP = 3,          /* a HIP runtime call failed; spcn_last_error() has its message    */
+    SPCN_E_UNSUPPORTED = 4   /* valid request this build does not implement                     */
+} spcn_status;
+
+/* Device-side result flags, one int32 word per stain (bit OR). */
+#define SPCN_FLAG_NO_TISSUE 1   /* no pixel passed the non-white mask: scale kept at 1            */
+#define SPCN_FLAG_RANGE     2   /* percentile fell in the last histogram bin: raise hist_hi       */
+#define SPCN_FLAG_BIN0      4   /* percentile fell in bin 0 (stain absent): scale kept at 1       */
+#define SPCN_FLAG_BASIS     8   /* the basis has a singular Gram matrix: densities set to 0       */
+#define SPCN_FLAG_SHORT    16   /* basis estimation drew fewer tissue samples than requested      */
+
+#define SPCN_HIST_BINS 256
+
+typedef struct {
+    float i0[3];        /* Eq. (1) maximum intensity per channel (255 for 8-bit input; 1 for [0,1]) */
+    float lambda;       /* Eq. (2) sparsity weight of the per-pixel density solve, >= 0            */
+    int32_t white_sum;  /* non-white mask (Sec. 3.1 item 2): tissue iff R+G+B < white_sum; for float
+                           input, iff 255*(x0+x1+x2) < white_sum in FP32; <= 0 disables the mask   */
+    float percentile;   /* Eq. (3) percentile, in (0, 100]                                         */
+    float hist_hi[2];   /* per-stain density histogram range [0, hist_hi): power of two in
+                           [2^-8, 2^8]; 256 bins; values beyond land in the last bin               */
+} spcn_params;
+
+/* Fills the paper's defaults: i0 = 255, lambda = 0.01, white_sum = 660 (mean intensity 220),
+ * percentile 99, hist_hi = 4. */
+void spcn_default_params(spcn_params* p);
+
+/* Operation codes for spcn_workspace_size. */
+#define SPCN_OP_DENSITIES         0
+#define SPCN_OP_NORMALIZE         1
+#define SPCN_OP_ESTIMATE_BASIS    2
+#define SPCN_OP_NORMALIZE_BATCHED 3
+#define SPCN_OP_ESTIMATE_BATCHED  4
+#define SPCN_OP_FORWARD_F32       5
+#define SPCN_OP_BACKWARD_F32      6
+
+/* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
+ * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
+ * for an unknown op. */
+size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samples);
+
+/* Densities of every pixel (Eq. 1 + Eq. 2 with W fixed) and their non-white histogram with its
+ * percentile (Eq. 3 numerator when applied to a target image).
+ *   img       uint8 HWC, height*width pixels
+ *   w         [6] basis
+ *   h_out     [2][n_px] FP32 densities, or NULL (histogram only)
+ *   hist_out  [2][256] uint64 counts over non-white pixels (overwritten)
+ *   p99_out   [2] histogram percentile per stain (interpolated in the crossing bin), or NULL
+ *   flags_out [2] SPCN_FLAG_* per stain, or NULL
+ * Histogram counts are exact: bin decisions agree with FP64 arithmetic on every pixel. */
+spcn_status spcn_densities(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                           const spcn_params* p, float* h_out, uint64_t* hist_out, float* p99_out,
+                           int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Optional device outputs of spcn_normalize (any member may be NULL). */
+typedef struct {
+    uint64_t* hist;     /* [2][256] source histogram                    */
+    float* p99_src;     /* [2] source percentile P99(H_src)             */
+    float* scale;       /* [2] applied scale P99(H_tgt) / P99(H_src)    */
+    int32_t* flags;     /* [2] SPCN_FLAG_* per stain                    */
+} spcn_norm_stats;
+
+/* Fused normalisation of one uint8 image (Eqs. 1-4): pass 1 solves every pixel and builds the
+ * non-white density histogram; pass 2 takes the percentile, scales, recolours with w_tgt and
+ * writes uint8 (round half to even, clamped to [0, 255]).
+ *   src, out   uint8 HWC images of height*width pixels (out may not alias src)
+ *   w_src      [6] source basis;  w_tgt [6] target basis
+ *   scale_tgt  [2] target percentiles P99(H_tgt) (e.g. p99_out of spcn_densities on the target)
+ *   i0_out     host [3] intensity of Eq. (4), or NULL for p->i0
+ *   st         host struct of optional device outputs, or NULL */
+spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                           const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                           const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Pass 2 of spcn_normalize on its own: percentile of Eq. 3 from a given non-white histogram (from
+ * spcn_densities on this image, or the element-wise sum of the histograms of its shards), scaling,
+ * recolouring and Eq. 4.  Arguments as for spcn_normalize; hist is an input here and st->hist is
+ * ignored.  spcn_densities followed by spcn_recolor equals spcn_normalize. */
+spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                         const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                         const spcn_params* p, const uint64_t* hist, uint8_t* out,
+                         const spcn_norm_stats* st, hipStream_t stream);
+
+/* Basis estimation (Eq. 2 with both factors free; Sec. 3.1 items 2-3, Sec. 3.2 item 2): draws
+ * n_samples non-white pixels with a counter-based SplitMix64 stream (candidate t -> pixel
+ * floor(splitmix64(seed + (t+1)*0x9E3779B97F4A7C15) * n_px / 2^64), first n_samples non-white
+ * candidates in draw order, at most 64*n_samples candidates), then n_iter alternating exact
+ * H-steps and block-coordinate W-steps on the non-negative unit ball, normalises the columns and
+ * puts hematoxylin (larger red-minus-blue OD) first.
+ *   lambda_nmf   Eq. (2) sparsity weight for the fit (0.1 in the paper)
+ *   w_init       [6] initial basis, or NULL for the unit reference H&E vectors
+ *                [0.65, 0.70, 0.29] and [0.07, 0.99, 0.11]
+ *   w_out        [6] fitted basis;  sample_p99 [2] nearest-rank percentile (p->percentile) of the
+ *                fitted densities of the samples, or NULL;  flags_out [2] or NULL */
+spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t width,
+                                const spcn_params* p, float lambda_nmf, int64_t n_samples,
+                                uint64_t seed, int32_t n_iter, const float* w_init, float* w_out,
+                                float* sample_p99, int32_t* flags_out, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* One tile of a batch (device-resident descriptor array). */
+typedef struct {
+    const uint8_t* src;   /* uint8 HWC tile, 4-byte aligned */
+    uint8_t* out;         /* uint8 HWC output of the same size */
+    int64_t height, width;
+} spcn_tile;
+
+/* Basis estimation for every tile of a batch (same algorithm as spcn_estimate_basis, one
+ * workgroup per tile).  tiles: device array of n_tiles descriptors; w_out [n_tiles][6];
+ * sample_p99 [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.  Tile t uses seed + t. */
+spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t max_tile_px,
+                                        const spcn_params* p, float lambda_nmf, int64_t n_samples,
+                                        uint64_t seed, int32_t n_iter, const float* w_init,
+                                        float* w_out, float* sample_p99, int32_t* flags_out,
+                                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Normalises every tile of a batch to one target (Eqs. 1-4, each tile with its own basis
+ * w_src[t] and its own percentile) in ONE persistent kernel launch: a global work queue hands out
+ * all pass-1 chunks before any pass-2 chunk; the last pass-1 chunk of a tile finalises that tile's
+ * percentile and releases its pass-2 chunks.
+ *   w_src [n_tiles][6]; w_tgt [6]; scale_tgt [2]; i0_out host [3] or NULL;
+ *   p99_out, scale_out [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.
+ * Results are identical to calling spcn_normalize on each tile. */
+spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px,
+                                   const float* w_src, const float* w_tgt, const float* scale_tgt,
+                                   const float* i0_out, const spcn_params* p, float* p99_out,
+                                   float* scale_out, int32_t* flags_out, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/* Differentiable float path (extension: normalisation as a training-time augmentation layer).
+ * x, y: [n][3][height][width] FP32 in [0, 1] (p->i0 is the input's i0, normally 1).  Per-sample
+ * parameters are read at sample*stride (stride 0 broadcasts one value): w_src (stride in floats,
+ * 6 per basis), w_tgt (6), scale_tgt (2).  The percentile is the EXACT nearest-rank order statistic
+ * of each sample's non-white densities, k = max(1, ceil(q * n)); the selected pixel (smallest index
+ * among equal values) is returned in sel_idx so the backward pass can route its gradient.
+ *   i0_out   host [3] output intensity of Eq. (4), or NULL for p->i0
+ *   p99_out [n][2], scale_out [n][2], sel_idx [n][2] (int64), flags_out [n][2]: saved state. */
+spcn_status spcn_normalize_f32(const float* x, int64_t n, int64_t height, int64_t width,
+                               const float* w_src, int64_t w_src_stride, const float* w_tgt,
+                               int64_t w_tgt_stride, const float* scale_tgt, int64_t scale_stride,
+                               const float* i0_out, const spcn_params* p, float* y, float* p99_out,
+                               float* scale_out, int64_t* sel_idx, int32_t* flags_out, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of spcn_normalize_f32 with w_src held fixed (the mask and the rank selection are
+ * piecewise constant): given dL/dy, returns dL/dx, dL/dw_tgt and dL/dscale_tgt.  Per pixel the
+ * density Jacobian comes from the active set's KKT system (h_F = G_FF^-1 (W_F^T v - lambda/2));
+ * the percentile contributes through the density of the selected pixel sel_idx.
+ *   p99, sel_idx, flags: the forward's saved outputs
+ *   grad_x [n][3][h][w]; grad_w_tgt [n][6] per sample; grad_scale [n][2] per sample
+ *   (sum over samples for a shared parameter). */
+spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, int64_t width,
+                                    const float* w_src, int64_t w_src_stride, const float* w_tgt,
+                                    int64_t w_tgt_stride, const float* scale_tgt,
+                                    int64_t scale_stride, const float* i0_out, const spcn_params* p,
+                                    const float* p99, const int64_t* sel_idx, const int32_t* flags,
+                                    const float* grad_y, float* grad_x, float* grad_w_tgt,
+                                    float* grad_scale, void* ws, size_t ws_bytes,
+                                    hipStream_t stream);
+
+/* Static description of a status code. */
+const char* spcn_status_string(spcn_status s);
+/* Detail of the last error returned on this thread ("" if none). */
+const char* spcn_last_error(void);
+/* Library version string. */
+const char* spcn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPCN_H */

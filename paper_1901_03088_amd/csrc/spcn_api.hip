@@ -1,0 +1,279 @@
+// spcn_api.hip -- host side of the C ABI declared in include/spcn.h: argument validation,
+// workspace layout, error reporting and dispatch to the kernel launchers.
+#include "spcn_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+namespace spcn {
+
+static thread_local char g_err[512];
+
+spcn_status fail(spcn_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+spcn_status hip_fail(hipError_t e, const char* what) {
+    return fail(SPCN_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+spcn_status dev_info(DevInfo* out) {
+    static int cached_id[64];
+    static int cached_cus[64];
+    static bool have[64] = {false};
+    int id = 0;
+    hipError_t e = hipGetDevice(&id);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (id < 0 || id >= 64) return fail(SPCN_E_UNSUPPORTED, "device id %d out of range", id);
+    if (!have[id]) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, id);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(MultiprocessorCount)");
+        cached_cus[id] = cus > 0 ? cus : 1;
+        cached_id[id] = id;
+        have[id] = true;
+    }
+    out->id = cached_id[id];
+    out->cus = cached_cus[id];
+    return SPCN_OK;
+}
+
+ParamsK make_params(const spcn_params* p) {
+    ParamsK k{};
+    for (int c = 0; c < 3; ++c) k.i0[c] = p->i0[c];
+    k.lambda = p->lambda;
+    k.white_sum = p->white_sum;
+    k.q = p->percentile / 100.0f;
+    k.q64 = (double)p->percentile / 100.0;
+    k.hist_hi[0] = p->hist_hi[0];
+    k.hist_hi[1] = p->hist_hi[1];
+    return k;
+}
+
+static bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
+
+static bool pow2(float x) {
+    if (!finite_pos(x)) return false;
+    int e;
+    float m = frexpf(x, &e);
+    return m == 0.5f;
+}
+
+static spcn_status check_params(const spcn_params* p, bool u8_input) {
+    if (!p) return fail(SPCN_E_ARG, "params is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(p->i0[c])) return fail(SPCN_E_ARG, "i0[%d] = %g must be finite and > 0", c, (double)p->i0[c]);
+    if (u8_input)
+        for (int c = 0; c < 3; ++c)
+            if (p->i0[c] > 65536.0f) return fail(SPCN_E_ARG, "i0[%d] = %g too large", c, (double)p->i0[c]);
+    if (!(isfinite(p->lambda) && p->lambda >= 0.0f))
+        return fail(SPCN_E_ARG, "lambda = %g must be finite and >= 0", (double)p->lambda);
+    if (!(isfinite(p->percentile) && p->percentile > 0.0f && p->percentile <= 100.0f))
+        return fail(SPCN_E_ARG, "percentile = %g must lie in (0, 100]", (double)p->percentile);
+    for (int j = 0; j < 2; ++j) {
+        if (!pow2(p->hist_hi[j]) || p->hist_hi[j] < 0.00390625f || p->hist_hi[j] > 256.0f)
+            return fail(SPCN_E_ARG, "hist_hi[%d] = %g must be a power of two in [2^-8, 2^8]", j,
+                        (double)p->hist_hi[j]);
+    }
+    return SPCN_OK;
+}
+
+static spcn_status check_image(const void* ptr, int64_t height, int64_t width, const char* name) {
+    if (!ptr) return fail(SPCN_E_ARG, "%s is NULL", name);
+    if (height <= 0 || width <= 0) return fail(SPCN_E_ARG, "%s: height and width must be > 0 (got %lld x %lld)",
+                                               name, (long long)height, (long long)width);
+    if (height > ((int64_t)1 << 36) / width) return fail(SPCN_E_ARG, "%s: more than 2^36 pixels", name);
+    if (((uintptr_t)ptr) & 3) return fail(SPCN_E_ARG, "%s must be 4-byte aligned", name);
+    return SPCN_OK;
+}
+
+static spcn_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return SPCN_OK;
+    if (!ws) return fail(SPCN_E_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
+    if (ws_bytes < need) return fail(SPCN_E_WORKSPACE, "workspace has %zu bytes, need %zu", ws_bytes, need);
+    if (((uintptr_t)ws) & 255) return fail(SPCN_E_WORKSPACE, "workspace must be 256-byte aligned");
+    return SPCN_OK;
+}
+
+}  // namespace spcn
+
+using namespace spcn;
+
+#define SPCN_CHECK(x)                         \
+    do {                                      \
+        spcn_status s_ = (x);                 \
+        if (s_ != SPCN_OK) return s_;         \
+    } while (0)
+
+extern "C" {
+
+void spcn_default_params(spcn_params* p) {
+    if (!p) return;
+    for (int c = 0; c < 3; ++c) p->i0[c] = 255.0f;
+    p->lambda = 0.01f;
+    p->white_sum = 660;
+    p->percentile = 99.0f;
+    p->hist_hi[0] = 4.0f;
+    p->hist_hi[1] = 4.0f;
+}
+
+size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samples) {
+    if (n_px < 0 || n_items < 0 || n_samples < 0) return 0;
+    switch (op) {
+        case SPCN_OP_DENSITIES:
+        case SPCN_OP_NORMALIZE:
+            return u8_workspace_bytes();
+        case SPCN_OP_ESTIMATE_BASIS:
+            return basis_workspace_bytes(n_samples);
+        case SPCN_OP_ESTIMATE_BATCHED:
+            return basis_batched_workspace_bytes(n_items, n_samples);
+        case SPCN_OP_NORMALIZE_BATCHED:
+            return batched_workspace_bytes(n_items, n_px);
+        case SPCN_OP_FORWARD_F32:
+            return f32_forward_workspace_bytes(n_px, n_items);
+        case SPCN_OP_BACKWARD_F32:
+            return f32_backward_workspace_bytes(n_px, n_items);
+        default:
+            return 0;
+    }
+}
+
+spcn_status spcn_densities(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                           const spcn_params* p, float* h_out, uint64_t* hist_out, float* p99_out,
+                           int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    (void)ws; (void)ws_bytes;
+    SPCN_CHECK(check_image(img, height, width, "img"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w) return fail(SPCN_E_ARG, "w is NULL");
+    if (!hist_out) return fail(SPCN_E_ARG, "hist_out is NULL");
+    if (h_out && (((uintptr_t)h_out) & 15)) return fail(SPCN_E_ARG, "h_out must be 16-byte aligned");
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_densities(img, height * width, w, make_params(p), h_out, hist_out, p99_out, flags_out,
+                                    dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_densities launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                           const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                           const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_image(src, height, width, "src"));
+    SPCN_CHECK(check_image(out, height, width, "out"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w_src || !w_tgt || !scale_tgt) return fail(SPCN_E_ARG, "w_src, w_tgt and scale_tgt must be non-NULL");
+    const int64_t n = height * width;
+    if ((const void*)src < (const void*)(out + 3 * n) && (const void*)out < (const void*)(src + 3 * n))
+        return fail(SPCN_E_ARG, "out must not overlap src");
+    float io[3];
+    for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
+    uint64_t* hist = st && st->hist ? st->hist : nullptr;
+    if (!hist) {
+        SPCN_CHECK(check_ws(ws, ws_bytes, u8_workspace_bytes()));
+        hist = static_cast<uint64_t*>(ws);
+    }
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_normalize(src, n, w_src, w_tgt, scale_tgt, io, make_params(p), out, hist,
+                                    st ? st->p99_src : nullptr, st ? st->scale : nullptr,
+                                    st ? st->flags : nullptr, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_normalize launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                         const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                         const spcn_params* p, const uint64_t* hist, uint8_t* out,
+                         const spcn_norm_stats* st, hipStream_t stream) {
+    SPCN_CHECK(check_image(src, height, width, "src"));
+    SPCN_CHECK(check_image(out, height, width, "out"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w_src || !w_tgt || !scale_tgt || !hist)
+        return fail(SPCN_E_ARG, "w_src, w_tgt, scale_tgt and hist must be non-NULL");
+    const int64_t n = height * width;
+    if ((const void*)src < (const void*)(out + 3 * n) && (const void*)out < (const void*)(src + 3 * n))
+        return fail(SPCN_E_ARG, "out must not overlap src");
+    float io[3];
+    for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_recolor(src, n, w_src, w_tgt, scale_tgt, io, make_params(p), out, hist,
+                                  st ? st->p99_src : nullptr, st ? st->scale : nullptr, st ? st->flags : nullptr,
+                                  dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_recolor launch");
+    return SPCN_OK;
+}
+
+static spcn_status check_fit(float lambda_nmf, int64_t n_samples, int32_t n_iter, int64_t max_samples) {
+    if (!(isfinite(lambda_nmf) && lambda_nmf >= 0.0f))
+        return fail(SPCN_E_ARG, "lambda_nmf = %g must be finite and >= 0", (double)lambda_nmf);
+    if (n_samples < 1 || n_samples > max_samples)
+        return fail(SPCN_E_ARG, "n_samples = %lld must lie in [1, %lld]", (long long)n_samples, (long long)max_samples);
+    if (n_iter < 0 || n_iter > 100000) return fail(SPCN_E_ARG, "n_iter = %d must lie in [0, 100000]", (int)n_iter);
+    return SPCN_OK;
+}
+
+spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t width, const spcn_params* p,
+                                float lambda_nmf, int64_t n_samples, uint64_t seed, int32_t n_iter,
+                                const float* w_init, float* w_out, float* sample_p99, int32_t* flags_out,
+                                void* ws, size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_image(img, height, width, "img"));
+    SPCN_CHECK(check_params(p, true));
+    SPCN_CHECK(check_fit(lambda_nmf, n_samples, n_iter, kMaxBasisSamples));
+    if (!w_out) return fail(SPCN_E_ARG, "w_out is NULL");
+    SPCN_CHECK(check_ws(ws, ws_bytes, basis_workspace_bytes(n_samples)));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_estimate_basis(img, height * width, make_params(p), lambda_nmf, n_samples, seed, n_iter,
+                                         w_init, w_out, sample_p99, flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_estimate_basis launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t max_tile_px,
+                                        const spcn_params* p, float lambda_nmf, int64_t n_samples,
+                                        uint64_t seed, int32_t n_iter, const float* w_init, float* w_out,
+                                        float* sample_p99, int32_t* flags_out, void* ws, size_t ws_bytes,
+                                        hipStream_t stream) {
+    (void)max_tile_px;
+    if (!tiles) return fail(SPCN_E_ARG, "tiles is NULL");
+    if (n_tiles < 1) return fail(SPCN_E_ARG, "n_tiles = %d must be >= 1", (int)n_tiles);
+    SPCN_CHECK(check_params(p, true));
+    SPCN_CHECK(check_fit(lambda_nmf, n_samples, n_iter, basis_tile_max_samples()));
+    if (!w_out) return fail(SPCN_E_ARG, "w_out is NULL");
+    SPCN_CHECK(check_ws(ws, ws_bytes, basis_batched_workspace_bytes(n_tiles, n_samples)));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_estimate_basis_batched(tiles, n_tiles, make_params(p), lambda_nmf, n_samples, seed, n_iter,
+                                                 w_init, w_out, sample_p99, flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_estimate_basis_batched launch");
+    return SPCN_OK;
+}
+
+const char* spcn_status_string(spcn_status s) {
+    switch (s) {
+        case SPCN_OK: return "ok";
+        case SPCN_E_ARG: return "invalid argument";
+        case SPCN_E_WORKSPACE: return "workspace missing or too small";
+        case SPCN_E_HIP: return "HIP runtime error";
+        case SPCN_E_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* spcn_last_error(void) { return g_err; }
+
+const char* spcn_version(void) { return "spcn-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,625 @@
+// spcn_basis.hip -- stain-basis estimation on gfx950: sample non-white pixels, fit the sparse NMF of
+// Eq. (2) (Sec. 2.1 step 2), normalise the columns and put hematoxylin first (Sec. 3.1 item 3).
+//
+// Sampling (Sec. 3.1 item 2, Sec. 3.2 item 2): candidate t is pixel floor(z_t * n_px / 2^64) with
+// z_t the SplitMix64 finaliser of seed + (t+1)*0x9E3779B97F4A7C15 (Steele, Lea & Flood 2014);
+// the first n_s non-white candidates in draw order are kept, at most 64*n_s candidates are drawn.
+//
+// Fit: T rounds of (exact H-step for every sample with W fixed) then (one block-coordinate pass over
+// the two columns of W, each the projection onto {w >= 0, ||w|| <= 1} of the column's unconstrained
+// least-squares update u = w_j + (B_j - W A_j) / A_jj, with A = H H^T, B = V H^T).  The unit-norm
+// equality of Eq. (2) is imposed after the last round.  The fit is small (<= a few 10^5 samples), so
+// it runs in FP64 throughout (FP64 vector rate equals FP32 scalar rate on this chip); reductions
+// have a fixed order, so results are bitwise reproducible.
+//
+// Two layouts:
+//   * one image with many samples: several workgroups per H-step, per-workgroup FP64 partial sums,
+//     the last workgroup of each round (atomic ticket) reduces them in order and updates W;
+//   * a batch of tiles: one 1024-thread workgroup per tile, samples held in registers, every round
+//     inside the workgroup.
+#include "spcn_internal.h"
+#include "spcn_device.hpp"
+
+namespace spcn {
+
+namespace {
+
+constexpr int SAMPLE_BLOCK = 1024;     // candidates per workgroup and round
+constexpr int MAX_ROUNDS = 3;          // candidate budget 4, 12 and 48 times n_s
+constexpr int ITER_THREADS = 256;
+constexpr int ITER_MAX_BLOCKS = 512;
+constexpr int TILE_THREADS = 1024;
+constexpr int TILE_SPT = 4;            // samples per thread in the batched kernel (n_s <= 4096)
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t t) {
+    uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int64_t candidate_pixel(uint64_t seed, uint64_t t, int64_t n_px) {
+    return (int64_t)__umul64hi(splitmix64(seed, t), (uint64_t)n_px);
+}
+
+__device__ __forceinline__ bool non_white(const uint8_t* img, int64_t i, int32_t white_sum) {
+    if (white_sum <= 0) return true;
+    const uint8_t* p = img + 3 * i;
+    return (int32_t)p[0] + (int32_t)p[1] + (int32_t)p[2] < white_sum;
+}
+
+// Block-wide exclusive prefix count of a predicate (blockDim.x multiple of 64).  Returns this
+// thread's rank among the set predicates; *total receives the block's count.
+__device__ int block_rank(bool pred, int* s_wave, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t m = __ballot(pred);
+    const int below = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (lane == 0) s_wave[wave] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        int c = s_wave[w];
+        off += (w < wave) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + below;
+}
+
+// Sum of a double over the block in a fixed order (wave shuffles, then waves in order).
+__device__ double block_sum(double x, double* s_red) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) s_red[wave] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += s_red[w];
+    __syncthreads();
+    return t;
+}
+
+// FP64 basis for the H-step: Gram matrix and its determinant, from a double W.
+struct NmfBasis {
+    double w[6];
+    double g00, g01, g11, det, half_lambda;
+    int ok;
+};
+
+__device__ inline void nmf_basis(const double* W, double lambda, NmfBasis& B) {
+#pragma clang fp contract(off)
+    for (int i = 0; i < 6; ++i) B.w[i] = W[i];
+    double g00 = W[0] * W[0]; g00 = g00 + W[1] * W[1]; g00 = g00 + W[2] * W[2];
+    double g01 = W[0] * W[3]; g01 = g01 + W[1] * W[4]; g01 = g01 + W[2] * W[5];
+    double g11 = W[3] * W[3]; g11 = g11 + W[4] * W[4]; g11 = g11 + W[5] * W[5];
+    B.g00 = g00; B.g01 = g01; B.g11 = g11;
+    B.det = g00 * g11 - g01 * g01;
+    B.half_lambda = 0.5 * lambda;
+    B.ok = g00 > 0.0 && g11 > 0.0 && B.det > 0.0;
+}
+
+// Exact non-negative lasso of one sample (Eq. 2 with W fixed): h_j = max(0, min(p_j, f_j)) with
+// f = G^-1 b, p_j = b_j / g_jj (valid because g01 >= 0 for a non-negative W).  Columns of zero
+// norm give zero densities.
+__device__ inline void nmf_solve(const NmfBasis& B, double v0, double v1, double v2, double& h0, double& h1) {
+#pragma clang fp contract(off)
+    const double* W = B.w;
+    double b0 = W[0] * v0; b0 = b0 + W[1] * v1; b0 = b0 + W[2] * v2; b0 = b0 - B.half_lambda;
+    double b1 = W[3] * v0; b1 = b1 + W[4] * v1; b1 = b1 + W[5] * v2; b1 = b1 - B.half_lambda;
+    if (B.ok) {
+        double f0 = (B.g11 * b0 - B.g01 * b1) / B.det;
+        double f1 = (B.g00 * b1 - B.g01 * b0) / B.det;
+        double p0 = b0 / B.g00, p1 = b1 / B.g11;
+        double t0 = p0 < f0 ? p0 : f0, t1 = p1 < f1 ? p1 : f1;
+        h0 = t0 > 0.0 ? t0 : 0.0;
+        h1 = t1 > 0.0 ? t1 : 0.0;
+    } else {
+        double p0 = B.g00 > 0.0 ? b0 / B.g00 : 0.0, p1 = B.g11 > 0.0 ? b1 / B.g11 : 0.0;
+        // one live column (or none): the problem is a scalar lasso in the better one
+        double o0 = -p0 * b0, o1 = -p1 * b1;   // objective drop of each single-column candidate
+        h0 = 0.0; h1 = 0.0;
+        if (p0 > 0.0 && (o0 <= o1 || !(p1 > 0.0))) h0 = p0;
+        else if (p1 > 0.0) h1 = p1;
+    }
+}
+
+// One block-coordinate pass of the W-step from the 9 sums (A00, A01, A11, B00, B01, B10, B11, B20,
+// B21 with B_cj = sum v_c h_j), in place on W.
+__device__ inline void w_step(double* W, const double* s) {
+#pragma clang fp contract(off)
+    const double A[2][2] = {{s[0], s[1]}, {s[1], s[2]}};
+    for (int j = 0; j < 2; ++j) {
+        if (!(A[j][j] > 0.0)) continue;                 // stain unused by every sample: keep w_j
+        double u[3], nrm2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double WAj = W[c] * A[0][j] + W[c + 3] * A[1][j];
+            double Bcj = s[3 + 2 * c + j];
+            double uc = W[c + 3 * j] + (Bcj - WAj) / A[j][j];
+            u[c] = uc > 0.0 ? uc : 0.0;
+            nrm2 = nrm2 + u[c] * u[c];
+        }
+        if (!(nrm2 > 0.0)) continue;                    // projection is zero: keep w_j
+        double sc = nrm2 > 1.0 ? 1.0 / sqrt(nrm2) : 1.0;
+        for (int c = 0; c < 3; ++c) W[c + 3 * j] = u[c] * sc;
+    }
+}
+
+// Unit columns, then hematoxylin (larger red-minus-blue OD) first.
+__device__ inline void finish_basis(double* W) {
+#pragma clang fp contract(off)
+    for (int j = 0; j < 2; ++j) {
+        double n = sqrt(W[3 * j] * W[3 * j] + W[3 * j + 1] * W[3 * j + 1] + W[3 * j + 2] * W[3 * j + 2]);
+        if (n > 0.0)
+            for (int c = 0; c < 3; ++c) W[c + 3 * j] /= n;
+    }
+    if (W[3] - W[5] > W[0] - W[2]) {
+        for (int c = 0; c < 3; ++c) { double t = W[c]; W[c] = W[c + 3]; W[c + 3] = t; }
+    }
+}
+
+__device__ inline void initial_basis(const float* w_init, double* W) {
+    if (w_init) {
+        for (int i = 0; i < 6; ++i) W[i] = (double)w_init[i];
+        return;
+    }
+    // unit reference vectors of hematoxylin [0.65, 0.70, 0.29] and eosin [0.07, 0.99, 0.11], rounded
+    // to FP32 like any basis handed to the library
+    const double hr[3] = {0.65, 0.70, 0.29}, er[3] = {0.07, 0.99, 0.11};
+    double nh = sqrt(hr[0] * hr[0] + hr[1] * hr[1] + hr[2] * hr[2]);
+    double ne = sqrt(er[0] * er[0] + er[1] * er[1] + er[2] * er[2]);
+    for (int c = 0; c < 3; ++c) {
+        W[c] = (double)(float)(hr[c] / nh);
+        W[c + 3] = (double)(float)(er[c] / ne);
+    }
+}
+
+// Exact k-th smallest (1-based) of n non-negative doubles produced by `val(i)`, by a most-
+// significant-digit radix select over their bit patterns (monotone for x >= 0), block-wide.
+template <class F>
+__device__ double block_select(int64_t n, int64_t k, F val, uint32_t* s_hist, int* s_misc) {
+    uint64_t prefix = 0, pmask = 0;
+    int64_t kk = k;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = threadIdx.x; b < 256; b += blockDim.x) s_hist[b] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            uint64_t u = (uint64_t)__double_as_longlong(val(i));
+            if ((u & pmask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t acc = 0;
+            int d = 0;
+            for (; d < 256; ++d) {
+                if (acc + (int64_t)s_hist[d] >= kk) break;
+                acc += s_hist[d];
+            }
+            s_misc[0] = d;
+            s_misc[1] = (int)(kk - acc);
+        }
+        __syncthreads();
+        prefix |= (uint64_t)s_misc[0] << shift;
+        pmask |= (uint64_t)255 << shift;
+        kk = s_misc[1];
+        __syncthreads();
+    }
+    return __longlong_as_double((long long)prefix);
+}
+
+// ------------------------------------------------------------------ one image, many samples
+
+struct BasisWork {          // layout of the caller's workspace (single image)
+    int64_t n_s, max_cand;
+    int32_t n_acc;          // samples kept so far
+    uint32_t ticket;        // arrival counter of the current round's workgroups
+    double W[6];
+    int32_t flags;
+};
+
+struct SampleArgs {
+    const uint8_t* img; int64_t n_px; int32_t white_sum; uint64_t seed;
+    int64_t t0, t_end;      // candidates [t0, t_end) form this round
+    int64_t nb;             // workgroups in this round
+    BasisWork* bw;
+    int64_t* staging;       // [nb][SAMPLE_BLOCK]
+    int32_t* counts;        // [nb]
+    int64_t* idx;           // [n_s] kept pixel indices
+};
+
+__global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_round(SampleArgs a) {
+    __shared__ int s_wave[SAMPLE_BLOCK / 64];
+    if (a.bw->n_acc >= a.bw->n_s) return;                  // earlier rounds found enough
+    const int64_t t = a.t0 + (int64_t)blockIdx.x * SAMPLE_BLOCK + threadIdx.x;
+    bool keep = false;
+    int64_t pix = 0;
+    if (t < a.t_end) {
+        pix = candidate_pixel(a.seed, (uint64_t)t, a.n_px);
+        keep = non_white(a.img, pix, a.white_sum);
+    }
+    int total;
+    int r = block_rank(keep, s_wave, &total);
+    if (keep) a.staging[(int64_t)blockIdx.x * SAMPLE_BLOCK + r] = pix;
+    if (threadIdx.x == 0) a.counts[blockIdx.x] = total;
+}
+
+// Appends the round's kept candidates, in draw order, until n_s are kept (one workgroup): an
+// exclusive scan of the per-workgroup counts, then one wavefront per source workgroup copies.
+constexpr int MERGE_MAX_BLOCKS = 12288;   // rounds of at most 48 * 262144 candidates
+__global__ __launch_bounds__(1024) void k_sample_merge(SampleArgs a) {
+    __shared__ int s_off[MERGE_MAX_BLOCKS];
+    __shared__ int s_part[1024];
+    BasisWork* bw = a.bw;
+    if (bw->n_acc >= bw->n_s) return;
+    const int base = bw->n_acc;
+    const int nb = (int)a.nb;
+    const int per = (nb + 1023) / 1024;
+    const int t = threadIdx.x;
+    int run = 0;
+    for (int i = 0; i < per; ++i) {
+        int b = t * per + i;
+        if (b < nb) { s_off[b] = run; run += a.counts[b]; }
+    }
+    s_part[t] = run;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = t >= o ? s_part[t - o] : 0;
+        __syncthreads();
+        s_part[t] += v;
+        __syncthreads();
+    }
+    const int excl = t ? s_part[t - 1] : 0;
+    for (int i = 0; i < per; ++i) {
+        int b = t * per + i;
+        if (b < nb) s_off[b] += excl;
+    }
+    __syncthreads();
+    const int64_t room = bw->n_s - base;
+    const int lane = t & 63, wave = t >> 6;
+    for (int b = wave; b < nb; b += 16) {
+        const int off = s_off[b];
+        if (off >= room) continue;
+        const int c = a.counts[b];
+        for (int i = lane; i < c && off + i < room; i += 64) a.idx[base + off + i] = a.staging[(int64_t)b * SAMPLE_BLOCK + i];
+    }
+    __syncthreads();
+    if (t == 0) bw->n_acc = (int)min((int64_t)base + s_part[1023], bw->n_s);
+}
+
+__global__ void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->ticket = 0; bw->flags = 0;
+        initial_basis(w_init, bw->W);
+    }
+}
+
+// FP64 optical densities of the kept samples, planar [3][n_s].
+__global__ __launch_bounds__(256) void k_od_gather(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
+                                                   float i00, float i01, float i02, double* V) {
+    __shared__ double s_od[3 * kHistBins];
+    const float i0[3] = {i00, i01, i02};
+    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
+        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)i0[c], k);
+    __syncthreads();
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t* p = img + 3 * idx[i];
+        for (int c = 0; c < 3; ++c) V[c * ns + i] = s_od[c * kHistBins + p[c]];
+    }
+}
+
+struct IterArgs {
+    BasisWork* bw;
+    const double* V;        // [3][n_s]
+    double* partial;        // [gridDim][9]
+    double lambda;
+};
+
+// One NMF round: H-step of every sample, FP64 partial sums per workgroup; the last workgroup to
+// arrive reduces the partials in workgroup order and performs the W-step.
+__global__ __launch_bounds__(ITER_THREADS) void k_nmf_round(IterArgs a) {
+    __shared__ double s_red[ITER_THREADS / 64];
+    __shared__ double s_sum[9];
+    __shared__ int s_last;
+    BasisWork* bw = a.bw;
+    NmfBasis B;
+    double W[6];
+    for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
+    nmf_basis(W, a.lambda, B);
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const double v0 = a.V[i], v1 = a.V[ns + i], v2 = a.V[2 * ns + i];
+        double h0, h1;
+        nmf_solve(B, v0, v1, v2, h0, h1);
+        acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
+        acc[3] += v0 * h0; acc[4] += v0 * h1;
+        acc[5] += v1 * h0; acc[6] += v1 * h1;
+        acc[7] += v2 * h0; acc[8] += v2 * h1;
+    }
+    for (int q = 0; q < 9; ++q) {
+        double t = block_sum(acc[q], s_red);
+        if (threadIdx.x == 0) a.partial[blockIdx.x * 9 + q] = t;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&bw->ticket, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x < 9) {
+        double t = 0.0;
+        const volatile double* pp = a.partial;
+        for (unsigned b = 0; b < gridDim.x; ++b) t += pp[b * 9 + threadIdx.x];
+        s_sum[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        w_step(W, s_sum);
+        for (int i = 0; i < 6; ++i) bw->W[i] = W[i];
+        bw->ticket = 0;
+        __threadfence();
+    }
+}
+
+// Unit columns, stain order, outputs; optionally the nearest-rank percentile of the fitted
+// densities of the samples (one workgroup).
+__global__ __launch_bounds__(1024) void k_nmf_finish(BasisWork* bw, const double* V, double lambda, double q,
+                                                     float* w_out, float* sample_p99, int32_t* flags_out) {
+    __shared__ uint32_t s_hist[256];
+    __shared__ int s_misc[2];
+    __shared__ double s_W[6];
+    if (threadIdx.x == 0) {
+        double W[6];
+        for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
+        finish_basis(W);
+        for (int i = 0; i < 6; ++i) { s_W[i] = W[i]; w_out[i] = (float)W[i]; }
+    }
+    __syncthreads();
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    if (flags_out && threadIdx.x < 2)
+        flags_out[threadIdx.x] = (n < ns ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0);
+    if (!sample_p99) return;
+    NmfBasis B;
+    nmf_basis(s_W, lambda, B);
+    for (int j = 0; j < 2; ++j) {
+        double P = 0.0;
+        if (n > 0) {
+            int64_t k = (int64_t)ceil(q * (double)n);
+            k = k < 1 ? 1 : (k > n ? n : k);
+            P = block_select(n, k, [&](int64_t i) {
+                double h0, h1;
+                nmf_solve(B, V[i], V[ns + i], V[2 * ns + i], h0, h1);
+                return j == 0 ? h0 : h1;
+            }, s_hist, s_misc);
+        }
+        if (threadIdx.x == 0) sample_p99[j] = (float)P;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ a batch of tiles
+
+struct TileArgs {
+    const spcn_tile* tiles;
+    int32_t n_tiles;
+    float i0[3];
+    int32_t white_sum;
+    double lambda;
+    double q;
+    int64_t n_s;
+    uint64_t seed;
+    int32_t n_iter;
+    const float* w_init;
+    float* w_out;
+    float* sample_p99;
+    int32_t* flags_out;
+};
+
+__global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
+    __shared__ int64_t s_idx[TILE_THREADS * TILE_SPT];
+    __shared__ double s_od[3 * kHistBins];
+    __shared__ int s_wave[TILE_THREADS / 64];
+    __shared__ double s_red[TILE_THREADS / 64];
+    __shared__ double s_W[6];
+    __shared__ uint32_t s_hist[256];
+    __shared__ int s_misc[2];
+    __shared__ int s_count;
+    const int tile = blockIdx.x;
+    const spcn_tile T = a.tiles[tile];
+    const int64_t n_px = T.height * T.width;
+    const uint64_t seed = a.seed + (uint64_t)tile;
+    const int64_t n_s = a.n_s, max_cand = 64 * a.n_s;
+
+    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
+        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)a.i0[c], k);
+    if (threadIdx.x == 0) { s_count = 0; initial_basis(a.w_init, s_W); }
+    __syncthreads();
+
+    // sampling, in draw order, one candidate per thread per step
+    for (int64_t t0 = 0; t0 < max_cand; t0 += blockDim.x) {
+        const int base = s_count;
+        if (base >= n_s) break;
+        const int64_t t = t0 + threadIdx.x;
+        bool keep = false;
+        int64_t pix = 0;
+        if (t < max_cand) {
+            pix = candidate_pixel(seed, (uint64_t)t, n_px);
+            keep = non_white(T.src, pix, a.white_sum);
+        }
+        int total;
+        const int r = block_rank(keep, s_wave, &total);
+        if (keep && base + r < n_s) s_idx[base + r] = pix;
+        if (threadIdx.x == 0) s_count = (int)min((int64_t)base + total, n_s);
+        __syncthreads();
+    }
+    const int n = s_count;
+
+    // samples in registers: sample s lives in thread s % 1024, slot s / 1024
+    double v[TILE_SPT][3];
+    bool live[TILE_SPT];
+#pragma unroll
+    for (int k = 0; k < TILE_SPT; ++k) {
+        const int s = k * TILE_THREADS + threadIdx.x;
+        live[k] = s < n;
+        const uint8_t* p = T.src + 3 * (live[k] ? s_idx[s] : 0);
+        for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? s_od[c * kHistBins + p[c]] : 0.0;
+    }
+
+    double W[6];
+    for (int i = 0; i < 6; ++i) W[i] = s_W[i];
+    for (int it = 0; it < a.n_iter; ++it) {
+        NmfBasis B;
+        nmf_basis(W, a.lambda, B);
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < TILE_SPT; ++k) {
+            if (!live[k]) continue;
+            double h0, h1;
+            nmf_solve(B, v[k][0], v[k][1], v[k][2], h0, h1);
+            acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
+            acc[3] += v[k][0] * h0; acc[4] += v[k][0] * h1;
+            acc[5] += v[k][1] * h0; acc[6] += v[k][1] * h1;
+            acc[7] += v[k][2] * h0; acc[8] += v[k][2] * h1;
+        }
+        double sums[9];
+        for (int q = 0; q < 9; ++q) sums[q] = block_sum(acc[q], s_red);
+        w_step(W, sums);           // every thread performs the same update on the same sums
+    }
+    finish_basis(W);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 6; ++i) a.w_out[6 * tile + i] = (float)W[i];
+        if (a.flags_out)
+            for (int j = 0; j < 2; ++j)
+                a.flags_out[2 * tile + j] = (n < n_s ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0);
+    }
+    if (!a.sample_p99) return;
+    NmfBasis B;
+    nmf_basis(W, a.lambda, B);
+    double hv[TILE_SPT][2];
+#pragma unroll
+    for (int k = 0; k < TILE_SPT; ++k) nmf_solve(B, v[k][0], v[k][1], v[k][2], hv[k][0], hv[k][1]);
+    for (int j = 0; j < 2; ++j) {
+        double P = 0.0;
+        if (n > 0) {
+            int64_t kth = (int64_t)ceil(a.q * (double)n);
+            kth = kth < 1 ? 1 : (kth > n ? n : kth);
+            // radix select over the register-resident values: thread-owned slots are visited by
+            // index i = slot * 1024 + thread, so val() is only called with this thread's indices
+            uint64_t prefix = 0, pmask = 0;
+            int64_t kk = kth;
+            for (int shift = 56; shift >= 0; shift -= 8) {
+                for (int b = threadIdx.x; b < 256; b += blockDim.x) s_hist[b] = 0;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < TILE_SPT; ++k) {
+                    if (!live[k]) continue;
+                    uint64_t u = (uint64_t)__double_as_longlong(hv[k][j]);
+                    if ((u & pmask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255], 1u);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int64_t acc = 0;
+                    int d = 0;
+                    for (; d < 256; ++d) {
+                        if (acc + (int64_t)s_hist[d] >= kk) break;
+                        acc += s_hist[d];
+                    }
+                    s_misc[0] = d;
+                    s_misc[1] = (int)(kk - acc);
+                }
+                __syncthreads();
+                prefix |= (uint64_t)s_misc[0] << shift;
+                pmask |= (uint64_t)255 << shift;
+                kk = s_misc[1];
+                __syncthreads();
+            }
+            P = __longlong_as_double((long long)prefix);
+        }
+        if (threadIdx.x == 0) a.sample_p99[2 * tile + j] = (float)P;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int64_t hmin(int64_t a, int64_t b) { return a < b ? a : b; }
+
+static int64_t round_candidates(int64_t n_s, int r) {
+    const int64_t mult[MAX_ROUNDS] = {4, 12, 48};
+    return mult[r] * n_s;
+}
+
+static int64_t max_round_blocks(int64_t n_s) {
+    return (round_candidates(n_s, MAX_ROUNDS - 1) + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK;
+}
+
+size_t basis_workspace_bytes(int64_t n_s) {
+    if (n_s <= 0) return 0;
+    const int64_t nb = max_round_blocks(n_s);
+    size_t b = align256(sizeof(BasisWork));
+    b += align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t));   // staging
+    b += align256((size_t)nb * sizeof(int32_t));                  // counts
+    b += align256((size_t)n_s * sizeof(int64_t));                 // idx
+    b += align256((size_t)3 * n_s * sizeof(double));              // V
+    b += align256((size_t)ITER_MAX_BLOCKS * 9 * sizeof(double));  // partial sums
+    return b;
+}
+
+hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK& pk, float lambda_nmf,
+                                 int64_t n_s, uint64_t seed, int32_t n_iter, const float* w_init,
+                                 float* w_out, float* sample_p99, int32_t* flags_out, void* ws,
+                                 const DevInfo& dev, hipStream_t s) {
+    uint8_t* p = static_cast<uint8_t*>(ws);
+    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
+    const int64_t nbmax = max_round_blocks(n_s);
+    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)nbmax * sizeof(int32_t));
+    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
+    double* V = reinterpret_cast<double*>(p); p += align256((size_t)3 * n_s * sizeof(double));
+    double* partial = reinterpret_cast<double*>(p);
+
+    const int64_t max_cand = 64 * n_s;
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, w_init);
+    int64_t t0 = 0;
+    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
+        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
+        SampleArgs a{img, n_px, pk.white_sum, seed, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
+                     counts, idx};
+        hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_sample_merge, dim3(1), dim3(1024), 0, s, a);
+        t0 += rc;
+    }
+    hipLaunchKernelGGL(k_od_gather, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s, img, idx,
+                       bw, pk.i0[0], pk.i0[1], pk.i0[2], V);
+    int nblk = (int)hmin(hmin((n_s + 1023) / 1024, ITER_MAX_BLOCKS), dev.cus);
+    if (nblk < 1) nblk = 1;
+    IterArgs ia{bw, V, partial, (double)lambda_nmf};
+    for (int it = 0; it < n_iter; ++it)
+        hipLaunchKernelGGL(k_nmf_round, dim3(nblk), dim3(ITER_THREADS), 0, s, ia);
+    hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(1024), 0, s, bw, (const double*)V, (double)lambda_nmf, pk.q64,
+                       w_out, sample_p99, flags_out);
+    return hipGetLastError();
+}
+
+size_t basis_batched_workspace_bytes(int64_t, int64_t) { return 0; }
+
+hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, const ParamsK& pk,
+                                         float lambda_nmf, int64_t n_s, uint64_t seed, int32_t n_iter,
+                                         const float* w_init, float* w_out, float* sample_p99,
+                                         int32_t* flags_out, void*, const DevInfo&, hipStream_t s) {
+    TileArgs a{};
+    a.tiles = tiles; a.n_tiles = n_tiles;
+    for (int c = 0; c < 3; ++c) a.i0[c] = pk.i0[c];
+    a.white_sum = pk.white_sum; a.lambda = (double)lambda_nmf; a.q = pk.q64; a.n_s = n_s; a.seed = seed;
+    a.n_iter = n_iter; a.w_init = w_init; a.w_out = w_out; a.sample_p99 = sample_p99; a.flags_out = flags_out;
+    hipLaunchKernelGGL(k_nmf_tiles, dim3(n_tiles), dim3(TILE_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+int64_t basis_tile_max_samples() { return (int64_t)TILE_THREADS * TILE_SPT; }
+
+}  // namespace spcn

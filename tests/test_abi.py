@@ -1,0 +1,106 @@
+"""CPU tests of the C-ABI boundary: the library loads, exports every function include/spcn.h declares,
+and rejects invalid arguments on the host before anything reaches a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "spcn.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spcn_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1901_03088_amd as s
+    return s
+
+
+def test_header_functions_all_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib._L, n), n
+    assert set(names) == set(lib.EXPORTED)
+
+
+def test_defaults_follow_the_paper(lib):
+    p = lib.params()
+    assert list(p.i0) == [255.0, 255.0, 255.0]        # 8-bit maximum intensity (Eq. 1)
+    assert p.white_sum == 660                          # mean intensity 220 (Sec. 3.1 item 2)
+    assert p.percentile == 99.0                        # Eq. 3
+    q = lib.spcn_params()
+    lib._L.spcn_default_params(C.byref(q))
+    assert list(q.hist_hi) == [4.0, 4.0]
+
+
+def test_status_strings(lib):
+    for s in range(5):
+        assert lib._L.spcn_status_string(s)
+    assert lib.version().startswith("spcn")
+
+
+def call_normalize(lib, **kw):
+    p = kw.pop("p", lib.params())
+    args = dict(src=C.c_void_p(1 << 20), h=8, w=8, ws=C.c_void_p(1 << 24), wt=C.c_void_p(1 << 24),
+                sc=C.c_void_p(1 << 24), out=C.c_void_p(2 << 20), wsp=C.c_void_p(3 << 20), wsn=1 << 20)
+    args.update(kw)
+    return lib._L.spcn_normalize(args["src"], args["h"], args["w"], args["ws"], args["wt"], args["sc"], None,
+                                 C.byref(p), args["out"], None, args["wsp"], args["wsn"], None)
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(src=None), "src is NULL"),
+    (dict(out=None), "out is NULL"),
+    (dict(h=0), "height and width"),
+    (dict(w=-3), "height and width"),
+    (dict(src=C.c_void_p((1 << 20) + 1)), "aligned"),
+    (dict(ws=None), "non-NULL"),
+    (dict(out=C.c_void_p((1 << 20) + 96)), "overlap"),
+    (dict(wsp=None), "workspace"),
+    (dict(wsn=16), "workspace"),
+    (dict(h=1 << 20, w=1 << 20), "2^36"),
+])
+def test_normalize_rejects(lib, kw, frag):
+    st = call_normalize(lib, **kw)
+    assert st in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
+    assert frag in lib._L.spcn_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,frag", [
+    ("lambda_", -0.1, "lambda"),
+    ("lambda_", float("nan"), "lambda"),
+    ("percentile", 0.0, "percentile"),
+    ("percentile", 100.5, "percentile"),
+    ("hist_hi", (3.0, 4.0), "power of two"),
+    ("hist_hi", (4.0, 1024.0), "power of two"),
+    ("i0", (255.0, 0.0, 255.0), "i0"),
+])
+def test_params_rejected(lib, field, value, frag):
+    p = lib.params()
+    if isinstance(value, tuple):
+        getattr(p, field)[:] = list(value)
+    else:
+        setattr(p, field, value)
+    st = call_normalize(lib, p=p)
+    assert st == lib.SPCN_E_ARG
+    assert frag in lib._L.spcn_last_error().decode()
+
+
+def test_densities_requires_histogram(lib):
+    p = lib.params()
+    st = lib._L.spcn_densities(C.c_void_p(1 << 20), 4, 4, C.c_void_p(1 << 24), C.byref(p), None, None, None, None,
+                               None, 0, None)
+    assert st == lib.SPCN_E_ARG
+    assert "hist_out" in lib._L.spcn_last_error().decode()
+
+
+def test_workspace_sizes(lib):
+    assert lib.workspace_size(lib.OP_NORMALIZE, 1000) >= 2 * 256 * 8
+    assert lib.workspace_size(99, 10) == 0
+    assert lib.workspace_size(lib.OP_NORMALIZE, -1) == 0

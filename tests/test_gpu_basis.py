@@ -1,0 +1,98 @@
+"""GPU parity of basis estimation (sampling, sparse NMF of Eq. 2, stain order) with the FP64 oracle:
+identical sample indices (both sides implement SplitMix64 from its published definition), fitted
+columns within 1e-6 rad, sample percentiles within 1e-9 relative."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def S():
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_1901_03088_amd as s
+    return s
+
+
+def col_angles(a, b):
+    a = np.asarray(a, np.float64).reshape(2, 3); b = np.asarray(b, np.float64).reshape(2, 3)
+    out = []
+    for j in range(2):
+        c = a[j] @ b[j] / (np.linalg.norm(a[j]) * np.linalg.norm(b[j]))
+        out.append(math.acos(min(1.0, c)))
+    return np.array(out)
+
+
+def oracle_fit(orc, img, n_s, seed, lam, T, p, W_init=None):
+    idx = orc.sample_tissue(img, n_s, seed, p.white_sum)
+    V = orc.od_samples(img, idx, list(p.i0))
+    if W_init is None:
+        H0 = np.array([0.65, 0.70, 0.29]); E0 = np.array([0.07, 0.99, 0.11])
+        W_init = orc.f32(np.stack([H0 / np.linalg.norm(H0), E0 / np.linalg.norm(E0)], axis=1))
+    W, sp, _ = orc.nmf(V, lam, T, W_init, p.percentile)
+    return W, sp, idx
+
+
+@pytest.mark.parametrize("n_s,T,lam", [(20000, 50, 0.1), (2000, 10, 0.01), (1, 5, 0.1), (77, 0, 0.1)])
+def test_estimate_basis_config0(S, orc, n_s, T, lam):
+    d = synth.make_image(0, 1024, 1024, device=DEV)
+    p = S.params()
+    w, sp, flags = S.spcn_estimate_basis(d["img"], n_s, seed=1234, p=p, lambda_nmf=lam, n_iter=T)
+    torch.cuda.synchronize()
+    img = d["img"].cpu().numpy()
+    Wo, spo, idx = oracle_fit(orc, img, n_s, 1234, orc.f32(lam), T, p)
+    ang = col_angles(w.cpu().numpy(), Wo)
+    print(f"[basis n_s={n_s} T={T}] angle rad {ang}, p99 gpu {sp.cpu().numpy()} oracle {spo}", flush=True)
+    assert ang.max() < 1e-6
+    assert np.allclose(sp.cpu().numpy(), spo, rtol=1e-6, atol=1e-9)
+    assert (flags.cpu().numpy() == 0).all()
+    if T == 50:
+        for j in range(2):       # and the fit recovers the generator's stains (sample, noise and lasso bias)
+            assert math.degrees(col_angles(w.cpu().numpy(), orc.basis(d["W"]))[j]) < 4.0
+
+
+def test_estimate_basis_short_and_white(S, orc):
+    img = torch.full((64, 64, 3), 250, dtype=torch.uint8, device=DEV)
+    img[:2, :2] = 60      # 4 tissue pixels only
+    w, sp, flags = S.spcn_estimate_basis(img, 100, seed=7)
+    torch.cuda.synchronize()
+    assert (flags.cpu().numpy() & S.FLAG_SHORT).all()
+    white = torch.full((32, 32, 3), 255, dtype=torch.uint8, device=DEV)
+    w, sp, flags = S.spcn_estimate_basis(white, 100, seed=7)
+    torch.cuda.synchronize()
+    f = flags.cpu().numpy()
+    assert (f & S.FLAG_NO_TISSUE).all() and (f & S.FLAG_SHORT).all()
+
+
+def test_estimate_basis_large_sample(S, orc):
+    """200k samples (the gigapixel configuration's sample size) on an 8-Mpixel tissue block."""
+    d = synth.make_image(21, 2048, 4096, device=DEV)
+    p = S.params()
+    w, sp, flags = S.spcn_estimate_basis(d["img"], 200000, seed=99, p=p, lambda_nmf=0.1, n_iter=50)
+    torch.cuda.synchronize()
+    Wo, spo, idx = oracle_fit(orc, d["img"].cpu().numpy(), 200000, 99, orc.f32(0.1), 50, p)
+    ang = col_angles(w.cpu().numpy(), Wo)
+    print(f"[basis 200k] angle rad {ang}", flush=True)
+    assert ang.max() < 1e-6
+    assert np.allclose(sp.cpu().numpy(), spo, rtol=1e-6)
+
+
+def test_estimate_basis_batched_tiles(S, orc):
+    shapes = [(256, 320), (512, 256), (64, 64), (300, 200)]
+    tiles = [synth.make_tile(t, h, w, device=DEV) for t, (h, w) in enumerate(shapes)]
+    table = S.tile_table([t["img"] for t in tiles])
+    p = S.params()
+    w, sp, flags = S.spcn_estimate_basis_batched(table, len(tiles), 4096, seed=500, p=p, lambda_nmf=0.1, n_iter=50)
+    torch.cuda.synchronize()
+    w = w.cpu().numpy(); sp = sp.cpu().numpy()
+    for t, d in enumerate(tiles):
+        Wo, spo, idx = oracle_fit(orc, d["img"].cpu().numpy(), 4096, 500 + t, orc.f32(0.1), 50, p)
+        ang = col_angles(w[t], Wo)
+        assert ang.max() < 1e-6, (t, ang)
+        assert np.allclose(sp[t], spo, rtol=1e-6)
