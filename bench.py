@@ -2,9 +2,11 @@
 """Benchmark of the SPCN hot path on one MI355X: a 50000 x 40000 (2 Gpixel) synthetic slide,
 ~60% background, normalised to one target.
 
-One step = the whole path for the slide: basis estimation from 200k sampled tissue pixels
-(when available in the library) + pass 1 (densities + exact histogram) + pass 2 (percentile,
-recolour, uint8 write).  Inputs are resident in HBM before the timed region.  Prints ONE JSON line.
+One step = the whole path for the slide: basis estimation from 200k sampled tissue pixels (sparse
+NMF, 50 rounds) + pass 1 (densities + exact histogram) + pass 2 (percentile, recolour, uint8 write).
+Inputs are resident in HBM before the timed region.  Extras (same JSON line): the batched workload
+(512 tiles in one graph) against a per-tile loop, and forward+backward of the float path against
+forward only.  Prints ONE JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload slide|cfg1|small]
 """
@@ -71,6 +73,98 @@ def cpu_baseline(img_dev, W_src, W_tgt, scale_tgt, min_seconds: float = 10.0, ba
                       f"full normalisation per band, {t_total:.1f} s"}
 
 
+def timed(fn, steps, warmup, stream):
+    """Mean ms of fn() over `steps` runs bracketed by events on `stream` (after `warmup` runs)."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+
+
+def bench_batched(dev, S, synth, steps, warmup, n_tiles=512):
+    """512 uneven tiles (sides 256..2048 step 64), per-tile basis fit (4096 samples, 50 rounds,
+    lambda 0.1) and normalisation to one target, captured in one hipGraph and replayed; against a
+    per-tile loop of the plain single-image path (same work, same results)."""
+    import torch
+    shapes = synth.tile_shapes(n_tiles)
+    srcs = [synth.make_tile(t, h, w, device=dev)["img"] for t, (h, w) in enumerate(shapes)]
+    outs = [torch.empty_like(x) for x in srcs]
+    total = sum(h * w for h, w in shapes)
+    table = S.tile_table(srcs, outs)
+    p = S.params()
+    tgt = synth.target_image(device=dev)
+    wt = S.as_basis(tgt["W"], dev)
+    _, _, sc, _ = S.spcn_densities(tgt["img"], wt, p, want_h=False)
+    ws_b = S.workspace(S.workspace_size(S.OP_ESTIMATE_BATCHED, 0, n_tiles, 4096), dev)
+    ws_n = S.workspace(S.workspace_size(S.OP_NORMALIZE_BATCHED, total, n_tiles), dev)
+
+    def run():
+        W, _, _ = S.spcn_estimate_basis_batched(table, n_tiles, 4096, seed=30000, p=p, want_p99=False, ws=ws_b)
+        S.spcn_normalize_batched(table, n_tiles, total, W, wt, sc, p, ws=ws_n, stats=False)
+    run()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    stream = torch.cuda.current_stream()
+    ms_graph = timed(g.replay, steps, warmup, stream)
+    ws1 = S.workspace(S.workspace_size(S.OP_ESTIMATE_BASIS, 0, 1, 4096), dev)
+    wsn1 = S.workspace(S.workspace_size(S.OP_NORMALIZE, 0, 1, 0), dev)
+    w1 = torch.empty((n_tiles, 6), dtype=torch.float32, device=dev)
+
+    def loop():
+        for t in range(n_tiles):
+            S.spcn_estimate_basis(srcs[t], 4096, seed=30000 + t, p=p, lambda_nmf=0.1, n_iter=50, want_p99=False,
+                                  w_out=w1[t], ws=ws1)
+            S.spcn_normalize(srcs[t], w1[t], wt, sc, p, out=outs[t], stats=False, ws=wsn1)
+    ms_loop = timed(loop, max(1, steps // 4), 1, stream)
+    return {"tiles": n_tiles, "pixels": total, "graph_ms": round(ms_graph, 3),
+            "graph_Mpx_s": round(total / ms_graph / 1e3, 1), "per_tile_loop_ms": round(ms_loop, 3),
+            "per_tile_loop_Mpx_s": round(total / ms_loop / 1e3, 1), "speedup": round(ms_loop / ms_graph, 2)}
+
+
+def bench_fwdbwd(dev, S, synth, steps, warmup, n=64, size=512):
+    """Differentiable path: 64 x 3 x 512 x 512 float images, per-sample target bases, forward +
+    backward of L = sum(w * y), against forward only."""
+    import torch
+    x, Ws, Wt, wts = synth.float_batch(n, size, device=dev)
+    p = S.float_params()
+    ws = torch.stack([S.as_basis(W, dev) for W in Ws]).contiguous()
+    wt = torch.stack([S.as_basis(W, dev) for W in Wt]).contiguous()
+    sc = torch.tensor([0.9, 1.1], dtype=torch.float32, device=dev)
+    fws = S.workspace(S.workspace_size(S.OP_FORWARD_F32, size * size, n), dev)
+    bws = S.workspace(S.workspace_size(S.OP_BACKWARD_F32, size * size, n), dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    state = {}
+
+    def fwd():
+        state["saved"] = S.spcn_normalize_f32(x, ws, wt, sc, p, y=y, ws=fws)[1]
+
+    def fwd_bwd():
+        fwd()
+        S.spcn_normalize_backward(x, ws, wt, sc, state["saved"], wts, p, ws=bws)
+    ms_f = timed(fwd, steps, warmup, stream)
+    ms_fb = timed(fwd_bwd, steps, warmup, stream)
+    px = n * size * size
+    return {"batch": [n, 3, size, size], "forward_ms": round(ms_f, 3), "forward_Mpx_s": round(px / ms_f / 1e3, 1),
+            "fwd_bwd_ms": round(ms_fb, 3), "fwd_bwd_Mpx_s": round(px / ms_fb / 1e3, 1),
+            "forward_bytes_per_px": 48, "backward_bytes_per_px": 36}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +173,8 @@ def main() -> int:
     ap.add_argument("--workload", default="slide", choices=["slide", "cfg1", "small"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="skip the batched and forward+backward measurements")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -104,43 +200,53 @@ def main() -> int:
     _, _, scale_tgt, _ = S.spcn_densities(tgt["img"], w_tgt, p, want_h=False)
     out = torch.empty_like(img)
     hist = torch.empty((2, 256), dtype=torch.uint64, device=dev)
+    w_fit = torch.empty(6, dtype=torch.float32, device=dev)
+    n_samples = 200000
+    ws_fit = S.workspace(S.workspace_size(S.OP_ESTIMATE_BASIS, n_px, 1, n_samples), dev)
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
+        # one step = the whole path for the slide: basis fit (200k samples) -> pass 1 -> pass 2
         if ev is not None:
             ev[0].record(stream)
-        S.spcn_densities(img, w_src, p, want_h=False, hist_out=hist, finalize=False)
+        S.spcn_estimate_basis(img, n_samples, seed=2024, p=S.params(), lambda_nmf=0.1, n_iter=50, want_p99=False,
+                              w_out=w_fit, ws=ws_fit)
         if ev is not None:
             ev[1].record(stream)
-        S.spcn_recolor(img, w_src, w_tgt, scale_tgt, hist, p, out=out, stats=False)
+        S.spcn_densities(img, w_fit, p, want_h=False, hist_out=hist, finalize=False)
         if ev is not None:
             ev[2].record(stream)
+        S.spcn_recolor(img, w_fit, w_tgt, scale_tgt, hist, p, out=out, stats=False)
+        if ev is not None:
+            ev[3].record(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    p1 = [e[0].elapsed_time(e[1]) for e in evs]
-    p2 = [e[1].elapsed_time(e[2]) for e in evs]
-    tot = [e[0].elapsed_time(e[2]) for e in evs]
+    pb = [e[0].elapsed_time(e[1]) for e in evs]
+    p1 = [e[1].elapsed_time(e[2]) for e in evs]
+    p2 = [e[2].elapsed_time(e[3]) for e in evs]
+    tot = [e[0].elapsed_time(e[3]) for e in evs]
     ms_step = float(np.mean(tot))
     value = n_px / (ms_step / 1e3) / 1e6
-    p1m, p2m = float(np.mean(p1)), float(np.mean(p2))
+    pbm, p1m, p2m = float(np.mean(pb)), float(np.mean(p1)), float(np.mean(p2))
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}), "
-        f"pass1 {p1m:.3f} ms, pass2 {p2m:.3f} ms")
+        f"basis {pbm:.3f} ms, pass1 {p1m:.3f} ms, pass2 {p2m:.3f} ms")
 
     # roofline of the dominant kernel (algorithmic bytes: 3 B/px read in pass 1; 3 read + 3 written in pass 2)
     k_name, k_ms, k_bytes = ("pass2_recolor", p2m, 6.0 * n_px) if p2m >= p1m else ("pass1_histogram", p1m, 3.0 * n_px)
     achieved = k_bytes / (k_ms / 1e3) / 1e9
-    path_gbs = 9.0 * n_px / (ms_step / 1e3) / 1e9
+    norm_ms = p1m + p2m
+    path_gbs = 9.0 * n_px / (norm_ms / 1e3) / 1e9
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -148,12 +254,29 @@ def main() -> int:
         "config": dict(desc, pixels=n_px, background_frac=0.6, lambda_density=0.01, io="uint8 RGB HWC"),
         "roofline": {"bound": "hbm", "kernel": k_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
-        "path": {"pass1_ms": round(p1m, 4), "pass2_ms": round(p2m, 4),
-                 "normalize_GBs_9B_per_px": round(path_gbs, 1), "normalize_frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "path": {"basis_fit_ms": round(pbm, 4), "pass1_ms": round(p1m, 4), "pass2_ms": round(p2m, 4),
+                 "normalize_ms": round(norm_ms, 4), "normalize_Mpx_s": round(n_px / norm_ms / 1e3, 1),
+                 "normalize_GBs_9B_per_px": round(path_gbs, 1),
+                 "normalize_frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
     }
     if not args.no_cpu_baseline:
-        sc = scale_tgt.cpu().numpy()
-        res["cpu_baseline"] = cpu_baseline(img, W_src, tgt["W"], sc, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(img, W_src, tgt["W"], scale_tgt.cpu().numpy(), args.cpu_seconds)
+    if args.extras and args.workload == "slide":
+        del img, out
+        torch.cuda.empty_cache()
+        extras = {}
+        try:
+            extras["batched"] = bench_batched(dev, S, synth, args.steps, args.warmup)
+            log(f"[bench] batched {extras['batched']}")
+        except Exception as e:   # report, never hide, a failing extra
+            extras["batched"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        try:
+            extras["fwd_bwd"] = bench_fwdbwd(dev, S, synth, args.steps, args.warmup)
+            log(f"[bench] fwd_bwd {extras['fwd_bwd']}")
+        except Exception as e:
+            extras["fwd_bwd"] = {"error": repr(e)}
+        res["extras"] = extras
     print(json.dumps(res), flush=True)
     return 0
 

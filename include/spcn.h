@@ -54,6 +54,8 @@ typedef enum {
 #define SPCN_FLAG_BIN0      4   /* percentile fell in bin 0 (stain absent): scale kept at 1       */
 #define SPCN_FLAG_BASIS     8   /* the basis has a singular Gram matrix: densities set to 0       */
 #define SPCN_FLAG_SHORT    16   /* basis estimation drew fewer tissue samples than requested      */
+#define SPCN_FLAG_BATCH    32   /* batched call: this tile was skipped (bad descriptor, total_px too
+                                   small for the tiles, or a bounded wait expired)                  */
 
 #define SPCN_HIST_BINS 256
 
@@ -164,7 +166,10 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
 /* Normalises every tile of a batch to one target (Eqs. 1-4, each tile with its own basis
  * w_src[t] and its own percentile) in ONE persistent kernel launch: a global work queue hands out
  * all pass-1 chunks before any pass-2 chunk; the last pass-1 chunk of a tile finalises that tile's
- * percentile and releases its pass-2 chunks.
+ * percentile and releases its pass-2 chunks.  (Two tiny set-up kernels precede it.)
+ *   tiles    device array of n_tiles descriptors (1 <= n_tiles <= 8192), 4-byte aligned pointers
+ *   total_px an upper bound of the tiles' total pixel count (sizes the workspace; if the tiles hold
+ *            more, nothing is processed and every tile's flags get SPCN_FLAG_BATCH)
  *   w_src [n_tiles][6]; w_tgt [6]; scale_tgt [2]; i0_out host [3] or NULL;
  *   p99_out, scale_out [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.
  * Results are identical to calling spcn_normalize on each tile. */
@@ -204,6 +209,23 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
                                     const float* grad_y, float* grad_x, float* grad_w_tgt,
                                     float* grad_scale, void* ws, size_t ws_bytes,
                                     hipStream_t stream);
+
+/* Tuning options (autotuner hooks).  They select among kernel variants that compute identical
+ * results; they are process-wide and read when work is enqueued.
+ *   SPCN_OPT_P1_VARIANT        pass-1 table copies / histogram columns / units per thread and
+ *                              iteration / workgroups per CU: 0 = (1, 64, 4, 1), 1 = (2, 64, 4, 1),
+ *                              2 = (4, 32, 4, 1), 3 = (8, 16, 4, 1), 4 = (1, 32, 2, 2),
+ *                              5 = (2, 16, 2, 2)
+ *   SPCN_OPT_P2_VARIANT        pass-2 table copies: 0 = 1, 1 = 4 (256-thread groups), 2 = 16
+ *                              (1024-thread groups)
+ *   SPCN_OPT_P2_BLOCKS_PER_CU  pass-2 workgroups per compute unit, 1..16
+ * spcn_set_option returns SPCN_E_ARG for an unknown option or a value out of range. */
+#define SPCN_OPT_P1_VARIANT       0
+#define SPCN_OPT_P2_VARIANT       1
+#define SPCN_OPT_P2_BLOCKS_PER_CU 2
+spcn_status spcn_set_option(int option, int value);
+/* Current value of an option, or -1 for an unknown option. */
+int spcn_get_option(int option);
 
 /* Static description of a status code. */
 const char* spcn_status_string(spcn_status s);

@@ -24,10 +24,11 @@ _L = C.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ ABI mirror
 
 SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
-FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT = 1, 2, 4, 8, 16
+FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH = 1, 2, 4, 8, 16, 32
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
     OP_FORWARD_F32, OP_BACKWARD_F32 = range(7)
 HIST_BINS = 256
+OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU = range(3)
 
 
 class spcn_params(C.Structure):
@@ -63,6 +64,8 @@ _SIGS = {
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_backward": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp,
                                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_set_option": (C.c_int, [C.c_int, C.c_int]),
+    "spcn_get_option": (C.c_int, [C.c_int]),
     "spcn_status_string": (C.c_char_p, [C.c_int]),
     "spcn_last_error": (C.c_char_p, []),
     "spcn_version": (C.c_char_p, []),
@@ -273,6 +276,128 @@ def spcn_estimate_basis_batched(tiles: torch.Tensor, n_tiles: int, n_samples: in
                                           _ptr(w_out), _ptr(sp), _ptr(flags), wsp, wsn, _stream()),
            "spcn_estimate_basis_batched")
     return w_out, sp, flags
+
+
+def spcn_normalize_batched(tiles: torch.Tensor, n_tiles: int, total_px: int, w_src: torch.Tensor,
+                           w_tgt: torch.Tensor, scale_tgt: torch.Tensor, p: spcn_params | None = None,
+                           i0_out=None, ws=None, stats: bool = True):
+    """Normalises every tile of a device tile table (tile_table(srcs, outs)) in one persistent launch.
+    w_src [n_tiles, 6].  Returns dict(p99 [n, 2], scale [n, 2], flags [n, 2]) (empty if stats=False)."""
+    _dev(w_src, torch.float32, "w_src")
+    p = p or params()
+    dev = tiles.device
+    res = {}
+    if stats:
+        res = {"p99": torch.empty((n_tiles, 2), dtype=torch.float32, device=dev),
+               "scale": torch.empty((n_tiles, 2), dtype=torch.float32, device=dev),
+               "flags": torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)}
+    if ws is None:
+        ws = workspace(workspace_size(OP_NORMALIZE_BATCHED, total_px, n_tiles), dev)
+    wsp, wsn = _ws_ptr(ws)
+    io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
+    _check(_L.spcn_normalize_batched(_ptr(tiles), int(n_tiles), int(total_px), _ptr(w_src), _ptr(w_tgt),
+                                     _ptr(scale_tgt), io, C.byref(p), _ptr(res.get("p99")), _ptr(res.get("scale")),
+                                     _ptr(res.get("flags")), wsp, wsn, _stream()), "spcn_normalize_batched")
+    return res
+
+
+def float_params(lam=0.01, white_sum=660, percentile=99.0) -> spcn_params:
+    """Parameters of the float path: input in [0, 1], so i0 = 1."""
+    return params(i0=(1.0, 1.0, 1.0), lam=lam, white_sum=white_sum, percentile=percentile)
+
+
+def _per_sample(t, width, name):
+    _dev(t, torch.float32, name)
+    if t.dim() == 1:
+        if t.numel() != width:
+            raise ValueError(f"{name} must have {width} values or shape (n, {width})")
+        return 0
+    if t.dim() != 2 or t.shape[1] != width:
+        raise ValueError(f"{name} must have shape (n, {width})")
+    return width
+
+
+def spcn_normalize_f32(x: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
+                       p: spcn_params | None = None, i0_out=None, y=None, ws=None):
+    """x (n, 3, H, W) float32 in [0, 1] on the GPU; w_src / w_tgt (n, 6) or (6,); scale_tgt (n, 2) or (2,).
+    Returns (y, saved) with saved = dict(p99, scale, sel, flags), each (n, 2)."""
+    _dev(x, torch.float32, "x")
+    if x.dim() != 4 or x.shape[1] != 3:
+        raise ValueError("x must have shape (n, 3, H, W)")
+    n, _, H, W_ = (int(v) for v in x.shape)
+    sw, st_, ss = _per_sample(w_src, 6, "w_src"), _per_sample(w_tgt, 6, "w_tgt"), _per_sample(scale_tgt, 2, "scale_tgt")
+    p = p or float_params()
+    dev = x.device
+    y = y if y is not None else torch.empty_like(x)
+    saved = {"p99": torch.empty((n, 2), dtype=torch.float32, device=dev),
+             "scale": torch.empty((n, 2), dtype=torch.float32, device=dev),
+             "sel": torch.empty((n, 2), dtype=torch.int64, device=dev),
+             "flags": torch.empty((n, 2), dtype=torch.int32, device=dev)}
+    if ws is None:
+        ws = workspace(workspace_size(OP_FORWARD_F32, H * W_, n), dev)
+    wsp, wsn = _ws_ptr(ws)
+    io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
+    _check(_L.spcn_normalize_f32(_ptr(x), n, H, W_, _ptr(w_src), sw, _ptr(w_tgt), st_, _ptr(scale_tgt), ss, io,
+                                 C.byref(p), _ptr(y), _ptr(saved["p99"]), _ptr(saved["scale"]), _ptr(saved["sel"]),
+                                 _ptr(saved["flags"]), wsp, wsn, _stream()), "spcn_normalize_f32")
+    return y, saved
+
+
+def spcn_normalize_backward(x: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
+                            saved: dict, grad_y: torch.Tensor, p: spcn_params | None = None, i0_out=None, ws=None):
+    """Adjoint of spcn_normalize_f32.  Returns (grad_x, grad_w_tgt (n, 6), grad_scale (n, 2)) per sample."""
+    _dev(x, torch.float32, "x")
+    _dev(grad_y, torch.float32, "grad_y")
+    n, _, H, W_ = (int(v) for v in x.shape)
+    sw, st_, ss = _per_sample(w_src, 6, "w_src"), _per_sample(w_tgt, 6, "w_tgt"), _per_sample(scale_tgt, 2, "scale_tgt")
+    p = p or float_params()
+    dev = x.device
+    gx = torch.empty_like(x)
+    gw = torch.empty((n, 6), dtype=torch.float32, device=dev)
+    gs = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(workspace_size(OP_BACKWARD_F32, H * W_, n), dev)
+    wsp, wsn = _ws_ptr(ws)
+    io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
+    _check(_L.spcn_normalize_backward(_ptr(x), n, H, W_, _ptr(w_src), sw, _ptr(w_tgt), st_, _ptr(scale_tgt), ss, io,
+                                      C.byref(p), _ptr(saved["p99"]), _ptr(saved["sel"]), _ptr(saved["flags"]),
+                                      _ptr(grad_y), _ptr(gx), _ptr(gw), _ptr(gs), wsp, wsn, _stream()),
+           "spcn_normalize_backward")
+    return gx, gw, gs
+
+
+class SPCNNormalize(torch.autograd.Function):
+    """y = SPCN(x; W_src, W_tgt, scale_tgt) on float images, differentiable in x, W_tgt and scale_tgt
+    (W_src is treated as a constant).  Shapes as in spcn_normalize_f32; a (6,) W_tgt or (2,) scale
+    shared by the batch receives the sum of the per-sample gradients."""
+
+    @staticmethod
+    def forward(ctx, x, w_src, w_tgt, scale_tgt, p=None, i0_out=None):
+        x = x.contiguous()
+        w_src, w_tgt, scale_tgt = w_src.contiguous(), w_tgt.contiguous(), scale_tgt.contiguous()
+        y, saved = spcn_normalize_f32(x, w_src, w_tgt, scale_tgt, p, i0_out)
+        ctx.save_for_backward(x, w_src, w_tgt, scale_tgt, saved["p99"], saved["sel"], saved["flags"])
+        ctx.p, ctx.i0_out = p, i0_out
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w_src, w_tgt, scale_tgt, p99, sel, flags = ctx.saved_tensors
+        gx, gw, gs = spcn_normalize_backward(x, w_src, w_tgt, scale_tgt, {"p99": p99, "sel": sel, "flags": flags},
+                                             gy.contiguous(), ctx.p, ctx.i0_out)
+        if w_tgt.dim() == 1:
+            gw = gw.sum(0)
+        if scale_tgt.dim() == 1:
+            gs = gs.sum(0)
+        return gx, None, gw, gs, None, None
+
+
+def set_option(opt: int, value: int) -> None:
+    _check(_L.spcn_set_option(int(opt), int(value)), "spcn_set_option")
+
+
+def get_option(opt: int) -> int:
+    return int(_L.spcn_get_option(int(opt)))
 
 
 def version() -> str:

@@ -2,6 +2,7 @@
 // workspace layout, error reporting and dispatch to the kernel launchers.
 #include "spcn_internal.h"
 
+#include <atomic>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -10,6 +11,13 @@
 namespace spcn {
 
 static thread_local char g_err[512];
+
+// option id -> (value, min, max)
+static std::atomic<int> g_opt[3] = {{0}, {0}, {8}};
+static const int g_opt_lo[3] = {0, 0, 1};
+static const int g_opt_hi[3] = {5, 2, 16};
+
+int option(int id) { return (id >= 0 && id < 3) ? g_opt[id].load(std::memory_order_relaxed) : 0; }
 
 spcn_status fail(spcn_status s, const char* fmt, ...) {
     va_list ap;
@@ -260,6 +268,101 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
     if (e != hipSuccess) return hip_fail(e, "spcn_estimate_basis_batched launch");
     return SPCN_OK;
 }
+
+spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px, const float* w_src,
+                                   const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                                   const spcn_params* p, float* p99_out, float* scale_out, int32_t* flags_out,
+                                   void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!tiles) return fail(SPCN_E_ARG, "tiles is NULL");
+    if (n_tiles < 1 || n_tiles > batched_max_tiles())
+        return fail(SPCN_E_ARG, "n_tiles = %d must lie in [1, %lld]", (int)n_tiles, (long long)batched_max_tiles());
+    if (total_px < 1 || total_px > ((int64_t)1 << 40)) return fail(SPCN_E_ARG, "total_px = %lld out of range", (long long)total_px);
+    SPCN_CHECK(check_params(p, true));
+    if (!w_src || !w_tgt || !scale_tgt) return fail(SPCN_E_ARG, "w_src, w_tgt and scale_tgt must be non-NULL");
+    float io[3];
+    for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
+    SPCN_CHECK(check_ws(ws, ws_bytes, batched_workspace_bytes(n_tiles, total_px)));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_normalize_batched(tiles, n_tiles, total_px, w_src, w_tgt, scale_tgt, io, make_params(p),
+                                            p99_out, scale_out, flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_normalize_batched launch");
+    return SPCN_OK;
+}
+
+static spcn_status check_f32(const float* x, int64_t n, int64_t height, int64_t width, const float* w_src,
+                             int64_t w_src_stride, const float* w_tgt, int64_t w_tgt_stride, const float* scale_tgt,
+                             int64_t scale_stride, const spcn_params* p) {
+    if (!x) return fail(SPCN_E_ARG, "x is NULL");
+    if (n < 1 || height < 1 || width < 1) return fail(SPCN_E_ARG, "n, height and width must be >= 1");
+    if (height > (((int64_t)1 << 31) - 1) / width) return fail(SPCN_E_ARG, "more than 2^31 - 1 pixels per sample");
+    if (n > 65535) return fail(SPCN_E_ARG, "n = %lld exceeds 65535 samples", (long long)n);
+    if (((uintptr_t)x) & 3) return fail(SPCN_E_ARG, "x must be 4-byte aligned");
+    if (!w_src || !w_tgt || !scale_tgt) return fail(SPCN_E_ARG, "w_src, w_tgt and scale_tgt must be non-NULL");
+    if (w_src_stride < 0 || w_tgt_stride < 0 || scale_stride < 0) return fail(SPCN_E_ARG, "strides must be >= 0");
+    SPCN_CHECK(check_params(p, false));
+    return SPCN_OK;
+}
+
+spcn_status spcn_normalize_f32(const float* x, int64_t n, int64_t height, int64_t width, const float* w_src,
+                               int64_t w_src_stride, const float* w_tgt, int64_t w_tgt_stride, const float* scale_tgt,
+                               int64_t scale_stride, const float* i0_out, const spcn_params* p, float* y,
+                               float* p99_out, float* scale_out, int64_t* sel_idx, int32_t* flags_out, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_f32(x, n, height, width, w_src, w_src_stride, w_tgt, w_tgt_stride, scale_tgt, scale_stride, p));
+    if (!y) return fail(SPCN_E_ARG, "y is NULL");
+    const int64_t n_px = height * width;
+    if ((const void*)x < (const void*)(y + 3 * n * n_px) && (const void*)y < (const void*)(x + 3 * n * n_px))
+        return fail(SPCN_E_ARG, "y must not overlap x");
+    SPCN_CHECK(check_ws(ws, ws_bytes, f32_forward_workspace_bytes(n_px, n)));
+    F32Args a{x, n, n_px, w_src, w_src_stride, w_tgt, w_tgt_stride, scale_tgt, scale_stride, {0, 0, 0}};
+    for (int c = 0; c < 3; ++c) {
+        a.i0_out[c] = i0_out ? i0_out[c] : p->i0[c];
+        if (!finite_pos(a.i0_out[c])) return fail(SPCN_E_ARG, "i0_out[%d] must be finite and > 0", c);
+    }
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_forward_f32(a, make_params(p), y, p99_out, scale_out, sel_idx, flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_normalize_f32 launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, int64_t width, const float* w_src,
+                                    int64_t w_src_stride, const float* w_tgt, int64_t w_tgt_stride,
+                                    const float* scale_tgt, int64_t scale_stride, const float* i0_out,
+                                    const spcn_params* p, const float* p99, const int64_t* sel_idx,
+                                    const int32_t* flags, const float* grad_y, float* grad_x, float* grad_w_tgt,
+                                    float* grad_scale, void* ws, size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_f32(x, n, height, width, w_src, w_src_stride, w_tgt, w_tgt_stride, scale_tgt, scale_stride, p));
+    if (!p99 || !sel_idx || !flags) return fail(SPCN_E_ARG, "p99, sel_idx and flags (saved forward state) are required");
+    if (!grad_y || !grad_x || !grad_w_tgt || !grad_scale)
+        return fail(SPCN_E_ARG, "grad_y, grad_x, grad_w_tgt and grad_scale must be non-NULL");
+    const int64_t n_px = height * width;
+    SPCN_CHECK(check_ws(ws, ws_bytes, f32_backward_workspace_bytes(n_px, n)));
+    F32Args a{x, n, n_px, w_src, w_src_stride, w_tgt, w_tgt_stride, scale_tgt, scale_stride, {0, 0, 0}};
+    for (int c = 0; c < 3; ++c) {
+        a.i0_out[c] = i0_out ? i0_out[c] : p->i0[c];
+        if (!finite_pos(a.i0_out[c])) return fail(SPCN_E_ARG, "i0_out[%d] must be finite and > 0", c);
+    }
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_backward_f32(a, make_params(p), p99, sel_idx, flags, grad_y, grad_x, grad_w_tgt, grad_scale,
+                                       ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_normalize_backward launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_set_option(int opt, int value) {
+    if (opt < 0 || opt >= 3) return fail(SPCN_E_ARG, "unknown option %d", opt);
+    if (value < g_opt_lo[opt] || value > g_opt_hi[opt])
+        return fail(SPCN_E_ARG, "option %d: value %d outside [%d, %d]", opt, value, g_opt_lo[opt], g_opt_hi[opt]);
+    g_opt[opt].store(value, std::memory_order_relaxed);
+    return SPCN_OK;
+}
+
+int spcn_get_option(int opt) { return (opt >= 0 && opt < 3) ? g_opt[opt].load(std::memory_order_relaxed) : -1; }
 
 const char* spcn_status_string(spcn_status s) {
     switch (s) {

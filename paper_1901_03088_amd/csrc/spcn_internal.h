@@ -20,6 +20,9 @@ spcn_status hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::spcn::hip_fail(e_, #call);       \
     } while (0)
 
+// Process-wide tuning options (spcn_set_option).
+int option(int id);
+
 // Device properties of the current device (cached per device id).
 struct DevInfo {
     int id;
@@ -73,6 +76,7 @@ hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles
 
 // ---- batched persistent normalisation (spcn_batched.hip)
 size_t batched_workspace_bytes(int64_t n_tiles, int64_t total_px);
+int64_t batched_max_tiles();
 hipError_t launch_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px,
                                     const float* w_src, const float* w_tgt, const float* scale_tgt,
                                     const float i0_out[3], const ParamsK& pk, float* p99_out,

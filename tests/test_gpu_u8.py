@@ -224,3 +224,38 @@ def test_config1_full_size(S, orc):
     out, st, sc = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], p)
     o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, p)
     check_normalize("cfg1", out, st, o_out, o_st, o_hist)
+
+
+def test_kernel_variants_identical(S, orc):
+    """Every tuning variant (table copies, histogram columns, workgroups per CU) gives the same
+    histogram, statistics and output bytes."""
+    src = synth.make_image(0, 700, 900, device=DEV)
+    tgt = synth.make_image(1, 256, 256, device=DEV)
+    p = S.params()
+    saved = [S.get_option(o) for o in range(3)]
+    ref = None
+    try:
+        for v1 in range(4):
+            for v2, bpc in ((0, 8), (1, 4), (2, 1), (0, 2)):
+                S.set_option(S.OPT_P1_VARIANT, v1)
+                S.set_option(S.OPT_P2_VARIANT, v2)
+                S.set_option(S.OPT_P2_BLOCKS_PER_CU, bpc)
+                out, st, sc = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], p)
+                cur = (out.cpu().numpy(), st["hist"], st["p99_src"], st["scale"])
+                if ref is None:
+                    ref = cur
+                    o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, p)
+                    check_normalize("variants", out, st, o_out, o_st, o_hist)
+                else:
+                    for a, b in zip(ref, cur):
+                        assert np.array_equal(a, b), (v1, v2, bpc)
+    finally:
+        for o, v in enumerate(saved):
+            S.set_option(o, v)
+
+
+def test_option_validation(S):
+    import ctypes
+    assert S._L.spcn_set_option(0, 9) == S.SPCN_E_ARG
+    assert S._L.spcn_set_option(7, 0) == S.SPCN_E_ARG
+    assert S.get_option(7) == -1
