@@ -109,6 +109,10 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512):
     def run():
         W, _, _ = S.spcn_estimate_basis_batched(table, n_tiles, 4096, seed=30000, p=p, want_p99=False, ws=ws_b)
         S.spcn_normalize_batched(table, n_tiles, total, W, wt, sc, p, ws=ws_n, stats=False)
+        return W
+    from paper_1901_03088_amd import autotune
+    W_fit = run()
+    tuned = autotune.tune_batched(table, n_tiles, total, W_fit, wt, sc, outs, p)
     run()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -131,7 +135,7 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512):
                                   w_out=w1[t], ws=ws1)
             S.spcn_normalize(srcs[t], w1[t], wt, sc, p, out=outs[t], stats=False, ws=wsn1)
     ms_loop = timed(loop, max(1, steps // 4), 1, stream)
-    return {"tiles": n_tiles, "pixels": total, "graph_ms": round(ms_graph, 3),
+    return {"tiles": n_tiles, "pixels": total, "autotune": tuned["options"], "graph_ms": round(ms_graph, 3),
             "graph_Mpx_s": round(total / ms_graph / 1e3, 1), "per_tile_loop_ms": round(ms_loop, 3),
             "per_tile_loop_Mpx_s": round(total / ms_loop / 1e3, 1), "speedup": round(ms_loop / ms_graph, 2)}
 
@@ -175,6 +179,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="skip the batched and forward+backward measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg on float32), "
+                         "whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -206,6 +213,9 @@ def main() -> int:
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
+    from paper_1901_03088_amd import autotune
+    tuned = autotune.tune_image(img, w_src, w_tgt, scale_tgt, p)
+    log(f"[bench] autotune chose {tuned['options']}")
 
     def step(ev=None):
         # one step = the whole path for the slide: basis fit (200k samples) -> pass 1 -> pass 2
@@ -254,11 +264,22 @@ def main() -> int:
         "config": dict(desc, pixels=n_px, background_frac=0.6, lambda_density=0.01, io="uint8 RGB HWC"),
         "roofline": {"bound": "hbm", "kernel": k_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "autotune": tuned["options"],
         "path": {"basis_fit_ms": round(pbm, 4), "pass1_ms": round(p1m, 4), "pass2_ms": round(p2m, 4),
                  "normalize_ms": round(norm_ms, 4), "normalize_Mpx_s": round(n_px / norm_ms / 1e3, 1),
                  "normalize_GBs_9B_per_px": round(path_gbs, 1),
                  "normalize_frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},
     }
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        res["copy_calibration"] = {"kernel": "torch.neg float32", "read_bytes": a.numel() * 4,
+                                   "write_bytes": b.numel() * 4, "launches": 3}
+        del a, b
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img, W_src, tgt["W"], scale_tgt.cpu().numpy(), args.cpu_seconds)
     if args.extras and args.workload == "slide":

@@ -56,6 +56,8 @@ typedef enum {
 #define SPCN_FLAG_SHORT    16   /* basis estimation drew fewer tissue samples than requested      */
 #define SPCN_FLAG_BATCH    32   /* batched call: this tile was skipped (bad descriptor, total_px too
                                    small for the tiles, or a bounded wait expired)                  */
+#define SPCN_FLAG_TIMEOUT  64   /* a bounded device-side wait between workgroups expired: the
+                                   results of this call are invalid                                 */
 
 #define SPCN_HIST_BINS 256
 
@@ -219,10 +221,13 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
  *   SPCN_OPT_P2_VARIANT        pass-2 table copies: 0 = 1, 1 = 4 (256-thread groups), 2 = 16
  *                              (1024-thread groups)
  *   SPCN_OPT_P2_BLOCKS_PER_CU  pass-2 workgroups per compute unit, 1..16
+ *   SPCN_OPT_BATCH_CHUNK       batched normalisation: log2 of the 4-pixel units in one work item,
+ *                              12..16 (default 15 = 131072 pixels)
  * spcn_set_option returns SPCN_E_ARG for an unknown option or a value out of range. */
 #define SPCN_OPT_P1_VARIANT       0
 #define SPCN_OPT_P2_VARIANT       1
 #define SPCN_OPT_P2_BLOCKS_PER_CU 2
+#define SPCN_OPT_BATCH_CHUNK      3
 spcn_status spcn_set_option(int option, int value);
 /* Current value of an option, or -1 for an unknown option. */
 int spcn_get_option(int option);

@@ -24,11 +24,11 @@ _L = C.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ ABI mirror
 
 SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
-FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH = 1, 2, 4, 8, 16, 32
+FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT = 1, 2, 4, 8, 16, 32, 64
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
     OP_FORWARD_F32, OP_BACKWARD_F32 = range(7)
 HIST_BINS = 256
-OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU = range(3)
+OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
 
 class spcn_params(C.Structure):

@@ -1,0 +1,159 @@
+"""Autotuner for the library's run-time kernel variants.
+
+The library exposes tuning options (``spcn_set_option``) that select among kernel variants which
+compute identical results: pass-1 table replication / histogram columns / occupancy, pass-2 table
+replication / workgroup size / workgroups per CU, and the work-item size of the batched
+persistent kernel.  This module times the candidates on the caller's own workload (inputs already
+on the device), keeps a candidate only if its results equal the first candidate's byte for byte,
+selects the fastest, and can remember the choice in a JSON cache keyed by device name, workload
+kind and size class.  It only orchestrates: every candidate runs through the library's entry
+points.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Callable, Dict, Iterable, List, Optional, Tuple
+
+import torch
+
+from . import (OPT_BATCH_CHUNK, OPT_P1_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_P2_VARIANT, get_option, params,
+               set_option, spcn_densities, spcn_normalize_batched, spcn_recolor, workspace, workspace_size,
+               OP_NORMALIZE_BATCHED)
+
+P1_CANDIDATES = (0, 1, 2, 3, 4, 5)
+P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2))
+CHUNK_CANDIDATES = (12, 13, 14, 15, 16)
+
+
+def _median_ms(fn: Callable[[], None], reps: int) -> float:
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+    return t[len(t) // 2]
+
+
+def _sweep(cands: Iterable, apply: Callable, run: Callable[[], None], result: Callable[[], List[torch.Tensor]],
+           reps: int) -> Tuple[object, List[dict]]:
+    """Times every candidate; a candidate whose results differ from the first one's is rejected
+    (raises: variants are required to be identical)."""
+    ref = None
+    rows = []
+    best, best_ms = None, math.inf
+    for c in cands:
+        apply(c)
+        ms = _median_ms(run, reps)
+        cur = [r.clone() for r in result()]
+        if ref is None:
+            ref = cur
+        elif not all(torch.equal(a, b) for a, b in zip(ref, cur)):
+            raise RuntimeError(f"autotune: variant {c} changed the results")
+        rows.append({"candidate": c, "ms": round(ms, 4)})
+        if ms < best_ms:
+            best, best_ms = c, ms
+    return best, rows
+
+
+def size_class(n_px: int) -> int:
+    return int(math.log2(max(1, n_px)))
+
+
+def cache_key(kind: str, n_px: int, device: Optional[torch.device] = None) -> str:
+    name = torch.cuda.get_device_name(device)
+    return f"{name}|{kind}|2^{size_class(n_px)}"
+
+
+def load_cache(path: str) -> Dict[str, dict]:
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_cache(path: str, cache: Dict[str, dict]) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply(options: Dict[str, int]) -> None:
+    ids = {"p1_variant": OPT_P1_VARIANT, "p2_variant": OPT_P2_VARIANT, "p2_blocks_per_cu": OPT_P2_BLOCKS_PER_CU,
+           "batch_chunk_log2": OPT_BATCH_CHUNK}
+    for k, v in options.items():
+        if k in ids:
+            set_option(ids[k], int(v))
+
+
+def current() -> Dict[str, int]:
+    return {"p1_variant": get_option(OPT_P1_VARIANT), "p2_variant": get_option(OPT_P2_VARIANT),
+            "p2_blocks_per_cu": get_option(OPT_P2_BLOCKS_PER_CU), "batch_chunk_log2": get_option(OPT_BATCH_CHUNK)}
+
+
+def tune_image(img: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor, p=None,
+               reps: int = 5, cache_path: Optional[str] = None) -> dict:
+    """Tunes pass 1 and pass 2 of the single-image normalisation on `img` (uint8 HWC on the device);
+    leaves the chosen options set and returns them with the timings of every candidate."""
+    p = p or params()
+    n_px = int(img.shape[0]) * int(img.shape[1])
+    key = cache_key("image", n_px, img.device)
+    cache = load_cache(cache_path) if cache_path else {}
+    if key in cache:
+        apply(cache[key]["options"])
+        return dict(cache[key], cached=True)
+    hist = torch.empty((2, 256), dtype=torch.uint64, device=img.device)
+    out = torch.empty_like(img)
+
+    def p1_run():
+        spcn_densities(img, w_src, p, want_h=False, hist_out=hist, finalize=False)
+    best1, rows1 = _sweep(P1_CANDIDATES, lambda v: set_option(OPT_P1_VARIANT, v), p1_run, lambda: [hist], reps)
+    set_option(OPT_P1_VARIANT, best1)
+    p1_run()
+
+    def p2_set(c):
+        set_option(OPT_P2_VARIANT, c[0])
+        set_option(OPT_P2_BLOCKS_PER_CU, c[1])
+
+    def p2_run():
+        spcn_recolor(img, w_src, w_tgt, scale_tgt, hist, p, out=out, stats=False)
+    best2, rows2 = _sweep(P2_CANDIDATES, p2_set, p2_run, lambda: [out], reps)
+    p2_set(best2)
+    res = {"options": {"p1_variant": best1, "p2_variant": best2[0], "p2_blocks_per_cu": best2[1]},
+           "pass1": rows1, "pass2": [{"candidate": list(r["candidate"]), "ms": r["ms"]} for r in rows2],
+           "key": key, "cached": False}
+    if cache_path:
+        cache[key] = {k: v for k, v in res.items() if k != "cached"}
+        save_cache(cache_path, cache)
+    return res
+
+
+def tune_batched(table: torch.Tensor, n_tiles: int, total_px: int, w_src: torch.Tensor, w_tgt: torch.Tensor,
+                 scale_tgt: torch.Tensor, outs: List[torch.Tensor], p=None, reps: int = 5,
+                 cache_path: Optional[str] = None) -> dict:
+    """Tunes the work-item size of the batched persistent normalisation on the caller's tiles;
+    leaves the chosen option set."""
+    p = p or params()
+    key = cache_key(f"batched{n_tiles}", total_px, table.device)
+    cache = load_cache(cache_path) if cache_path else {}
+    if key in cache:
+        apply(cache[key]["options"])
+        return dict(cache[key], cached=True)
+    ws = workspace(workspace_size(OP_NORMALIZE_BATCHED, total_px, n_tiles), table.device)
+
+    def run():
+        spcn_normalize_batched(table, n_tiles, total_px, w_src, w_tgt, scale_tgt, p, ws=ws, stats=False)
+    best, rows = _sweep(CHUNK_CANDIDATES, lambda c: set_option(OPT_BATCH_CHUNK, c), run, lambda: outs, reps)
+    set_option(OPT_BATCH_CHUNK, best)
+    res = {"options": {"batch_chunk_log2": best}, "chunk": rows, "key": key, "cached": False}
+    if cache_path:
+        cache[key] = {k: v for k, v in res.items() if k != "cached"}
+        save_cache(cache_path, cache)
+    return res

@@ -13,11 +13,12 @@ namespace spcn {
 static thread_local char g_err[512];
 
 // option id -> (value, min, max)
-static std::atomic<int> g_opt[3] = {{0}, {0}, {8}};
-static const int g_opt_lo[3] = {0, 0, 1};
-static const int g_opt_hi[3] = {5, 2, 16};
+constexpr int N_OPT = 4;
+static std::atomic<int> g_opt[N_OPT] = {{0}, {0}, {8}, {15}};
+static const int g_opt_lo[N_OPT] = {0, 0, 1, 12};
+static const int g_opt_hi[N_OPT] = {5, 2, 16, 16};
 
-int option(int id) { return (id >= 0 && id < 3) ? g_opt[id].load(std::memory_order_relaxed) : 0; }
+int option(int id) { return (id >= 0 && id < N_OPT) ? g_opt[id].load(std::memory_order_relaxed) : 0; }
 
 spcn_status fail(spcn_status s, const char* fmt, ...) {
     va_list ap;
@@ -355,14 +356,14 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
 }
 
 spcn_status spcn_set_option(int opt, int value) {
-    if (opt < 0 || opt >= 3) return fail(SPCN_E_ARG, "unknown option %d", opt);
+    if (opt < 0 || opt >= N_OPT) return fail(SPCN_E_ARG, "unknown option %d", opt);
     if (value < g_opt_lo[opt] || value > g_opt_hi[opt])
         return fail(SPCN_E_ARG, "option %d: value %d outside [%d, %d]", opt, value, g_opt_lo[opt], g_opt_hi[opt]);
     g_opt[opt].store(value, std::memory_order_relaxed);
     return SPCN_OK;
 }
 
-int spcn_get_option(int opt) { return (opt >= 0 && opt < 3) ? g_opt[opt].load(std::memory_order_relaxed) : -1; }
+int spcn_get_option(int opt) { return (opt >= 0 && opt < N_OPT) ? g_opt[opt].load(std::memory_order_relaxed) : -1; }
 
 const char* spcn_status_string(spcn_status s) {
     switch (s) {

@@ -13,8 +13,9 @@
 // have a fixed order, so results are bitwise reproducible.
 //
 // Two layouts:
-//   * one image with many samples: several workgroups per H-step, per-workgroup FP64 partial sums,
-//     the last workgroup of each round (atomic ticket) reduces them in order and updates W;
+//   * one image with many samples: one launch for all rounds, up to 256 workgroups holding 1024
+//     samples each in registers; per round FP64 partial sums per workgroup, an arrival counter, and
+//     the same fixed-order reduction and W-step in every workgroup;
 //   * a batch of tiles: one 1024-thread workgroup per tile, samples held in registers, every round
 //     inside the workgroup.
 #include "spcn_internal.h"
@@ -26,8 +27,6 @@ namespace {
 
 constexpr int SAMPLE_BLOCK = 1024;     // candidates per workgroup and round
 constexpr int MAX_ROUNDS = 3;          // candidate budget 4, 12 and 48 times n_s
-constexpr int ITER_THREADS = 256;
-constexpr int ITER_MAX_BLOCKS = 512;
 constexpr int TILE_THREADS = 1024;
 constexpr int TILE_SPT = 4;            // samples per thread in the batched kernel (n_s <= 4096)
 
@@ -67,16 +66,22 @@ __device__ int block_rank(bool pred, int* s_wave, int* total) {
     return off + below;
 }
 
-// Sum of a double over the block in a fixed order (wave shuffles, then waves in order).
-__device__ double block_sum(double x, double* s_red) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+// Sums of N values over the workgroup (wavefront butterflies, then the waves in order); the
+// totals land in out[0..N) (shared) for every thread.  Fixed association: deterministic.
+template <int N>
+__device__ inline void block_sums(double (&v)[N], double* s_red, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) s_red[wave] = x;
+    for (int q = 0; q < N; ++q)
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+    if (lane == 0)
+        for (int q = 0; q < N; ++q) s_red[q * 16 + wave] = v[q];
     __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += s_red[w];
+    if (threadIdx.x < N) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += s_red[threadIdx.x * 16 + w];
+        out[threadIdx.x] = t;
+    }
     __syncthreads();
-    return t;
 }
 
 // FP64 basis for the H-step: Gram matrix and its determinant, from a double W.
@@ -211,9 +216,10 @@ __device__ double block_select(int64_t n, int64_t k, F val, uint32_t* s_hist, in
 struct BasisWork {          // layout of the caller's workspace (single image)
     int64_t n_s, max_cand;
     int32_t n_acc;          // samples kept so far
-    uint32_t ticket;        // arrival counter of the current round's workgroups
+    uint32_t arrive;        // NMF: workgroup arrivals, summed over rounds
+    int32_t base;           // sampling: samples kept before the current round
+    int32_t flags;          // SPCN_FLAG_TIMEOUT if a wait between workgroups expired
     double W[6];
-    int32_t flags;
 };
 
 struct SampleArgs {
@@ -222,7 +228,7 @@ struct SampleArgs {
     int64_t nb;             // workgroups in this round
     BasisWork* bw;
     int64_t* staging;       // [nb][SAMPLE_BLOCK]
-    int32_t* counts;        // [nb]
+    int32_t* counts;        // [nb] kept candidates per workgroup; the scan turns them into offsets
     int64_t* idx;           // [n_s] kept pixel indices
 };
 
@@ -242,52 +248,66 @@ __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_round(SampleArgs a) {
     if (threadIdx.x == 0) a.counts[blockIdx.x] = total;
 }
 
-// Appends the round's kept candidates, in draw order, until n_s are kept (one workgroup): an
-// exclusive scan of the per-workgroup counts, then one wavefront per source workgroup copies.
+// Exclusive scan of the round's per-workgroup counts (one workgroup), in place: counts[b] becomes
+// the rank of workgroup b's first kept candidate within the round and counts[nb] the round's total.
+// Records the samples kept before the round and the new total (capped at n_s).
 constexpr int MERGE_MAX_BLOCKS = 12288;   // rounds of at most 48 * 262144 candidates
-__global__ __launch_bounds__(1024) void k_sample_merge(SampleArgs a) {
-    __shared__ int s_off[MERGE_MAX_BLOCKS];
+__global__ __launch_bounds__(1024) void k_sample_scan(SampleArgs a) {
     __shared__ int s_part[1024];
     BasisWork* bw = a.bw;
-    if (bw->n_acc >= bw->n_s) return;
-    const int base = bw->n_acc;
+    const int t = threadIdx.x;
+    if (bw->n_acc >= bw->n_s) {                 // earlier rounds found enough: nothing to append
+        if (t == 0) bw->base = (int)bw->n_s;
+        return;
+    }
     const int nb = (int)a.nb;
     const int per = (nb + 1023) / 1024;
-    const int t = threadIdx.x;
     int run = 0;
     for (int i = 0; i < per; ++i) {
-        int b = t * per + i;
-        if (b < nb) { s_off[b] = run; run += a.counts[b]; }
+        const int b = t * per + i;
+        if (b < nb) run += a.counts[b];
     }
     s_part[t] = run;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-        int v = t >= o ? s_part[t - o] : 0;
+        const int v = t >= o ? s_part[t - o] : 0;
         __syncthreads();
         s_part[t] += v;
         __syncthreads();
     }
-    const int excl = t ? s_part[t - 1] : 0;
+    int off = t ? s_part[t - 1] : 0;
     for (int i = 0; i < per; ++i) {
-        int b = t * per + i;
-        if (b < nb) s_off[b] += excl;
+        const int b = t * per + i;
+        if (b < nb) {
+            const int c = a.counts[b];
+            a.counts[b] = off;
+            off += c;
+        }
     }
-    __syncthreads();
+    if (t == 0) {
+        const int base = bw->n_acc;
+        a.counts[nb] = s_part[1023];
+        bw->base = base;
+        bw->n_acc = (int)min((int64_t)base + s_part[1023], bw->n_s);
+    }
+}
+
+// Appends workgroup b's kept candidates of the round at their draw-order rank, while room is left.
+__global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_copy(SampleArgs a) {
+    const BasisWork* bw = a.bw;
+    const int base = bw->base;
     const int64_t room = bw->n_s - base;
-    const int lane = t & 63, wave = t >> 6;
-    for (int b = wave; b < nb; b += 16) {
-        const int off = s_off[b];
-        if (off >= room) continue;
-        const int c = a.counts[b];
-        for (int i = lane; i < c && off + i < room; i += 64) a.idx[base + off + i] = a.staging[(int64_t)b * SAMPLE_BLOCK + i];
-    }
-    __syncthreads();
-    if (t == 0) bw->n_acc = (int)min((int64_t)base + s_part[1023], bw->n_s);
+    if (room <= 0) return;
+    const int b = blockIdx.x;
+    const int64_t off = a.counts[b];
+    const int64_t c = a.counts[b + 1] - off;   // kept in this workgroup
+    const int i = threadIdx.x;
+    if (i < c && off + i < room) a.idx[base + off + i] = a.staging[(int64_t)b * SAMPLE_BLOCK + i];
 }
 
 __global__ void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->ticket = 0; bw->flags = 0;
+        bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->arrive = 0; bw->base = 0; bw->flags = 0;
         initial_basis(w_init, bw->W);
     }
 }
@@ -307,60 +327,91 @@ __global__ __launch_bounds__(256) void k_od_gather(const uint8_t* img, const int
     }
 }
 
-struct IterArgs {
+// The whole fit in one launch: every workgroup holds up to FIT_PER_BLOCK samples in registers for
+// all rounds.  Per round each workgroup publishes its FP64 partial sums (double-buffered by round
+// parity), arrives on a counter and waits for all others; then every workgroup reduces the same
+// partials in the same fixed order and performs the same W-step, so all hold bit-identical W.
+// The grid (at most 256 small workgroups) is far below what the chip keeps resident at once, so all
+// workgroups run concurrently; the wait is bounded nonetheless and reports SPCN_FLAG_TIMEOUT.
+constexpr int FIT_THREADS = 256;
+constexpr int FIT_SPT = 4;
+constexpr int FIT_PER_BLOCK = FIT_THREADS * FIT_SPT;
+constexpr int FIT_MAX_BLOCKS = FIT_THREADS;      // one partial row per thread in the reduction
+constexpr uint32_t FIT_SPIN_LIMIT = 1u << 20;
+
+struct FitArgs {
     BasisWork* bw;
     const double* V;        // [3][n_s]
-    double* partial;        // [gridDim][9]
+    double* partial;        // [2][gridDim][9]
     double lambda;
+    int32_t n_iter;
 };
 
-// One NMF round: H-step of every sample, FP64 partial sums per workgroup; the last workgroup to
-// arrive reduces the partials in workgroup order and performs the W-step.
-__global__ __launch_bounds__(ITER_THREADS) void k_nmf_round(IterArgs a) {
-    __shared__ double s_red[ITER_THREADS / 64];
+__global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
+    __shared__ double s_red[9 * 16];
     __shared__ double s_sum[9];
-    __shared__ int s_last;
+    __shared__ int s_abort;
     BasisWork* bw = a.bw;
-    NmfBasis B;
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    const unsigned nblk = gridDim.x;
+    double v[FIT_SPT][3];
+    bool live[FIT_SPT];
+#pragma unroll
+    for (int k = 0; k < FIT_SPT; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * FIT_PER_BLOCK + k * FIT_THREADS + threadIdx.x;
+        live[k] = i < n;
+        for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? a.V[c * ns + i] : 0.0;
+    }
     double W[6];
     for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
-    nmf_basis(W, a.lambda, B);
-    const int64_t n = bw->n_acc, ns = bw->n_s;
-    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        const double v0 = a.V[i], v1 = a.V[ns + i], v2 = a.V[2 * ns + i];
-        double h0, h1;
-        nmf_solve(B, v0, v1, v2, h0, h1);
-        acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
-        acc[3] += v0 * h0; acc[4] += v0 * h1;
-        acc[5] += v1 * h0; acc[6] += v1 * h1;
-        acc[7] += v2 * h0; acc[8] += v2 * h1;
-    }
-    for (int q = 0; q < 9; ++q) {
-        double t = block_sum(acc[q], s_red);
-        if (threadIdx.x == 0) a.partial[blockIdx.x * 9 + q] = t;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&bw->ticket, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (threadIdx.x < 9) {
-        double t = 0.0;
-        const volatile double* pp = a.partial;
-        for (unsigned b = 0; b < gridDim.x; ++b) t += pp[b * 9 + threadIdx.x];
-        s_sum[threadIdx.x] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        w_step(W, s_sum);
-        for (int i = 0; i < 6; ++i) bw->W[i] = W[i];
-        bw->ticket = 0;
+    for (int it = 0; it < a.n_iter; ++it) {
+        NmfBasis B;
+        nmf_basis(W, a.lambda, B);
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < FIT_SPT; ++k) {
+            if (!live[k]) continue;
+            double h0, h1;
+            nmf_solve(B, v[k][0], v[k][1], v[k][2], h0, h1);
+            acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
+            acc[3] += v[k][0] * h0; acc[4] += v[k][0] * h1;
+            acc[5] += v[k][1] * h0; acc[6] += v[k][1] * h1;
+            acc[7] += v[k][2] * h0; acc[8] += v[k][2] * h1;
+        }
+        block_sums(acc, s_red, s_sum);
+        double* part = a.partial + (size_t)(it & 1) * nblk * 9;
+        if (threadIdx.x < 9) part[blockIdx.x * 9 + threadIdx.x] = s_sum[threadIdx.x];
         __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&bw->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = (uint32_t)(it + 1) * nblk;
+            uint32_t spins = 0;
+            int abort = 0;
+            while (__hip_atomic_load(&bw->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > FIT_SPIN_LIMIT ||
+                    __hip_atomic_load(&bw->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    atomicOr(&bw->flags, SPCN_FLAG_TIMEOUT);
+                    abort = 1;
+                    break;
+                }
+            }
+            s_abort = abort;
+        }
+        __syncthreads();
+        if (s_abort) return;
+        double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (threadIdx.x < nblk)
+            for (int q = 0; q < 9; ++q)
+                tot[q] = __hip_atomic_load(part + threadIdx.x * 9 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        block_sums(tot, s_red, s_sum);
+        double sums[9];
+        for (int q = 0; q < 9; ++q) sums[q] = s_sum[q];
+        w_step(W, sums);           // every thread of every workgroup: the same update on the same sums
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int i = 0; i < 6; ++i) bw->W[i] = W[i];
 }
 
 // Unit columns, stain order, outputs; optionally the nearest-rank percentile of the fitted
@@ -379,7 +430,7 @@ __global__ __launch_bounds__(1024) void k_nmf_finish(BasisWork* bw, const double
     __syncthreads();
     const int64_t n = bw->n_acc, ns = bw->n_s;
     if (flags_out && threadIdx.x < 2)
-        flags_out[threadIdx.x] = (n < ns ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0);
+        flags_out[threadIdx.x] = (n < ns ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | bw->flags;
     if (!sample_p99) return;
     NmfBasis B;
     nmf_basis(s_W, lambda, B);
@@ -421,7 +472,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
     __shared__ int64_t s_idx[TILE_THREADS * TILE_SPT];
     __shared__ double s_od[3 * kHistBins];
     __shared__ int s_wave[TILE_THREADS / 64];
-    __shared__ double s_red[TILE_THREADS / 64];
+    __shared__ double s_red[9 * 16];
+    __shared__ double s_sum[9];
     __shared__ double s_W[6];
     __shared__ uint32_t s_hist[256];
     __shared__ int s_misc[2];
@@ -483,8 +535,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
             acc[5] += v[k][1] * h0; acc[6] += v[k][1] * h1;
             acc[7] += v[k][2] * h0; acc[8] += v[k][2] * h1;
         }
+        block_sums(acc, s_red, s_sum);
         double sums[9];
-        for (int q = 0; q < 9; ++q) sums[q] = block_sum(acc[q], s_red);
+        for (int q = 0; q < 9; ++q) sums[q] = s_sum[q];
         w_step(W, sums);           // every thread performs the same update on the same sums
     }
     finish_basis(W);
@@ -562,10 +615,10 @@ size_t basis_workspace_bytes(int64_t n_s) {
     const int64_t nb = max_round_blocks(n_s);
     size_t b = align256(sizeof(BasisWork));
     b += align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t));   // staging
-    b += align256((size_t)nb * sizeof(int32_t));                  // counts
+    b += align256((size_t)(nb + 1) * sizeof(int32_t));            // counts / offsets
     b += align256((size_t)n_s * sizeof(int64_t));                 // idx
     b += align256((size_t)3 * n_s * sizeof(double));              // V
-    b += align256((size_t)ITER_MAX_BLOCKS * 9 * sizeof(double));  // partial sums
+    b += align256((size_t)2 * FIT_MAX_BLOCKS * 9 * sizeof(double));  // partial sums
     return b;
 }
 
@@ -577,7 +630,7 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
     const int64_t nbmax = max_round_blocks(n_s);
     int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
-    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)nbmax * sizeof(int32_t));
+    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
     double* V = reinterpret_cast<double*>(p); p += align256((size_t)3 * n_s * sizeof(double));
     double* partial = reinterpret_cast<double*>(p);
@@ -590,16 +643,16 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
         SampleArgs a{img, n_px, pk.white_sum, seed, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
                      counts, idx};
         hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_sample_merge, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
         t0 += rc;
     }
     hipLaunchKernelGGL(k_od_gather, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s, img, idx,
                        bw, pk.i0[0], pk.i0[1], pk.i0[2], V);
-    int nblk = (int)hmin(hmin((n_s + 1023) / 1024, ITER_MAX_BLOCKS), dev.cus);
-    if (nblk < 1) nblk = 1;
-    IterArgs ia{bw, V, partial, (double)lambda_nmf};
-    for (int it = 0; it < n_iter; ++it)
-        hipLaunchKernelGGL(k_nmf_round, dim3(nblk), dim3(ITER_THREADS), 0, s, ia);
+    const int nblk = (int)((n_s + FIT_PER_BLOCK - 1) / FIT_PER_BLOCK);
+    if (nblk > FIT_MAX_BLOCKS) return hipErrorInvalidValue;
+    FitArgs fa{bw, V, partial, (double)lambda_nmf, n_iter};
+    if (n_iter > 0) hipLaunchKernelGGL(k_nmf_fit, dim3(nblk), dim3(FIT_THREADS), 0, s, fa);
     hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(1024), 0, s, bw, (const double*)V, (double)lambda_nmf, pk.q64,
                        w_out, sample_p99, flags_out);
     return hipGetLastError();

@@ -21,7 +21,7 @@ namespace {
 
 constexpr int RUN_THREADS = 1024;
 constexpr int RUN_UNROLL = 2;
-constexpr int CHUNK_UNITS = 32768;            // 131072 pixels per item
+constexpr int MIN_CHUNK_LOG2 = 12;           // smallest work item: 4096 units = 16384 pixels
 constexpr int B_COPIES = 4, B_COLS = 32;      // pass-1 table copies / histogram columns
 constexpr uint32_t SPIN_LIMIT = 1u << 26;
 constexpr int MAX_TILES = 8192;
@@ -60,7 +60,7 @@ struct BatchWs {
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 __host__ __device__ inline int64_t max_items_for(int64_t n_tiles, int64_t total_px) {
-    return total_px / (4 * (int64_t)CHUNK_UNITS) + n_tiles;
+    return total_px / (4 * ((int64_t)1 << MIN_CHUNK_LOG2)) + n_tiles;
 }
 
 __host__ __device__ inline BatchWs carve(void* ws, int64_t n, int64_t total_px) {
@@ -83,6 +83,7 @@ struct SetupArgs {
     const spcn_tile* tiles;
     const float* w_src;         // [n][6]
     P1Params pp;
+    int chunk_log2;             // 4-pixel units per work item = 2^chunk_log2
     BatchWs w;
 };
 
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
         TileInfo I;
         I.units = n_px >> 2;
         I.tail = (int32_t)(n_px & 3);
-        I.n_chunks = (int32_t)((I.units + CHUNK_UNITS - 1) / CHUNK_UNITS);
+        I.n_chunks = (int32_t)((I.units + ((int64_t)1 << a.chunk_log2) - 1) >> a.chunk_log2);
         if (I.n_chunks < 1) I.n_chunks = 1;
         I.item0 = 0;
         I.shift = s_shift;
@@ -134,17 +135,30 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
 
 
 // Exclusive scan of the tiles' chunk counts -> first item of every tile, then the item -> tile map.
-__global__ __launch_bounds__(1024) void k_tiles_plan(BatchWs w, int n_tiles, int64_t cap_items, int32_t* flags_out) {
+// The caller's total_px must bound the tiles' pixel count (it sized the workspace); otherwise the
+// whole batch is refused.
+__global__ __launch_bounds__(1024) void k_tiles_plan(BatchWs w, int n_tiles, int64_t total_px, int64_t cap_items,
+                                                     int32_t* flags_out) {
     __shared__ int32_t s_off[MAX_TILES];
     __shared__ int32_t s_part[1024];
+    __shared__ unsigned long long s_px;
     const int t0 = threadIdx.x;
     const int per = (n_tiles + 1023) / 1024;
+    if (t0 == 0) s_px = 0;
+    __syncthreads();
     int run = 0;
+    int64_t px = 0;
     for (int i = 0; i < per; ++i) {
         const int t = t0 * per + i;
-        if (t < n_tiles) { s_off[t] = run; run += w.info[t].n_chunks; }
+        if (t < n_tiles) {
+            const TileInfo I = w.info[t];
+            s_off[t] = run;
+            run += I.n_chunks;
+            px += 4 * I.units + I.tail;
+        }
     }
     s_part[t0] = run;
+    atomicAdd(&s_px, (unsigned long long)px);
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
         const int v = t0 >= o ? s_part[t0 - o] : 0;
@@ -158,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_tiles_plan(BatchWs w, int n_tiles, int
         if (t < n_tiles) { s_off[t] += excl; w.info[t].item0 = s_off[t]; }
     }
     int total = s_part[1023];
-    const bool fits = total <= cap_items;    // total_px given by the caller bounds the item count
+    const bool fits = total <= cap_items && (int64_t)s_px <= total_px;
     if (t0 == 0) {
         w.head->queue = 0;
         w.head->p1_items = fits ? (uint32_t)total : 0u;
@@ -189,6 +203,7 @@ struct RunArgs {
     float i0_out[3];
     P1Params pp;
     double q;
+    int chunk_log2;
     BatchWs w;
     float* p99_out;
     float* scale_out;
@@ -223,8 +238,8 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
         const TileInfo I = a.w.info[t];
         const spcn_tile T = a.tiles[t];
         const int chunk = (int)((first ? item : item - p1_items) - I.item0);
-        const int64_t u0 = (int64_t)chunk * CHUNK_UNITS;
-        const int cnt = (int)min((int64_t)CHUNK_UNITS, I.units - u0);
+        const int64_t u0 = (int64_t)chunk << a.chunk_log2;
+        const int cnt = (int)min((int64_t)1 << a.chunk_log2, I.units - u0);
         const bool last_chunk = chunk == I.n_chunks - 1;
 
         if (first) {
@@ -278,7 +293,10 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
                     if (++spins > SPIN_LIMIT) {
                         go = 0;
                         atomicOr(&a.w.head->error, 1);
-                        if (a.flags_out) { atomicOr(a.flags_out + 2 * t, SPCN_FLAG_BATCH); atomicOr(a.flags_out + 2 * t + 1, SPCN_FLAG_BATCH); }
+                        if (a.flags_out) {
+                            atomicOr(a.flags_out + 2 * t, SPCN_FLAG_BATCH | SPCN_FLAG_TIMEOUT);
+                            atomicOr(a.flags_out + 2 * t + 1, SPCN_FLAG_BATCH | SPCN_FLAG_TIMEOUT);
+                        }
                         break;
                     }
                 }
@@ -321,17 +339,18 @@ hipError_t launch_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int
                                     void* ws, const DevInfo& dev, hipStream_t s) {
     BatchWs w = carve(ws, n_tiles, total_px);
     SetupArgs sa{};
-    sa.tiles = tiles; sa.w_src = w_src; sa.w = w;
+    const int chunk_log2 = option(SPCN_OPT_BATCH_CHUNK);
+    sa.tiles = tiles; sa.w_src = w_src; sa.w = w; sa.chunk_log2 = chunk_log2;
     for (int c = 0; c < 3; ++c) sa.pp.i0[c] = pk.i0[c];
     sa.pp.lambda = pk.lambda; sa.pp.white_sum = pk.white_sum;
     sa.pp.hist_hi[0] = pk.hist_hi[0]; sa.pp.hist_hi[1] = pk.hist_hi[1];
     hipLaunchKernelGGL(k_tiles_setup, dim3(n_tiles), dim3(256), 0, s, sa);
-    hipLaunchKernelGGL(k_tiles_plan, dim3(1), dim3(1024), 0, s, w, (int)n_tiles, max_items_for(n_tiles, total_px),
-                       flags_out);
+    hipLaunchKernelGGL(k_tiles_plan, dim3(1), dim3(1024), 0, s, w, (int)n_tiles, total_px,
+                       max_items_for(n_tiles, total_px), flags_out);
     RunArgs ra{};
     ra.tiles = tiles; ra.w_tgt = w_tgt; ra.scale_tgt = scale_tgt;
     for (int c = 0; c < 3; ++c) ra.i0_out[c] = i0_out[c];
-    ra.pp = sa.pp; ra.q = pk.q64; ra.w = w;
+    ra.pp = sa.pp; ra.q = pk.q64; ra.w = w; ra.chunk_log2 = chunk_log2;
     ra.p99_out = p99_out; ra.scale_out = scale_out; ra.flags_out = flags_out;
     hipLaunchKernelGGL(k_tiles_run, dim3(dev.cus), dim3(RUN_THREADS), 0, s, ra);
     return hipGetLastError();

@@ -29,9 +29,16 @@ namespace spcn {
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 constexpr int kBufDword3 = 0x00020000;   // raw (untyped) buffer, gfx9-family descriptor word 3
 
+// Buffer resource over `units` 12-byte units starting at unit `unit0` of `base`.  Every argument
+// must be the same in all lanes of the wavefront (a workgroup's chunk): the fields are moved to
+// scalar registers explicitly, because a descriptor the compiler keeps in vector registers is
+// wrapped in a per-access loop over distinct lane values.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void* base, int64_t unit0, int64_t units) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(static_cast<const uint8_t*>(base)) + 12 * unit0,
-                                             0, (int)(12 * units), kBufDword3);
+    const uint64_t addr = reinterpret_cast<uint64_t>(base) + 12 * (uint64_t)unit0;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+    const int n = __builtin_amdgcn_readfirstlane((int)(12 * units));
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, n, kBufDword3);
 }
 
 __device__ __forceinline__ void bytes_of_unit(u32x3 d, uint32_t px[4][3]) {

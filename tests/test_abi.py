@@ -104,3 +104,23 @@ def test_workspace_sizes(lib):
     assert lib.workspace_size(lib.OP_NORMALIZE, 1000) >= 2 * 256 * 8
     assert lib.workspace_size(99, 10) == 0
     assert lib.workspace_size(lib.OP_NORMALIZE, -1) == 0
+
+
+def test_options_ranges(lib):
+    """Tuning options: defaults, accepted ranges, rejection of unknown options and bad values."""
+    saved = [lib.get_option(o) for o in range(4)]
+    assert saved == [0, 0, 8, 15]
+    try:
+        for opt, lo, hi in ((lib.OPT_P1_VARIANT, 0, 5), (lib.OPT_P2_VARIANT, 0, 2),
+                            (lib.OPT_P2_BLOCKS_PER_CU, 1, 16), (lib.OPT_BATCH_CHUNK, 12, 16)):
+            for v in (lo, hi):
+                lib.set_option(opt, v)
+                assert lib.get_option(opt) == v
+            assert lib._L.spcn_set_option(opt, lo - 1) == lib.SPCN_E_ARG
+            assert lib._L.spcn_set_option(opt, hi + 1) == lib.SPCN_E_ARG
+            assert lib.get_option(opt) == hi
+        assert lib._L.spcn_set_option(4, 0) == lib.SPCN_E_ARG
+        assert lib.get_option(4) == -1 and lib.get_option(-1) == -1
+    finally:
+        for o, v in enumerate(saved):
+            lib.set_option(o, v)

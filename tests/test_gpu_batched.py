@@ -61,6 +61,35 @@ def test_batched_equals_per_tile(S, orc, shapes):
             assert np.array_equal(o_st["P"].astype(np.float32), p99[t])
 
 
+def test_batched_chunk_sizes_identical(S):
+    """Every work-item size of the batched kernel gives the same bytes and statistics."""
+    p = S.params()
+    shapes = [(1024, 1024), (300, 200), (2048, 576), (64, 64), (1, 7)]
+    tiles, srcs, outs = make_batch(shapes, seed0=50)
+    tgt, wt, sc = target(S, p)
+    W = torch.stack([S.as_basis(d["W"], DEV) for d in tiles]).contiguous()
+    table = S.tile_table(srcs, outs)
+    total = sum(h * w for h, w in shapes)
+    saved = S.get_option(S.OPT_BATCH_CHUNK)
+    ref = None
+    try:
+        for c in (12, 13, 14, 15, 16):
+            S.set_option(S.OPT_BATCH_CHUNK, c)
+            for o in outs:
+                o.zero_()
+            st = S.spcn_normalize_batched(table, len(shapes), total, W, wt, sc, p)
+            torch.cuda.synchronize()
+            cur = [o.cpu().numpy() for o in outs] + [st["p99"].cpu().numpy(), st["scale"].cpu().numpy(),
+                                                     st["flags"].cpu().numpy()]
+            if ref is None:
+                ref = cur
+            else:
+                for a, b in zip(ref, cur):
+                    assert np.array_equal(a, b), c
+    finally:
+        S.set_option(S.OPT_BATCH_CHUNK, saved)
+
+
 def test_batched_bad_total_px_flags(S):
     p = S.params()
     tiles, srcs, outs = make_batch([(64, 64), (128, 64)])

@@ -232,10 +232,10 @@ def test_kernel_variants_identical(S, orc):
     src = synth.make_image(0, 700, 900, device=DEV)
     tgt = synth.make_image(1, 256, 256, device=DEV)
     p = S.params()
-    saved = [S.get_option(o) for o in range(3)]
+    saved = [S.get_option(o) for o in range(4)]
     ref = None
     try:
-        for v1 in range(4):
+        for v1 in range(6):
             for v2, bpc in ((0, 8), (1, 4), (2, 1), (0, 2)):
                 S.set_option(S.OPT_P1_VARIANT, v1)
                 S.set_option(S.OPT_P2_VARIANT, v2)
