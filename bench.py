@@ -214,7 +214,10 @@ def main() -> int:
 
     stream = torch.cuda.current_stream()
     from paper_1901_03088_amd import autotune
-    tuned = autotune.tune_image(img, w_src, w_tgt, scale_tgt, p)
+    # tune on the basis the step fits (the bin distribution, hence LDS contention, depends on it)
+    S.spcn_estimate_basis(img, n_samples, seed=2024, p=S.params(), lambda_nmf=0.1, n_iter=50, want_p99=False,
+                          w_out=w_fit, ws=ws_fit)
+    tuned = autotune.tune_image(img, w_fit, w_tgt, scale_tgt, p)
     log(f"[bench] autotune chose {tuned['options']}")
 
     def step(ev=None):

@@ -217,9 +217,12 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
  *   SPCN_OPT_P1_VARIANT        pass-1 table copies / histogram columns / units per thread and
  *                              iteration / workgroups per CU: 0 = (1, 64, 4, 1), 1 = (2, 64, 4, 1),
  *                              2 = (4, 32, 4, 1), 3 = (8, 16, 4, 1), 4 = (1, 32, 2, 2),
- *                              5 = (2, 16, 2, 2)
- *   SPCN_OPT_P2_VARIANT        pass-2 table copies: 0 = 1, 1 = 4 (256-thread groups), 2 = 16
- *                              (1024-thread groups)
+ *                              5 = (2, 16, 2, 2); 6, 7 = byte-permute table layout (8 copies,
+ *                              16 columns), grid-stride tiles, 4 or 2 units per thread and
+ *                              iteration; 8, 9 = the same with bin-0 counts in a lane-private row
+ *   SPCN_OPT_P2_VARIANT        pass-2 table copies / workgroup size, contiguous chunks: 0 = (1, 256),
+ *                              1 = (4, 256), 2 = (16, 1024); grid-stride tiles: 3 = (1, 256),
+ *                              4 = (1, 512), 5 = (16, 1024)
  *   SPCN_OPT_P2_BLOCKS_PER_CU  pass-2 workgroups per compute unit, 1..16
  *   SPCN_OPT_BATCH_CHUNK       batched normalisation: log2 of the 4-pixel units in one work item,
  *                              12..16 (default 15 = 131072 pixels)

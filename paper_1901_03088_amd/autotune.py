@@ -22,8 +22,9 @@ from . import (OPT_BATCH_CHUNK, OPT_P1_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_P2_VAR
                set_option, spcn_densities, spcn_normalize_batched, spcn_recolor, workspace, workspace_size,
                OP_NORMALIZE_BATCHED)
 
-P1_CANDIDATES = (0, 1, 2, 3, 4, 5)
-P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (0, 8), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2))
+P1_CANDIDATES = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9)
+P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 1), (3, 1), (3, 2), (3, 4), (3, 8), (4, 1), (4, 2),
+                 (4, 4), (5, 1))
 CHUNK_CANDIDATES = (12, 13, 14, 15, 16)
 
 

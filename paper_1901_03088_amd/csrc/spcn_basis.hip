@@ -13,7 +13,7 @@
 // have a fixed order, so results are bitwise reproducible.
 //
 // Two layouts:
-//   * one image with many samples: one launch for all rounds, up to 256 workgroups holding 1024
+//   * one image with many samples: one launch for all rounds, up to 64 workgroups holding 4096
 //     samples each in registers; per round FP64 partial sums per workgroup, an arrival counter, and
 //     the same fixed-order reduction and W-step in every workgroup;
 //   * a batch of tiles: one 1024-thread workgroup per tile, samples held in registers, every round
@@ -88,6 +88,7 @@ __device__ inline void block_sums(double (&v)[N], double* s_red, double* out) {
 struct NmfBasis {
     double w[6];
     double g00, g01, g11, det, half_lambda;
+    double r_det, r00, r11;     // reciprocals of det, g00, g11 (the H-step multiplies)
     int ok;
 };
 
@@ -101,6 +102,9 @@ __device__ inline void nmf_basis(const double* W, double lambda, NmfBasis& B) {
     B.det = g00 * g11 - g01 * g01;
     B.half_lambda = 0.5 * lambda;
     B.ok = g00 > 0.0 && g11 > 0.0 && B.det > 0.0;
+    B.r_det = B.ok ? 1.0 / B.det : 0.0;
+    B.r00 = B.ok ? 1.0 / g00 : 0.0;
+    B.r11 = B.ok ? 1.0 / g11 : 0.0;
 }
 
 // Exact non-negative lasso of one sample (Eq. 2 with W fixed): h_j = max(0, min(p_j, f_j)) with
@@ -112,9 +116,9 @@ __device__ inline void nmf_solve(const NmfBasis& B, double v0, double v1, double
     double b0 = W[0] * v0; b0 = b0 + W[1] * v1; b0 = b0 + W[2] * v2; b0 = b0 - B.half_lambda;
     double b1 = W[3] * v0; b1 = b1 + W[4] * v1; b1 = b1 + W[5] * v2; b1 = b1 - B.half_lambda;
     if (B.ok) {
-        double f0 = (B.g11 * b0 - B.g01 * b1) / B.det;
-        double f1 = (B.g00 * b1 - B.g01 * b0) / B.det;
-        double p0 = b0 / B.g00, p1 = b1 / B.g11;
+        double f0 = (B.g11 * b0 - B.g01 * b1) * B.r_det;
+        double f1 = (B.g00 * b1 - B.g01 * b0) * B.r_det;
+        double p0 = b0 * B.r00, p1 = b1 * B.r11;
         double t0 = p0 < f0 ? p0 : f0, t1 = p1 < f1 ? p1 : f1;
         h0 = t0 > 0.0 ? t0 : 0.0;
         h1 = t1 > 0.0 ? t1 : 0.0;
@@ -331,13 +335,15 @@ __global__ __launch_bounds__(256) void k_od_gather(const uint8_t* img, const int
 // all rounds.  Per round each workgroup publishes its FP64 partial sums (double-buffered by round
 // parity), arrives on a counter and waits for all others; then every workgroup reduces the same
 // partials in the same fixed order and performs the same W-step, so all hold bit-identical W.
-// The grid (at most 256 small workgroups) is far below what the chip keeps resident at once, so all
+// The grid (at most 64 workgroups) is far below what the chip keeps resident at once, so all
 // workgroups run concurrently; the wait is bounded nonetheless and reports SPCN_FLAG_TIMEOUT.
-constexpr int FIT_THREADS = 256;
-constexpr int FIT_SPT = 4;
+constexpr int FIT_THREADS = 512;
+constexpr int FIT_SPT = 8;
 constexpr int FIT_PER_BLOCK = FIT_THREADS * FIT_SPT;
-constexpr int FIT_MAX_BLOCKS = FIT_THREADS;      // one partial row per thread in the reduction
+constexpr int FIT_MAX_BLOCKS = 64;               // kMaxBasisSamples / FIT_PER_BLOCK
 constexpr uint32_t FIT_SPIN_LIMIT = 1u << 20;
+static_assert(FIT_MAX_BLOCKS * FIT_PER_BLOCK >= kMaxBasisSamples, "fit grid must cover every sample");
+static_assert(FIT_MAX_BLOCKS <= FIT_THREADS, "one partial row per thread in the reduction");
 
 struct FitArgs {
     BasisWork* bw;
@@ -381,15 +387,16 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
         block_sums(acc, s_red, s_sum);
         double* part = a.partial + (size_t)(it & 1) * nblk * 9;
         if (threadIdx.x < 9) part[blockIdx.x * 9 + threadIdx.x] = s_sum[threadIdx.x];
-        __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
+            // one release per workgroup and round publishes its partials; the wait polls with
+            // relaxed loads and a single acquire follows (no cache maintenance inside the loop)
             __hip_atomic_fetch_add(&bw->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t target = (uint32_t)(it + 1) * nblk;
             uint32_t spins = 0;
             int abort = 0;
-            while (__hip_atomic_load(&bw->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&bw->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > FIT_SPIN_LIMIT ||
                     __hip_atomic_load(&bw->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                     atomicOr(&bw->flags, SPCN_FLAG_TIMEOUT);
@@ -397,6 +404,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_abort = abort;
         }
         __syncthreads();

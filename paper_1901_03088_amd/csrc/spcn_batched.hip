@@ -288,7 +288,7 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
             if (tid == 0) {
                 uint32_t spins = 0;
                 int go = 1;
-                while (__hip_atomic_load(&a.w.ready[t], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                while (__hip_atomic_load(&a.w.ready[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
                     __builtin_amdgcn_s_sleep(8);
                     if (++spins > SPIN_LIMIT) {
                         go = 0;
@@ -300,6 +300,7 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
                         break;
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // pairs with the release of ready[t]
                 S.go = go && !I.bad;
                 if (go) S.K = a.w.K[t];
             }

@@ -24,6 +24,8 @@
 #include "spcn_device.hpp"
 #include "../../include/spcn.h"
 
+#include <cstddef>
+
 namespace spcn {
 
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
@@ -69,6 +71,13 @@ struct P1Params {
     int32_t white_sum;
     float hist_hi[2];
 };
+
+// A fixed-point sum x (value + guard, in units of 2^-u bin) decides its bin only if it is not within
+// the guard band of an edge k * 2^u with k >= 1.  Edge 0 needs no decision: every value below
+// 2^u, negative ones included (h = max(0, .)), lands in bin 0.
+__device__ __forceinline__ bool near_edge(int32_t x, int32_t fmask) {
+    return ((x & fmask) < 2 * kGuardUnits) & (x >= 2 * kGuardUnits);
+}
 
 // FP64 basis quantities, fixed-point shift and tables for one basis (whole workgroup; ends with a
 // barrier).  Requires blockDim.x >= 256.
@@ -135,7 +144,7 @@ __device__ void p1_chunk(P1Lds<COPIES, COLS>& S, const P1Params& pp, __amdgpu_bu
         const int4 a = entry(0, R), b = entry(1, G), c = entry(2, Bc);
         const int32_t x0 = min(a.x + b.x + c.x, a.y + b.y + c.y);
         const int32_t x1 = min(a.z + b.z + c.z, a.w + b.w + c.w);
-        const bool near = ((x0 & fmask) < 2 * kGuardUnits) | ((x1 & fmask) < 2 * kGuardUnits);
+        const bool near = near_edge(x0, fmask) | near_edge(x1, fmask);
         if (near) {
             double d0, d1;
             solve64(S.B, od_u8((double)pp.i0[0], (int)R), od_u8((double)pp.i0[1], (int)G),
@@ -181,7 +190,7 @@ __device__ void p1_chunk(P1Lds<COPIES, COLS>& S, const P1Params& pp, __amdgpu_bu
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const bool near = ((x0[q] & fmask) < 2 * kGuardUnits) | ((x1[q] & fmask) < 2 * kGuardUnits);
+                    const bool near = near_edge(x0[q], fmask) | near_edge(x1[q], fmask);
                     any_near |= tis[q] & near;
                     const uint32_t inc = (tis[q] & !near) ? 1u : 0u;
                     const int k0 = min(max(x0[q] >> u, 0), kHistBins - 1);
@@ -224,7 +233,7 @@ __device__ void p1_tail(P1Lds<COPIES, COLS>& S, const P1Params& pp, const uint8_
         const int32_t x0 = min(a.x + b.x + c.x, a.y + b.y + c.y);
         const int32_t x1 = min(a.z + b.z + c.z, a.w + b.w + c.w);
         int k0, k1;
-        if (((x0 & fmask) < 2 * kGuardUnits) | ((x1 & fmask) < 2 * kGuardUnits)) {
+        if (near_edge(x0, fmask) | near_edge(x1, fmask)) {
             double d0, d1;
             solve64(S.B, od_u8((double)pp.i0[0], (int)R), od_u8((double)pp.i0[1], (int)G),
                     od_u8((double)pp.i0[2], (int)Bc), d0, d1);
@@ -249,6 +258,264 @@ __device__ void p1_merge(P1Lds<COPIES, COLS>& S, unsigned long long* ghist) {
         const uint32_t* row = S.hist + t * COLS;
         uint32_t sum = 0;
         for (int l = 0; l < COLS; ++l) sum += row[(l + t) & (COLS - 1)];   // rotated: no bank conflicts
+        if (sum) atomicAdd(ghist + t, (unsigned long long)sum);
+    }
+}
+
+// ---------------------------------------------------------------- pass 1, byte-permute layout
+// The same exact counting with a table layout chosen so that every LDS address is one v_perm_b32
+// away from the pixel's dword: slot k (256 B) belongs to byte value k.
+//   region 0 (64 KB): R entry copy r at r*16, G entry copy r at 128 + r*16      (r = lane & 7)
+//   region 1 (64 KB): B entry copy r at r*16; the histogram words of bin k at 128 + j*64 + col*4
+// An address is (value << 8) | (region << 16) | lane bits; the perm takes the value byte from the
+// pixel's dword and the lane/region bytes from a per-lane constant.  With 2^16 fixed-point units
+// (when the basis allows it, see table_shift) the bin is byte 2 of the clamped sum, so a bin
+// address is one med3 + one perm.  Near-edge pixels take the same FP64 path as before.
+//
+// The tables of this layout carry the guard shifted down by 2 * kGuardUnits: a sum y = x - 4 (x as
+// in the other layout) is near an edge k >= 1 iff y >= 0 and its low u bits are >= 2^u - 4, i.e.
+// iff (y & (sign | bits 2..u-1)) == bits 2..u-1, one AND and one compare.  Away from edges the bin
+// of y equals the bin of x, so bins are taken from y directly.
+struct P1FLds {
+    int4 mem[2 * kHistBins * 16];   // 2 regions x 256 slots x 256 B
+    uint32_t zero[2][64];           // bin-0 counts, one word per lane: bin 0 is often shared by most
+                                    // lanes of a wavefront (an absent stain), so it gets its own row
+    Basis64 B;
+    int shift;                      // fixed-point resolution u (<= 16)
+};
+
+constexpr uint32_t kZeroRow = 2u * kHistBins * 256u;   // byte offset of P1FLds::zero from mem
+static_assert(offsetof(P1FLds, zero) == kZeroRow, "zero row follows the two table regions");
+
+constexpr uint32_t kRegion1 = 0x10000u;
+constexpr uint32_t kHistOff = 128u;
+
+// selector placing byte p of S0 in byte 1, S1's bytes 0 and 2 in bytes 0 and 2, zero in byte 3
+__device__ __forceinline__ constexpr uint32_t perm_sel(int p) { return 0x0c020000u | ((uint32_t)(4 + p) << 8); }
+
+__device__ __forceinline__ uint32_t p1f_hist_addr(int bin, uint32_t lh) { return ((uint32_t)bin << 8) | lh; }
+
+__device__ void p1f_setup(P1FLds& S, const float* w, const P1Params& pp, bool zero_hist) {
+    const int tid = threadIdx.x;
+    uint32_t* words = reinterpret_cast<uint32_t*>(S.mem);
+    if (zero_hist) {
+        for (int i = tid; i < kHistBins * 32; i += blockDim.x)
+            words[(kRegion1 + (uint32_t)(i >> 5) * 256u + kHistOff) / 4 + (i & 31)] = 0u;
+        for (int i = tid; i < 128; i += blockDim.x) S.zero[i >> 6][i & 63] = 0u;
+    }
+    if (tid == 0) {
+        derive_basis(w, pp.lambda, S.B);
+        const int u = table_shift(S.B, pp.i0, pp.hist_hi);
+        S.shift = u < 16 ? u : 16;
+    }
+    __syncthreads();
+    const int u = S.shift;
+    if (tid < kHistBins) {
+        const int k = tid;
+        const double sig0 = ldexp(256.0 / (double)pp.hist_hi[0], u), sig1 = ldexp(256.0 / (double)pp.hist_hi[1], u);
+        char* base = reinterpret_cast<char*>(S.mem);
+        for (int c = 0; c < 3; ++c) {
+            const double od = S.B.ok ? od_u8((double)pp.i0[c], k) : 0.0;
+            const int g = c == 0 ? kGuardUnits - 2 * kGuardUnits : 0;   // shifted guard (see above)
+            int4 e;
+            e.x = __double2int_rn((S.B.pc[0][c] * od + (c == 0 ? S.B.pconst[0] : 0.0)) * sig0) + g;
+            e.y = __double2int_rn((S.B.q[0][c] * od + (c == 0 ? S.B.fconst[0] : 0.0)) * sig0) + g;
+            e.z = __double2int_rn((S.B.pc[1][c] * od + (c == 0 ? S.B.pconst[1] : 0.0)) * sig1) + g;
+            e.w = __double2int_rn((S.B.q[1][c] * od + (c == 0 ? S.B.fconst[1] : 0.0)) * sig1) + g;
+            const uint32_t off = (c == 2 ? kRegion1 : 0u) + (c == 1 ? 128u : 0u) + ((uint32_t)k << 8);
+            for (int r = 0; r < 8; ++r) *reinterpret_cast<int4*>(base + off + r * 16) = e;
+        }
+    }
+    __syncthreads();
+}
+
+// Near-edge test of a shifted sum y (see the layout comment); nmask = sign | bits 2..u-1.
+__device__ __forceinline__ uint32_t p1f_nmask(int u) { return 0x80000000u | ((((1u << u) - 1u)) & ~3u); }
+__device__ __forceinline__ bool p1f_near(int32_t y, uint32_t nmask) {
+    return ((uint32_t)y & nmask) == (nmask & 0x7FFFFFFFu);
+}
+
+// FP64 decision for one pixel known to be non-white; adds to the exact bins.
+__device__ __forceinline__ void p1f_exact(P1FLds& S, const P1Params& pp, uint32_t R, uint32_t G, uint32_t Bc,
+                                          uint32_t lh) {
+    double d0, d1;
+    solve64(S.B, od_u8((double)pp.i0[0], (int)R), od_u8((double)pp.i0[1], (int)G), od_u8((double)pp.i0[2], (int)Bc),
+            d0, d1);
+    const double e0 = floor(d0 * (256.0 / (double)pp.hist_hi[0])), e1 = floor(d1 * (256.0 / (double)pp.hist_hi[1]));
+    char* base = reinterpret_cast<char*>(S.mem);
+    atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(e0 >= 255.0 ? 255 : (int)e0, lh)), 1u);
+    atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(e1 >= 255.0 ? 255 : (int)e1, lh) + 64), 1u);
+}
+
+// Fixed-point (shifted) sums of one pixel from its three bytes (cold path and tail).
+__device__ __forceinline__ void p1f_sums(const P1FLds& S, uint32_t R, uint32_t G, uint32_t Bc, uint32_t r16,
+                                         int32_t& x0, int32_t& x1) {
+    const char* base = reinterpret_cast<const char*>(S.mem);
+    const int4 a = *reinterpret_cast<const int4*>(base + ((R << 8) | r16));
+    const int4 b = *reinterpret_cast<const int4*>(base + ((G << 8) | r16) + 128);
+    const int4 c = *reinterpret_cast<const int4*>(base + (kRegion1 | (Bc << 8) | r16));
+    x0 = min(a.x + b.x + c.x, a.y + b.y + c.y);
+    x1 = min(a.z + b.z + c.z, a.w + b.w + c.w);
+}
+
+// Per-lane constants of the byte-permute layout.
+struct P1FLane {
+    uint32_t r16, la, lb, lh, lh1, lz, lz1;
+};
+
+__device__ __forceinline__ P1FLane p1f_lane(int tid) {
+    P1FLane L;
+    L.r16 = (uint32_t)(tid & 7) << 4;
+    L.la = L.r16;
+    L.lb = kRegion1 | L.r16;
+    L.lh = kRegion1 | (kHistOff + ((uint32_t)(tid & 15) << 2));   // stain 0 column word
+    L.lh1 = L.lh + 64u;                                             // stain 1
+    L.lz = kZeroRow + ((uint32_t)(tid & 63) << 2);
+    L.lz1 = L.lz + 256u;
+    return L;
+}
+
+// Counts the non-white pixels among UNROLL units of one thread: unit j is unit lb0 + j * nthreads
+// of a run of cnt units starting at src_run (for the byte-wise re-reads of near-edge pixels).
+template <int UNROLL, bool U16, bool ZROW>
+__device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P1FLane& L, const u32x3 (&cur)[UNROLL],
+                                          int lb0, int cnt, int nthreads, const uint8_t* src_run) {
+    const int u = U16 ? 16 : S.shift;
+    const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
+    const uint32_t nmask = p1f_nmask(u);
+    char* base = reinterpret_cast<char*>(S.mem);
+    auto rd = [&](uint32_t addr) -> int4 { return *reinterpret_cast<const int4*>(base + addr); };
+    // ZROW: bin 0 (and below) -> this lane's zero-row word; otherwise the clamped bin's column word
+    auto bin_addr = [&](int32_t y, uint32_t lh, uint32_t lz) -> uint32_t {
+        if (ZROW) {
+            const uint32_t a = U16 ? __builtin_amdgcn_perm((uint32_t)min(y, 0xFFFFFF), lh, perm_sel(2))
+                                   : p1f_hist_addr(min(y >> u, kHistBins - 1), lh);
+            return y < (1 << u) ? lz : a;
+        }
+        return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
+                   : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
+    };
+    uint64_t near_waves = 0;   // wave-uniform: some lane has a near-edge non-white pixel
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) {
+        const bool valid = lb0 + j * nthreads < cnt;
+        const uint32_t X = cur[j].x, Y = cur[j].y, Z = cur[j].z;
+        // R + G + B of the four pixels (byte dot products)
+        int32_t sum[4];
+        sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
+        sum[1] = (int32_t)__builtin_amdgcn_udot4(Y, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
+        sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y, 0x01010000u, 0u, false), false);
+        sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
+        bool tis[4];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            tis[q] = valid && sum[q] < thr;
+            any |= tis[q];
+        }
+        if (any) {
+            // table addresses: (word holding the byte, byte position) per pixel and channel
+            const uint32_t aR[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(0)), __builtin_amdgcn_perm(X, L.la, perm_sel(3)),
+                                    __builtin_amdgcn_perm(Y, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
+            const uint32_t aG[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(1)), __builtin_amdgcn_perm(Y, L.la, perm_sel(0)),
+                                    __builtin_amdgcn_perm(Y, L.la, perm_sel(3)), __builtin_amdgcn_perm(Z, L.la, perm_sel(2))};
+            const uint32_t aB[4] = {__builtin_amdgcn_perm(X, L.lb, perm_sel(2)), __builtin_amdgcn_perm(Y, L.lb, perm_sel(1)),
+                                    __builtin_amdgcn_perm(Z, L.lb, perm_sel(0)), __builtin_amdgcn_perm(Z, L.lb, perm_sel(3))};
+            int32_t y0[4], y1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int4 a = rd(aR[q]), b = rd(aG[q] + 128), c = rd(aB[q]);
+                y0[q] = min(a.x + b.x + c.x, a.y + b.y + c.y);
+                y1[q] = min(a.z + b.z + c.z, a.w + b.w + c.w);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool nr = p1f_near(y0[q], nmask) | p1f_near(y1[q], nmask);
+                near_waves |= __ballot(tis[q] & nr);
+                const uint32_t inc = (tis[q] & !nr) ? 1u : 0u;
+                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh, L.lz)), inc);
+                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1, L.lz1)), inc);
+            }
+        }
+    }
+    if (near_waves) {   // rare: settle the near-edge pixels of these units in FP64
+#pragma unroll 1
+        for (int b = 0; b < 4 * UNROLL; ++b) {
+            const int lu = lb0 + (b >> 2) * nthreads;
+            if (lu >= cnt) continue;
+            const uint8_t* p = src_run + 3 * (4 * (int64_t)lu + (b & 3));
+            const uint32_t R = p[0], G = p[1], Bc = p[2];
+            if ((int32_t)(R + G + Bc) >= thr) continue;
+            int32_t y0, y1;
+            p1f_sums(S, R, G, Bc, L.r16, y0, y1);
+            if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
+        }
+    }
+}
+
+// Grid-stride form: the image's units form tiles of nthreads * UNROLL units; workgroup b takes tiles
+// b, b + gridDim.x, ... so that the whole grid sweeps the image front to back together.
+template <int UNROLL, bool U16, bool ZROW>
+__device__ void p1f_tiles(P1FLds& S, const P1Params& pp, const uint8_t* src, int64_t n_units, int tid, int nthreads) {
+    const P1FLane L = p1f_lane(tid);
+    const int64_t tu = (int64_t)nthreads * UNROLL;
+    const int64_t n_tiles = (n_units + tu - 1) / tu;
+    int64_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    auto tile_rs = [&](int64_t tt) {   // one descriptor built from selected fields (stays scalar)
+        const bool in = tt < n_tiles;
+        return chunk_rsrc(src, in ? tt * tu : 0, in ? min(tu, n_units - tt * tu) : 0);
+    };
+    __amdgpu_buffer_rsrc_t rs = tile_rs(t);
+    u32x3 cur[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (; t < n_tiles; t += gridDim.x) {
+        const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x);   // empty past the end: loads return zeros
+        u32x3 nxt[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
+        const int cnt = (int)min(tu, n_units - t * tu);
+        p1f_units<UNROLL, U16, ZROW>(S, pp, L, cur, tid, cnt, nthreads, src + 12 * t * tu);
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+    }
+}
+
+// Tail pixels (fewer than 4 after the last full unit) counted by one thread.
+__device__ void p1f_tail(P1FLds& S, const P1Params& pp, const uint8_t* px, int n) {
+    const int u = S.shift;
+    const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
+    const uint32_t nmask = p1f_nmask(u);
+    const int tid = threadIdx.x;
+    const uint32_t r16 = (uint32_t)(tid & 7) << 4;
+    const uint32_t lh = kRegion1 | (kHistOff + ((uint32_t)(tid & 15) << 2));
+    char* base = reinterpret_cast<char*>(S.mem);
+    for (int i = 0; i < n; ++i) {
+        const uint32_t R = px[3 * i], G = px[3 * i + 1], Bc = px[3 * i + 2];
+        if ((int32_t)(R + G + Bc) >= thr) continue;
+        int32_t y0, y1;
+        p1f_sums(S, R, G, Bc, r16, y0, y1);
+        if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) {
+            p1f_exact(S, pp, R, G, Bc, lh);
+        } else {
+            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(min(max(y0 >> u, 0), kHistBins - 1), lh)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(min(max(y1 >> u, 0), kHistBins - 1), lh) + 64), 1u);
+        }
+    }
+}
+
+// Adds the workgroup's LDS histogram to a global [2][256] uint64 histogram (barrier before).
+__device__ void p1f_merge(P1FLds& S, unsigned long long* ghist) {
+    __syncthreads();
+    const uint32_t* words = reinterpret_cast<const uint32_t*>(S.mem);
+    for (int t = threadIdx.x; t < 2 * kHistBins; t += blockDim.x) {
+        const int j = t >> 8, k = t & (kHistBins - 1);
+        const uint32_t* row = words + (kRegion1 + (uint32_t)k * 256u + kHistOff + (uint32_t)j * 64u) / 4;
+        uint32_t sum = 0;
+        for (int l = 0; l < 16; ++l) sum += row[(l + t) & 15];   // rotated: no bank conflicts
+        if (k == 0)
+            for (int l = 0; l < 64; ++l) sum += S.zero[j][l];
         if (sum) atomicAdd(ghist + t, (unsigned long long)sum);
     }
 }
@@ -407,6 +674,44 @@ __device__ void p2_chunk(const P2Lds<COPIES>& T, const RecolourConsts& K, __amdg
 #pragma unroll
             for (int q = 0; q < 4; ++q) p2_densities(T, roff, K, px[q][0], px[q][1], px[q][2], h0[q], h1[q]);
             __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (lb + j * nthreads), 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+    }
+}
+
+// Grid-stride form of pass 2 (tiles of nthreads * UNROLL units, workgroup b takes tiles b,
+// b + gridDim.x, ...).
+template <int COPIES, int UNROLL>
+__device__ void p2_tiles(const P2Lds<COPIES>& T, const RecolourConsts& K, const uint8_t* src, uint8_t* out,
+                         int64_t n_units, int tid, int nthreads) {
+    const uint32_t roff = (uint32_t)((tid & 63) & (COPIES - 1)) << 3;
+    const int64_t tu = (int64_t)nthreads * UNROLL;
+    const int64_t n_tiles = (n_units + tu - 1) / tu;
+    int64_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    auto tile_rs = [&](const uint8_t* base, int64_t tt) {   // one descriptor from selected fields
+        const bool in = tt < n_tiles;
+        return chunk_rsrc(base, in ? tt * tu : 0, in ? min(tu, n_units - tt * tu) : 0);
+    };
+    const __amdgpu_buffer_rsrc_t rs0 = tile_rs(src, t);
+    u32x3 cur[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs0, 12 * (tid + j * nthreads), 0, 0);
+    for (; t < n_tiles; t += gridDim.x) {
+        const __amdgpu_buffer_rsrc_t rn = tile_rs(src, t + gridDim.x);   // empty past the end
+        u32x3 nxt[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
+        const __amdgpu_buffer_rsrc_t ws = tile_rs(out, t);
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) {
+            uint32_t px[4][3];
+            bytes_of_unit(cur[j], px);
+            float h0[4], h1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) p2_densities(T, roff, K, px[q][0], px[q][1], px[q][2], h0[q], h1[q]);
+            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (tid + j * nthreads), 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];

@@ -105,12 +105,10 @@ struct P2Args {
     int32_t* flags_out;
 };
 
-template <int COPIES, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_pass2(const P2Args a) {
-    __shared__ P2Lds<COPIES> T;
-    __shared__ FinalShared F;
-    __shared__ Basis64 B;
-    __shared__ RecolourConsts K;
+// Prologue of every pass-2 workgroup: tables, percentile and recolouring constants (block 0 also
+// writes the statistics).  Ends with a barrier.
+template <int COPIES>
+__device__ void p2_prologue(const P2Args& a, P2Lds<COPIES>& T, FinalShared& F, Basis64& B, RecolourConsts& K) {
     if (threadIdx.x == 0) derive_basis(a.w_src, a.lambda, B);
     __syncthreads();
     p2_tables(T, B, a.i0);
@@ -132,6 +130,15 @@ __global__ __launch_bounds__(THREADS) void k_pass2(const P2Args a) {
         }
     }
     __syncthreads();
+}
+
+template <int COPIES, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_pass2(const P2Args a) {
+    __shared__ P2Lds<COPIES> T;
+    __shared__ FinalShared F;
+    __shared__ Basis64 B;
+    __shared__ RecolourConsts K;
+    p2_prologue(a, T, F, B, K);
     const RecolourConsts Kr = K;
     const int64_t n_units = a.n_px >> 2;
     const int64_t per = (n_units + gridDim.x - 1) / gridDim.x;
@@ -143,6 +150,36 @@ __global__ __launch_bounds__(THREADS) void k_pass2(const P2Args a) {
         p2_tail(T, Kr, a.src + 12 * n_units, a.out + 12 * n_units, (int)(a.n_px - 4 * n_units));
 }
 
+// Grid-stride pass 2 (the grid sweeps the image front to back together).
+template <int COPIES, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_pass2g(const P2Args a) {
+    __shared__ P2Lds<COPIES> T;
+    __shared__ FinalShared F;
+    __shared__ Basis64 B;
+    __shared__ RecolourConsts K;
+    p2_prologue(a, T, F, B, K);
+    const RecolourConsts Kr = K;
+    const int64_t n_units = a.n_px >> 2;
+    p2_tiles<COPIES, P2_UNROLL>(T, Kr, a.src, a.out, n_units, threadIdx.x, THREADS);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        p2_tail(T, Kr, a.src + 12 * n_units, a.out + 12 * n_units, (int)(a.n_px - 4 * n_units));
+}
+
+// Grid-stride pass 1 with the byte-permute layout (see p1f_units); same counts as k_pass1.
+template <int UNROLL, bool ZROW>
+__global__ __launch_bounds__(P1_THREADS, 4) void k_pass1g(const P1Args a) {
+    __shared__ P1FLds S;
+    p1f_setup(S, a.w, a.pp, true);
+    const int64_t n_units = a.n_px >> 2;
+    if (S.shift == 16)
+        p1f_tiles<UNROLL, true, ZROW>(S, a.pp, a.src, n_units, threadIdx.x, P1_THREADS);
+    else
+        p1f_tiles<UNROLL, false, ZROW>(S, a.pp, a.src, n_units, threadIdx.x, P1_THREADS);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        p1f_tail(S, a.pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
+    p1f_merge(S, a.hist);
+}
+
 template <int COPIES, int COLS, int UNROLL, int WAVES>
 hipError_t run_pass1(const P1Args& a, const DevInfo& dev, hipStream_t s) {
     int64_t units = a.n_px >> 2;
@@ -150,6 +187,23 @@ hipError_t run_pass1(const P1Args& a, const DevInfo& dev, hipStream_t s) {
     int64_t cap = (int64_t)dev.cus * (WAVES / 4);
     int grid = (int)(want < 1 ? 1 : (want < cap ? want : cap));
     hipLaunchKernelGGL((k_pass1<COPIES, COLS, UNROLL, WAVES>), dim3(grid), dim3(P1_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int UNROLL, bool ZROW>
+hipError_t run_pass1g(const P1Args& a, const DevInfo& dev, hipStream_t s) {
+    int64_t tiles = ((a.n_px >> 2) + (int64_t)P1_THREADS * UNROLL - 1) / ((int64_t)P1_THREADS * UNROLL);
+    int grid = (int)(tiles < 1 ? 1 : (tiles < dev.cus ? tiles : dev.cus));
+    hipLaunchKernelGGL((k_pass1g<UNROLL, ZROW>), dim3(grid), dim3(P1_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int COPIES, int THREADS>
+hipError_t run_pass2g(const P2Args& a, int blocks_per_cu, const DevInfo& dev, hipStream_t s) {
+    int64_t tiles = ((a.n_px >> 2) + (int64_t)THREADS * P2_UNROLL - 1) / ((int64_t)THREADS * P2_UNROLL);
+    int64_t cap = (int64_t)dev.cus * blocks_per_cu;
+    int grid = (int)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
+    hipLaunchKernelGGL((k_pass2g<COPIES, THREADS>), dim3(grid), dim3(THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -183,7 +237,11 @@ static hipError_t launch_pass1(const uint8_t* img, int64_t n_px, const float* w,
         case 2: return run_pass1<4, 32, 4, 4>(a, dev, s);
         case 3: return run_pass1<8, 16, 4, 4>(a, dev, s);
         case 4: return run_pass1<1, 32, 2, 8>(a, dev, s);
-        default: return run_pass1<2, 16, 2, 8>(a, dev, s);
+        case 5: return run_pass1<2, 16, 2, 8>(a, dev, s);
+        case 6: return run_pass1g<4, false>(a, dev, s);
+        case 7: return run_pass1g<2, false>(a, dev, s);
+        case 8: return run_pass1g<4, true>(a, dev, s);
+        default: return run_pass1g<2, true>(a, dev, s);
     }
 }
 
@@ -219,7 +277,10 @@ hipError_t launch_recolor(const uint8_t* src, int64_t n_px, const float* w_src, 
     switch (option(SPCN_OPT_P2_VARIANT)) {
         case 0: return run_pass2<1, 256>(b, bpc, dev, s);
         case 1: return run_pass2<4, 256>(b, bpc, dev, s);
-        default: return run_pass2<16, 1024>(b, 1, dev, s);
+        case 2: return run_pass2<16, 1024>(b, 1, dev, s);
+        case 3: return run_pass2g<1, 256>(b, bpc, dev, s);
+        case 4: return run_pass2g<1, 512>(b, bpc, dev, s);
+        default: return run_pass2g<16, 1024>(b, 1, dev, s);
     }
 }
 

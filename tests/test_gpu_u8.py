@@ -235,8 +235,8 @@ def test_kernel_variants_identical(S, orc):
     saved = [S.get_option(o) for o in range(4)]
     ref = None
     try:
-        for v1 in range(6):
-            for v2, bpc in ((0, 8), (1, 4), (2, 1), (0, 2)):
+        for v1 in range(10):
+            for v2, bpc in ((0, 8), (1, 4), (2, 1), (0, 2), (3, 2), (4, 1), (5, 1)):
                 S.set_option(S.OPT_P1_VARIANT, v1)
                 S.set_option(S.OPT_P2_VARIANT, v2)
                 S.set_option(S.OPT_P2_BLOCKS_PER_CU, bpc)
@@ -256,6 +256,6 @@ def test_kernel_variants_identical(S, orc):
 
 def test_option_validation(S):
     import ctypes
-    assert S._L.spcn_set_option(0, 9) == S.SPCN_E_ARG
+    assert S._L.spcn_set_option(0, 10) == S.SPCN_E_ARG
     assert S._L.spcn_set_option(7, 0) == S.SPCN_E_ARG
     assert S.get_option(7) == -1
