@@ -73,6 +73,37 @@ def cpu_baseline(img_dev, W_src, W_tgt, scale_tgt, min_seconds: float = 10.0, ba
                       f"full normalisation per band, {t_total:.1f} s"}
 
 
+P1_KERNELS = ["k_pass1<1, 64, 4, 4>", "k_pass1<2, 64, 4, 4>", "k_pass1<4, 32, 4, 4>", "k_pass1<8, 16, 4, 4>",
+              "k_pass1<1, 32, 2, 8>", "k_pass1<2, 16, 2, 8>", "k_pass1g<4, false>", "k_pass1g<2, false>",
+              "k_pass1g<4, true>", "k_pass1g<2, true>"]
+P2_KERNELS = ["k_pass2<1, 256>", "k_pass2<4, 256>", "k_pass2<16, 1024>", "k_pass2g<1, 256>", "k_pass2g<1, 512>",
+              "k_pass2g<16, 1024>"]
+TRAFFIC_SOURCES = ["paper_1901_03088_amd/csrc/spcn_passes.hpp", "paper_1901_03088_amd/csrc/spcn_u8.hip",
+                   "paper_1901_03088_amd/csrc/spcn_device.hpp", "paper_1901_03088_amd/csrc/spcn_internal.h"]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (rocprofv3 FETCH_SIZE /
+    WRITE_SIZE, calibrated), or None if the summary is for other sources, another workload or
+    lacks this kernel."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if workload != "gigapixel_slide" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get("kernels", {}).get(kernel)
+    if not rec or rec.get("write_bytes") is None:
+        return None
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return round(rec["read_bytes"] + rec["write_bytes"])
+
+
 def timed(fn, steps, warmup, stream):
     """Mean ms of fn() over `steps` runs bracketed by events on `stream` (after `warmup` runs)."""
     import numpy as np
@@ -256,7 +287,9 @@ def main() -> int:
         f"basis {pbm:.3f} ms, pass1 {p1m:.3f} ms, pass2 {p2m:.3f} ms")
 
     # roofline of the dominant kernel (algorithmic bytes: 3 B/px read in pass 1; 3 read + 3 written in pass 2)
-    k_name, k_ms, k_bytes = ("pass2_recolor", p2m, 6.0 * n_px) if p2m >= p1m else ("pass1_histogram", p1m, 3.0 * n_px)
+    k1 = P1_KERNELS[S.get_option(S.OPT_P1_VARIANT)]
+    k2 = P2_KERNELS[S.get_option(S.OPT_P2_VARIANT)]
+    k_name, k_ms, k_bytes = (k2, p2m, 6.0 * n_px) if p2m >= p1m else (k1, p1m, 3.0 * n_px)
     achieved = k_bytes / (k_ms / 1e3) / 1e9
     norm_ms = p1m + p2m
     path_gbs = 9.0 * n_px / (norm_ms / 1e3) / 1e9
@@ -266,7 +299,9 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, pixels=n_px, background_frac=0.6, lambda_density=0.01, io="uint8 RGB HWC"),
         "roofline": {"bound": "hbm", "kernel": k_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(k_name, desc["workload"]),
+                     "algorithmic_bytes": round(k_bytes)},
         "autotune": tuned["options"],
         "path": {"basis_fit_ms": round(pbm, 4), "pass1_ms": round(p1m, 4), "pass2_ms": round(p2m, 4),
                  "normalize_ms": round(norm_ms, 4), "normalize_Mpx_s": round(n_px / norm_ms / 1e3, 1),
