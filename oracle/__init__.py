@@ -57,6 +57,8 @@ def lib():
         L.orc_splitmix64.restype = C.c_uint64; L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_sample_tissue.restype = C.c_int64
         L.orc_sample_tissue.argtypes = [_u8, C.c_int64, C.c_int, C.c_uint64, C.c_int64, C.c_int64, _i64]
+        L.orc_estimate_i0.restype = C.c_int64
+        L.orc_estimate_i0.argtypes = [_u8, C.c_int64, C.c_int, C.c_uint64, C.c_int64, C.c_int64, C.c_double, _d]
         L.orc_nmf_objective.restype = C.c_double
         L.orc_nmf_objective.argtypes = [_d, _d, C.c_int64, _d, C.c_double]
         L.orc_nmf.restype = None
@@ -202,6 +204,16 @@ def target_scale(tgt, W_tgt, i0=(255, 255, 255), lam=0.01, white_sum=660, percen
 
 def splitmix64(seed, t) -> int:
     return int(lib().orc_splitmix64(C.c_uint64(seed & (2**64 - 1)), C.c_uint64(t)))
+
+
+def estimate_i0(img, n_s=100000, seed=0, white_sum=660, percentile=80.0, max_cand=None, default=(255.0, 255.0, 255.0)):
+    """Channel-wise background intensity (Sec. 3.1 item 1).  Returns (i0 (3,) float64, kept)."""
+    a = _img(img); n = a.shape[0]
+    max_cand = 64 * n_s if max_cand is None else max_cand
+    i0 = np.array(default, dtype=np.float64)
+    k = lib().orc_estimate_i0(_p(a, _u8), n, int(white_sum), C.c_uint64(seed & (2**64 - 1)), int(n_s),
+                              int(max_cand), q_of(percentile), _p(i0, _d))
+    return i0, int(k)
 
 
 def sample_tissue(img, n_s, seed, white_sum=660, max_cand=None):

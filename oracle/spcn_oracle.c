@@ -258,6 +258,38 @@ int64_t orc_sample_tissue(const uint8_t* img, int64_t n_px, int white_sum, uint6
     return kept;
 }
 
+static int cmp_int(const void* a, const void* b) {
+    int x = *(const int*)a, y = *(const int*)b;
+    return (x > y) - (x < y);
+}
+
+int64_t orc_estimate_i0(const uint8_t* img, int64_t n_px, int white_sum, uint64_t seed, int64_t n_s,
+                        int64_t max_cand, double q, double i0_out[3]) {
+    int* vals[3];
+    for (int c = 0; c < 3; ++c) vals[c] = (int*)malloc(sizeof(int) * (size_t)(n_s > 0 ? n_s : 1));
+    int64_t kept = 0;
+    for (int64_t t = 0; t < max_cand && kept < n_s; ++t) {
+        uint64_t r = orc_splitmix64(seed, (uint64_t)t);
+        int64_t i = (int64_t)(((unsigned __int128)r * (unsigned __int128)(uint64_t)n_px) >> 64);
+        const uint8_t* p = img + 3 * i;
+        if ((int)p[0] + (int)p[1] + (int)p[2] > white_sum) {
+            for (int c = 0; c < 3; ++c) vals[c][kept] = p[c];
+            ++kept;
+        }
+    }
+    if (kept > 0) {
+        int64_t k = (int64_t)ceil(q * (double)kept);
+        if (k < 1) k = 1;
+        if (k > kept) k = kept;
+        for (int c = 0; c < 3; ++c) {
+            qsort(vals[c], (size_t)kept, sizeof(int), cmp_int);
+            i0_out[c] = (double)vals[c][k - 1];
+        }
+    }
+    for (int c = 0; c < 3; ++c) free(vals[c]);
+    return kept;
+}
+
 double orc_nmf_objective(const double* V, const double* H, int64_t n, const double W[6], double lambda) {
     double f = 0.0;
     for (int64_t i = 0; i < n; ++i) {

@@ -14,8 +14,7 @@
  * plus the paper's fixes on this path: the non-white sample and the non-white percentile
  * (Sec. 3.1 item 2) and the red-minus-blue stain ordering (Sec. 3.1 item 3).
  *
- * Readings where the paper is silent are listed in DESIGN.md ("Readings of the paper") and repeated
- * at each function.  Layouts: images are uint8 interleaved RGB (HWC), n_px pixels, 3*n_px bytes;
+ * Readings where the paper is silent are stated at each function.  Layouts: images are uint8 interleaved RGB (HWC), n_px pixels, 3*n_px bytes;
  * W is 3x2 column-major, W[c + 3*j] (c = R,G,B; j = stain 0 (hematoxylin), 1 (eosin));
  * densities are planar H[j*n + i].
  *
@@ -84,6 +83,16 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t t);
  * kept or max_cand candidates were drawn.  Returns the number kept. */
 int64_t orc_sample_tissue(const uint8_t* img, int64_t n_px, int white_sum, uint64_t seed,
                           int64_t n_s, int64_t max_cand, int64_t* idx_out);
+
+/* Channel-wise background intensity (Sec. 3.1 item 1: the fixed maximum intensity i0 of Eqs. (1)
+ * and (4) replaced by a per-image, per-channel estimate).  Samples pixels whose mean intensity is
+ * above 220 -- R + G + B > white_sum, strict, the complement of the non-white test without the
+ * ties -- in the same SplitMix64 draw order as orc_sample_tissue (first n_s such candidates among at
+ * most max_cand draws), and returns in i0_out[c] the nearest-rank percentile q (0.8 in the paper)
+ * of channel c over the kept pixels: the k-th smallest value with k = max(1, ceil(q n)).  Returns
+ * the number of pixels kept; with none kept, i0_out is left unchanged. */
+int64_t orc_estimate_i0(const uint8_t* img, int64_t n_px, int white_sum, uint64_t seed, int64_t n_s,
+                        int64_t max_cand, double q, double i0_out[3]);
 
 /* Eq. (2) objective ||V - W H||_F^2 + lambda sum(H) over n columns, V is [3][n], H is [2][n]. */
 double orc_nmf_objective(const double* V, const double* H, int64_t n, const double W[6], double lambda);
