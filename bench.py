@@ -320,6 +320,15 @@ def main() -> int:
         del a, b
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img, W_src, tgt["W"], scale_tgt.cpu().numpy(), args.cpu_seconds)
+    if args.extras:
+        # channel-wise background intensity (Sec. 3.1 item 1): 100k background samples of the slide
+        i0_dev = torch.empty(3, dtype=torch.float32, device=dev)
+        ws_i0 = S.workspace(S.workspace_size(S.OP_ESTIMATE_I0, 0, 0, 100000), dev)
+        ms_i0 = timed(lambda: S.spcn_estimate_i0(img, 100000, seed=7, i0_out=i0_dev, ws=ws_i0), args.steps,
+                      args.warmup, stream)
+        res.setdefault("extras", {})["i0_estimate"] = {"samples": 100000, "ms": round(ms_i0, 4),
+                                                       "i0": [float(v) for v in i0_dev.cpu()]}
+        log(f"[bench] i0 estimate {res['extras']['i0_estimate']}")
     if args.extras and args.workload == "slide":
         del img, out
         torch.cuda.empty_cache()
@@ -335,7 +344,7 @@ def main() -> int:
             log(f"[bench] fwd_bwd {extras['fwd_bwd']}")
         except Exception as e:
             extras["fwd_bwd"] = {"error": repr(e)}
-        res["extras"] = extras
+        res.setdefault("extras", {}).update(extras)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -58,6 +58,7 @@ typedef enum {
                                    small for the tiles, or a bounded wait expired)                  */
 #define SPCN_FLAG_TIMEOUT  64   /* a bounded device-side wait between workgroups expired: the
                                    results of this call are invalid                                 */
+#define SPCN_FLAG_NO_BACKGROUND 128 /* spcn_estimate_i0 found no background pixel: i0 set to 255    */
 
 #define SPCN_HIST_BINS 256
 
@@ -83,6 +84,7 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_ESTIMATE_BATCHED  4
 #define SPCN_OP_FORWARD_F32       5
 #define SPCN_OP_BACKWARD_F32      6
+#define SPCN_OP_ESTIMATE_I0       7
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
@@ -148,6 +150,23 @@ spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t widt
                                 uint64_t seed, int32_t n_iter, const float* w_init, float* w_out,
                                 float* sample_p99, int32_t* flags_out, void* ws, size_t ws_bytes,
                                 hipStream_t stream);
+
+/* Channel-wise background intensity i0 (Sec. 3.1 item 1: the fixed maximum intensity of Eqs. 1
+ * and 4 replaced by a per-image, per-channel estimate).  Draws pixels with the same counter-based
+ * SplitMix64 stream as spcn_estimate_basis and keeps the first n_samples whose mean intensity is
+ * above 220 (R + G + B > white_sum, strict; at most 64*n_samples candidates), then takes per
+ * channel the nearest-rank `percentile` (80 in the paper) of their values: the k-th smallest with
+ * k = max(1, ceil(percentile/100 * n)).
+ *   n_samples   1 .. 1048576 (the paper uses at most 100000)
+ *   white_sum   1 .. 765 (660 = mean 220)
+ *   percentile  (0, 100]
+ *   i0_out      device [3] float, written with integer values; 255 if no background pixel is found
+ *   flags_out   device [1] int32 or NULL: SPCN_FLAG_NO_BACKGROUND, SPCN_FLAG_SHORT
+ *   ws          workspace of spcn_workspace_size(SPCN_OP_ESTIMATE_I0, 0, 0, n_samples) bytes
+ * The estimate is fed back as spcn_params.i0 (source, Eq. 1) and i0_out (target's, Eq. 4). */
+spcn_status spcn_estimate_i0(const uint8_t* img, int64_t height, int64_t width, int64_t n_samples,
+                             uint64_t seed, int32_t white_sum, float percentile, float* i0_out,
+                             int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One tile of a batch (device-resident descriptor array). */
 typedef struct {

@@ -24,9 +24,10 @@ _L = C.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ ABI mirror
 
 SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
-FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT = 1, 2, 4, 8, 16, 32, 64
+FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT, FLAG_NO_BACKGROUND = \
+    1, 2, 4, 8, 16, 32, 64, 128
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
-    OP_FORWARD_F32, OP_BACKWARD_F32 = range(7)
+    OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0 = range(8)
 HIST_BINS = 256
 OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
@@ -59,6 +60,7 @@ _SIGS = {
                                       _vp]),
     "spcn_estimate_basis_batched": (C.c_int, [_vp, _i32, _i64, _P, _f, _i64, _u64, _i32, _vp, _vp, _vp, _vp,
                                               _vp, _sz, _vp]),
+    "spcn_estimate_i0": (C.c_int, [_vp, _i64, _i64, _i64, _u64, _i32, _f, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_batched": (C.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_f32": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -244,6 +246,23 @@ def spcn_estimate_basis(img: torch.Tensor, n_samples: int, seed: int, p: spcn_pa
                                   int(seed) & (2 ** 64 - 1), int(n_iter), _ptr(w_init), _ptr(w_out), _ptr(sp),
                                   _ptr(flags), wsp, wsn, _stream()), "spcn_estimate_basis")
     return w_out, sp, flags
+
+
+def spcn_estimate_i0(img: torch.Tensor, n_samples: int = 100000, seed: int = 0, white_sum: int = 660,
+                     percentile: float = 80.0, i0_out=None, ws=None):
+    """Channel-wise background intensity of a uint8 (H, W, 3) image (Sec. 3.1 item 1).  Returns
+    (i0 [3] float32 on the device, flags [1] int32).  Feed it back as params(i0=...) / i0_out."""
+    _dev(img, torch.uint8, "img")
+    H, W_ = int(img.shape[0]), int(img.shape[1])
+    dev = img.device
+    i0_out = i0_out if i0_out is not None else torch.empty(3, dtype=torch.float32, device=dev)
+    flags = torch.empty(1, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(workspace_size(OP_ESTIMATE_I0, 0, 0, n_samples), dev)
+    wsp, wsn = _ws_ptr(ws)
+    _check(_L.spcn_estimate_i0(_ptr(img), H, W_, int(n_samples), C.c_uint64(seed & (2**64 - 1)), int(white_sum),
+                               float(percentile), _ptr(i0_out), _ptr(flags), wsp, wsn, _stream()), "spcn_estimate_i0")
+    return i0_out, flags
 
 
 def tile_table(srcs, outs=None) -> torch.Tensor:

@@ -148,6 +148,8 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
             return f32_forward_workspace_bytes(n_px, n_items);
         case SPCN_OP_BACKWARD_F32:
             return f32_backward_workspace_bytes(n_px, n_items);
+        case SPCN_OP_ESTIMATE_I0:
+            return n_samples <= kMaxI0Samples ? i0_workspace_bytes(n_samples) : 0;
         default:
             return 0;
     }
@@ -247,6 +249,23 @@ spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t widt
     hipError_t e = launch_estimate_basis(img, height * width, make_params(p), lambda_nmf, n_samples, seed, n_iter,
                                          w_init, w_out, sample_p99, flags_out, ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_estimate_basis launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_estimate_i0(const uint8_t* img, int64_t height, int64_t width, int64_t n_samples, uint64_t seed,
+                             int32_t white_sum, float percentile, float* i0_out, int32_t* flags_out, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_image(img, height, width, "img"));
+    if (n_samples < 1 || n_samples > kMaxI0Samples)
+        return fail(SPCN_E_ARG, "n_samples = %lld must lie in [1, %lld]", (long long)n_samples, (long long)kMaxI0Samples);
+    if (white_sum < 1 || white_sum > 765) return fail(SPCN_E_ARG, "white_sum = %d must lie in [1, 765]", (int)white_sum);
+    if (!(percentile > 0.0f && percentile <= 100.0f))
+        return fail(SPCN_E_ARG, "percentile = %g must lie in (0, 100]", (double)percentile);
+    if (!i0_out) return fail(SPCN_E_ARG, "i0_out is NULL");
+    SPCN_CHECK(check_ws(ws, ws_bytes, i0_workspace_bytes(n_samples)));
+    hipError_t e = launch_estimate_i0(img, height * width, white_sum, n_samples, seed, (double)percentile / 100.0,
+                                      i0_out, flags_out, ws, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_estimate_i0 launch");
     return SPCN_OK;
 }
 

@@ -228,6 +228,7 @@ struct BasisWork {          // layout of the caller's workspace (single image)
 
 struct SampleArgs {
     const uint8_t* img; int64_t n_px; int32_t white_sum; uint64_t seed;
+    int32_t background;     // keep pixels with R + G + B > white_sum instead of non-white ones
     int64_t t0, t_end;      // candidates [t0, t_end) form this round
     int64_t nb;             // workgroups in this round
     BasisWork* bw;
@@ -244,7 +245,12 @@ __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_round(SampleArgs a) {
     int64_t pix = 0;
     if (t < a.t_end) {
         pix = candidate_pixel(a.seed, (uint64_t)t, a.n_px);
-        keep = non_white(a.img, pix, a.white_sum);
+        if (a.background) {
+            const uint8_t* q = a.img + 3 * pix;
+            keep = (int32_t)q[0] + (int32_t)q[1] + (int32_t)q[2] > a.white_sum;
+        } else {
+            keep = non_white(a.img, pix, a.white_sum);
+        }
     }
     int total;
     int r = block_rank(keep, s_wave, &total);
@@ -648,7 +654,7 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
-        SampleArgs a{img, n_px, pk.white_sum, seed, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
+        SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
                      counts, idx};
         hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
@@ -663,6 +669,76 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     if (n_iter > 0) hipLaunchKernelGGL(k_nmf_fit, dim3(nblk), dim3(FIT_THREADS), 0, s, fa);
     hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(1024), 0, s, bw, (const double*)V, (double)lambda_nmf, pk.q64,
                        w_out, sample_p99, flags_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- channel-wise background intensity
+
+// Nearest-rank percentile of each channel over the sampled background pixels (one workgroup):
+// k = max(1, ceil(q n)) in FP64, the smallest value whose cumulative count reaches k.
+__global__ __launch_bounds__(1024) void k_i0_select(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
+                                                    double q, float* i0_out, int32_t* flags_out) {
+    __shared__ uint32_t s_hist[3][kHistBins];
+    __shared__ uint32_t s_cum[3][kHistBins];
+    const int t = threadIdx.x;
+    for (int i = t; i < 3 * kHistBins; i += blockDim.x) s_hist[i / kHistBins][i % kHistBins] = 0u;
+    __syncthreads();
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        const uint8_t* p = img + 3 * idx[i];
+        atomicAdd(&s_hist[0][p[0]], 1u);
+        atomicAdd(&s_hist[1][p[1]], 1u);
+        atomicAdd(&s_hist[2][p[2]], 1u);
+    }
+    __syncthreads();
+    if (t < 3) {   // 3 x 256 serial prefix sums: negligible next to the sampling
+        uint32_t run = 0;
+        for (int k = 0; k < kHistBins; ++k) { run += s_hist[t][k]; s_cum[t][k] = run; }
+    }
+    __syncthreads();
+    if (n > 0) {
+        int64_t k = (int64_t)ceil(q * (double)n);
+        k = k < 1 ? 1 : (k > n ? n : k);
+        if (t < 3 * kHistBins) {
+            const int c = t / kHistBins, v = t % kHistBins;
+            if ((int64_t)s_cum[c][v] >= k && (v == 0 || (int64_t)s_cum[c][v - 1] < k)) i0_out[c] = (float)v;
+        }
+    } else if (t < 3) {
+        i0_out[t] = 255.0f;
+    }
+    if (flags_out && t == 0)
+        flags_out[0] = (n == 0 ? SPCN_FLAG_NO_BACKGROUND : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
+}
+
+size_t i0_workspace_bytes(int64_t n_s) {
+    if (n_s <= 0) return 0;
+    const int64_t nb = max_round_blocks(n_s);
+    return align256(sizeof(BasisWork)) + align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t)) +
+           align256((size_t)(nb + 1) * sizeof(int32_t)) + align256((size_t)n_s * sizeof(int64_t));
+}
+
+hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
+                              double q, float* i0_out, int32_t* flags_out, void* ws, hipStream_t s) {
+    uint8_t* p = static_cast<uint8_t*>(ws);
+    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
+    const int64_t nbmax = max_round_blocks(n_s);
+    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
+    int64_t* idx = reinterpret_cast<int64_t*>(p);
+    const int64_t max_cand = 64 * n_s;
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr);
+    int64_t t0 = 0;
+    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
+        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
+        SampleArgs a{img, n_px, white_sum, seed, 1, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
+                     counts, idx};
+        hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        t0 += rc;
+    }
+    hipLaunchKernelGGL(k_i0_select, dim3(1), dim3(1024), 0, s, img, (const int64_t*)idx, (const BasisWork*)bw, q,
+                       i0_out, flags_out);
     return hipGetLastError();
 }
 

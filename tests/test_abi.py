@@ -124,3 +124,27 @@ def test_options_ranges(lib):
     finally:
         for o, v in enumerate(saved):
             lib.set_option(o, v)
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(n=0), "n_samples"),
+    (dict(n=(1 << 20) + 1), "n_samples"),
+    (dict(white=0), "white_sum"),
+    (dict(white=766), "white_sum"),
+    (dict(q=0.0), "percentile"),
+    (dict(q=100.5), "percentile"),
+    (dict(out=None), "i0_out is NULL"),
+    (dict(wsn=16), "workspace"),
+])
+def test_estimate_i0_rejects(lib, kw, frag):
+    a = dict(n=1000, white=660, q=80.0, out=C.c_void_p(1 << 24), wsn=1 << 26)
+    a.update(kw)
+    st = lib._L.spcn_estimate_i0(C.c_void_p(1 << 20), 16, 16, a["n"], C.c_uint64(1), a["white"], a["q"], a["out"],
+                                 None, C.c_void_p(1 << 28), a["wsn"], None)
+    assert st in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
+    assert frag in lib._L.spcn_last_error().decode()
+
+
+def test_estimate_i0_workspace_size(lib):
+    assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, 100000) > 100000 * 8
+    assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, (1 << 20) + 1) == 0
