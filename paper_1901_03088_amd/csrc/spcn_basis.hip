@@ -66,13 +66,41 @@ __device__ int block_rank(bool pred, int* s_wave, int* total) {
     return off + below;
 }
 
-// Sums of N values over the workgroup (wavefront butterflies, then the waves in order); the
-// totals land in out[0..N) (shared) for every thread.  Fixed association: deterministic.
+// One DPP lane exchange of a double (both halves moved by the same control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of a double over the 64 lanes of a wavefront, in a fixed order, returned to every lane:
+// butterflies inside each row of 16 lanes with DPP (quad xor 1, quad xor 2, half-row mirror, row
+// mirror: each pairs two disjoint groups that already hold their partial sums), then the four row
+// sums read from lanes 0, 16, 32, 48.  No LDS traffic.
+__device__ __forceinline__ double wave_sum_d(double x) {
+    x += dpp_d<0xB1>(x);     // quad_perm [1,0,3,2]
+    x += dpp_d<0x4E>(x);     // quad_perm [2,3,0,1]
+    x += dpp_d<0x141>(x);    // row_half_mirror
+    x += dpp_d<0x140>(x);    // row_mirror
+    const double r0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 0),
+                                       __builtin_amdgcn_readlane(__double2loint(x), 0));
+    const double r1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 16),
+                                       __builtin_amdgcn_readlane(__double2loint(x), 16));
+    const double r2 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 32),
+                                       __builtin_amdgcn_readlane(__double2loint(x), 32));
+    const double r3 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 48),
+                                       __builtin_amdgcn_readlane(__double2loint(x), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+// Sums of N values over the workgroup (wavefront DPP sums, then the waves in order); the totals
+// land in out[0..N) (shared) for every thread.  Fixed association: deterministic.  Requires all
+// lanes of every wavefront active.
 template <int N>
 __device__ inline void block_sums(double (&v)[N], double* s_red, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int q = 0; q < N; ++q)
-        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+    for (int q = 0; q < N; ++q) v[q] = wave_sum_d(v[q]);
     if (lane == 0)
         for (int q = 0; q < N; ++q) s_red[q * 16 + wave] = v[q];
     __syncthreads();
@@ -346,10 +374,10 @@ __global__ __launch_bounds__(256) void k_od_gather(const uint8_t* img, const int
 constexpr int FIT_THREADS = 512;
 constexpr int FIT_SPT = 8;
 constexpr int FIT_PER_BLOCK = FIT_THREADS * FIT_SPT;
-constexpr int FIT_MAX_BLOCKS = 64;               // kMaxBasisSamples / FIT_PER_BLOCK
+constexpr int FIT_MAX_BLOCKS = 64;               // kMaxBasisSamples / FIT_PER_BLOCK (one wavefront)
 constexpr uint32_t FIT_SPIN_LIMIT = 1u << 20;
 static_assert(FIT_MAX_BLOCKS * FIT_PER_BLOCK >= kMaxBasisSamples, "fit grid must cover every sample");
-static_assert(FIT_MAX_BLOCKS <= FIT_THREADS, "one partial row per thread in the reduction");
+static_assert(FIT_MAX_BLOCKS <= 64, "one partial row per lane of the reducing wavefront");
 
 struct FitArgs {
     BasisWork* bw;
@@ -415,11 +443,16 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
         }
         __syncthreads();
         if (s_abort) return;
-        double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (threadIdx.x < nblk)
-            for (int q = 0; q < 9; ++q)
-                tot[q] = __hip_atomic_load(part + threadIdx.x * 9 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        block_sums(tot, s_red, s_sum);
+        if (threadIdx.x < 64) {   // one wavefront reduces the (at most 64) partial rows
+            double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (threadIdx.x < nblk)
+                for (int q = 0; q < 9; ++q)
+                    tot[q] = __hip_atomic_load(part + threadIdx.x * 9 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < 9; ++q) tot[q] = wave_sum_d(tot[q]);
+            if (threadIdx.x == 0)
+                for (int q = 0; q < 9; ++q) s_sum[q] = tot[q];
+        }
+        __syncthreads();
         double sums[9];
         for (int q = 0; q < 9; ++q) sums[q] = s_sum[q];
         w_step(W, sums);           // every thread of every workgroup: the same update on the same sums
