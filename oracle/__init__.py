@@ -57,6 +57,14 @@ def lib():
         L.orc_splitmix64.restype = C.c_uint64; L.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.orc_sample_tissue.restype = C.c_int64
         L.orc_sample_tissue.argtypes = [_u8, C.c_int64, C.c_int, C.c_uint64, C.c_int64, C.c_int64, _i64]
+        L.orc_recolor_u8.restype = None
+        L.orc_recolor_u8.argtypes = [_u8, C.c_int64, _d, _d, _d, _d, _d, _d, C.c_double, C.c_int, _u8]
+        L.orc_band_percentiles.restype = C.c_int
+        L.orc_band_percentiles.argtypes = [_u8, C.c_int64, C.c_int64, _d, _d, C.c_double, C.c_int, C.c_double, _d,
+                                           C.c_int, C.c_int64, _d, _i, _d]
+        L.orc_sample_percentile.restype = C.c_int
+        L.orc_sample_percentile.argtypes = [_u8, C.c_int64, _d, _d, C.c_double, C.c_int, C.c_uint64, C.c_int64,
+                                            C.c_int64, C.c_double, _d, _i64]
         L.orc_estimate_i0.restype = C.c_int64
         L.orc_estimate_i0.argtypes = [_u8, C.c_int64, C.c_int, C.c_uint64, C.c_int64, C.c_int64, C.c_double, _d]
         L.orc_nmf_objective.restype = C.c_double
@@ -204,6 +212,42 @@ def target_scale(tgt, W_tgt, i0=(255, 255, 255), lam=0.01, white_sum=660, percen
 
 def splitmix64(seed, t) -> int:
     return int(lib().orc_splitmix64(C.c_uint64(seed & (2**64 - 1)), C.c_uint64(t)))
+
+
+def recolor_u8(src, W_src, W_tgt, scale_tgt, P_src, i0_in=(255, 255, 255), i0_out=(255, 255, 255), lam=0.01,
+               white_sum=660):
+    """Eqs. 3-4 with given source percentiles.  Returns out uint8 of the source's shape."""
+    a = _img(src); n = a.shape[0]
+    out = np.empty_like(a)
+    lib().orc_recolor_u8(_p(a, _u8), n, _p(basis(W_src), _d), _p(basis(W_tgt), _d), _p(_vec(scale_tgt, 2), _d),
+                         _p(_vec(P_src, 2), _d), _p(_vec(i0_in, 3), _d), _p(_vec(i0_out, 3), _d), float(lam),
+                         int(white_sum), _p(out, _u8))
+    return out.reshape(np.asarray(src).shape)
+
+
+def band_percentiles(img, W, band_rows, i0=(255, 255, 255), lam=0.01, white_sum=660, percentile=99.0,
+                     hist_hi=(4.0, 4.0), bins=256):
+    """Median of per-band percentiles.  Returns (median (2,), band_P (n_bands, 2), band_flags, flags)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    Hh, Ww = img.shape[0], img.shape[1]
+    nb = (Hh + band_rows - 1) // band_rows
+    bp = np.zeros((nb, 2)); bf = np.zeros((nb, 2), dtype=np.int32); med = np.zeros(2)
+    f = lib().orc_band_percentiles(_p(img, _u8), Hh, Ww, _p(basis(W), _d), _p(_vec(i0, 3), _d), float(lam),
+                                   int(white_sum), q_of(percentile), _p(_vec(hist_hi, 2), _d), int(bins),
+                                   int(band_rows), _p(bp, _d), _p(bf, _i), _p(med, _d))
+    return med, bp, bf, int(f)
+
+
+def sample_percentile(img, W, n_s, seed, i0=(255, 255, 255), lam=0.01, white_sum=660, percentile=99.0,
+                      max_cand=None):
+    """Percentile of the sub-sampled non-white pixels' densities.  Returns (P (2,), kept, flags)."""
+    a = _img(img); n = a.shape[0]
+    max_cand = 64 * n_s if max_cand is None else max_cand
+    P = np.zeros(2); kept = np.zeros(1, dtype=np.int64)
+    f = lib().orc_sample_percentile(_p(a, _u8), n, _p(basis(W), _d), _p(_vec(i0, 3), _d), float(lam), int(white_sum),
+                                    C.c_uint64(seed & (2**64 - 1)), int(n_s), int(max_cand), q_of(percentile),
+                                    _p(P, _d), _p(kept, _i64))
+    return P, int(kept[0]), int(f)
 
 
 def estimate_i0(img, n_s=100000, seed=0, white_sum=660, percentile=80.0, max_cand=None, default=(255.0, 255.0, 255.0)):

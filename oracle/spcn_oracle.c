@@ -238,6 +238,62 @@ int orc_normalize_u8(const uint8_t* src, int64_t n_px, const double W_src[6], co
     return all;
 }
 
+void orc_recolor_u8(const uint8_t* src, int64_t n_px, const double W_src[6], const double W_tgt[6],
+                    const double scale_tgt[2], const double P_src[2], const double i0_in[3],
+                    const double i0_out[3], double lambda, int white_sum, uint8_t* out) {
+    double* H = (double*)malloc(sizeof(double) * 2 * (size_t)n_px);
+    uint8_t* mask = (uint8_t*)malloc((size_t)n_px);
+    orc_densities_u8(src, n_px, W_src, i0_in, lambda, white_sum, H, mask);
+    double s[2];
+    for (int j = 0; j < 2; ++j) s[j] = stain_scale(scale_tgt[j], P_src[j], ORC_OK);
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n_px; ++i) {
+        double h[2] = {H[i], H[n_px + i]}, y[3];
+        orc_reconstruct_pixel(h, W_tgt, s, i0_out, y);
+        for (int c = 0; c < 3; ++c) {
+            double r = nearbyint(y[c]);
+            r = r < 0.0 ? 0.0 : (r > 255.0 ? 255.0 : r);
+            out[3 * i + c] = (uint8_t)r;
+        }
+    }
+    free(H); free(mask);
+}
+
+int orc_band_percentiles(const uint8_t* img, int64_t height, int64_t width, const double W[6],
+                         const double i0[3], double lambda, int white_sum, double q,
+                         const double hist_hi[2], int bins, int64_t band_rows, double* band_P,
+                         int* band_flags, double median_P[2]) {
+    int64_t n_bands = (height + band_rows - 1) / band_rows;
+    double* P = (double*)malloc(sizeof(double) * 2 * (size_t)n_bands);
+    int* F = (int*)malloc(sizeof(int) * 2 * (size_t)n_bands);
+    uint64_t* hist = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (size_t)bins);
+    for (int64_t b = 0; b < n_bands; ++b) {
+        int64_t r0 = b * band_rows, r1 = r0 + band_rows < height ? r0 + band_rows : height;
+        int64_t n = (r1 - r0) * width;
+        double* H = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+        uint8_t* mask = (uint8_t*)malloc((size_t)n);
+        orc_densities_u8(img + 3 * r0 * width, n, W, i0, lambda, white_sum, H, mask);
+        orc_histogram(H, mask, n, hist_hi, bins, hist);
+        for (int j = 0; j < 2; ++j)
+            F[2 * b + j] = orc_percentile_hist(hist + j * bins, bins, hist_hi[j], q, &P[2 * b + j], NULL);
+        free(H); free(mask);
+    }
+    int flags = ORC_OK;
+    double* vals = (double*)malloc(sizeof(double) * (size_t)n_bands);
+    for (int j = 0; j < 2; ++j) {
+        int64_t m = 0;
+        for (int64_t b = 0; b < n_bands; ++b)
+            if (!(F[2 * b + j] & ORC_NO_TISSUE)) vals[m++] = P[2 * b + j];
+        if (m == 0) { median_P[j] = 0.0; flags |= ORC_NO_TISSUE; continue; }
+        qsort(vals, (size_t)m, sizeof(double), cmp_double);
+        median_P[j] = (m & 1) ? vals[m / 2] : 0.5 * (vals[m / 2 - 1] + vals[m / 2]);
+    }
+    if (band_P) memcpy(band_P, P, sizeof(double) * 2 * (size_t)n_bands);
+    if (band_flags) memcpy(band_flags, F, sizeof(int) * 2 * (size_t)n_bands);
+    free(vals); free(P); free(F); free(hist);
+    return flags;
+}
+
 /* ------------------------------------------- basis estimation, Eq. (2), Sec. 3.1-3.2 ---------- */
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t t) {
@@ -256,6 +312,26 @@ int64_t orc_sample_tissue(const uint8_t* img, int64_t n_px, int white_sum, uint6
         if (orc_is_tissue_u8(img + 3 * i, white_sum)) idx_out[kept++] = i;
     }
     return kept;
+}
+
+int orc_sample_percentile(const uint8_t* img, int64_t n_px, const double W[6], const double i0[3],
+                          double lambda, int white_sum, uint64_t seed, int64_t n_s, int64_t max_cand,
+                          double q, double P[2], int64_t* kept) {
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_s > 0 ? n_s : 1));
+    int64_t n = orc_sample_tissue(img, n_px, white_sum, seed, n_s, max_cand, idx);
+    if (kept) *kept = n;
+    if (n == 0) { P[0] = P[1] = 0.0; free(idx); return ORC_NO_TISSUE; }
+    double* H = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const uint8_t* p = img + 3 * idx[i];
+        double v[3], h[2];
+        for (int c = 0; c < 3; ++c) v[c] = orc_od_u8(i0[c], p[c]);
+        orc_solve_pixel(W, lambda, v, h);
+        H[i] = h[0]; H[n + i] = h[1];
+    }
+    for (int j = 0; j < 2; ++j) orc_percentile_exact(H + j * n, NULL, n, q, &P[j], NULL);
+    free(H); free(idx);
+    return ORC_OK;
 }
 
 static int cmp_int(const void* a, const void* b) {

@@ -71,6 +71,33 @@ int orc_normalize_u8(const uint8_t* src, int64_t n_px, const double W_src[6], co
                      double lambda, int white_sum, double q, const double hist_hi[2], int bins,
                      uint8_t* out, double* stats, uint64_t* hist_out);
 
+/* Eqs. (3)-(4) with the source percentiles given (any percentile mode below): the densities of
+ * every pixel (Eq. 2 with W_src fixed), s_j = scale_tgt_j / P_src_j (1 where P_src_j is not > 0),
+ * Eq. (4), round half to even, clamp.  out: 3*n_px bytes. */
+void orc_recolor_u8(const uint8_t* src, int64_t n_px, const double W_src[6], const double W_tgt[6],
+                    const double scale_tgt[2], const double P_src[2], const double i0_in[3],
+                    const double i0_out[3], double lambda, int white_sum, uint8_t* out);
+
+/* Median of per-patch percentiles (Sec. 3.2 items 3-4: the slide is processed in longitudinal
+ * patches and the percentile of Eq. 3 is the median over patches of each patch's percentile).
+ * Patches are bands of band_rows full rows (the last one shorter); each band's percentile is the
+ * histogram percentile of orc_percentile_hist over its non-white pixels.  The median is taken over
+ * the bands that hold non-white pixels: the middle value, or the mean of the two middle values
+ * for an even count; with no such band it is 0 and ORC_NO_TISSUE is returned.  band_P and
+ * band_flags (optional) receive [n_bands][2] values.  Returns the OR of the median's flags. */
+int orc_band_percentiles(const uint8_t* img, int64_t height, int64_t width, const double W[6],
+                         const double i0[3], double lambda, int white_sum, double q,
+                         const double hist_hi[2], int bins, int64_t band_rows, double* band_P,
+                         int* band_flags, double median_P[2]);
+
+/* Percentile of the sub-sampled non-white pixels (Sec. 3.1 item 2): the densities (Eq. 2, W fixed)
+ * of the first n_s non-white pixels in the draw order of orc_sample_tissue, and per stain their
+ * nearest-rank percentile q.  *kept receives the number of samples; with none, P = 0 and
+ * ORC_NO_TISSUE is returned. */
+int orc_sample_percentile(const uint8_t* img, int64_t n_px, const double W[6], const double i0[3],
+                          double lambda, int white_sum, uint64_t seed, int64_t n_s, int64_t max_cand,
+                          double q, double P[2], int64_t* kept);
+
 /* Per-pixel normalized intensity before rounding (used by the tests to locate rounding ties). */
 void orc_reconstruct_pixel(const double h[2], const double W_tgt[6], const double s[2],
                            const double i0_out[3], double y[3]);
