@@ -329,6 +329,23 @@ def main() -> int:
         res.setdefault("extras", {})["i0_estimate"] = {"samples": 100000, "ms": round(ms_i0, 4),
                                                        "i0": [float(v) for v in i0_dev.cpu()]}
         log(f"[bench] i0 estimate {res['extras']['i0_estimate']}")
+        # the paper's percentile modes against the exact global histogram percentile
+        med = torch.empty(2, dtype=torch.float32, device=dev)
+        n_bands = (Hh + 1023) // 1024
+        ws_b = S.workspace(S.workspace_size(S.OP_BAND_PERCENTILES, 0, n_bands, 0), dev)
+        ms_band = timed(lambda: S.spcn_band_percentiles(img, w_fit, 1024, p, ws=ws_b), args.steps, args.warmup,
+                        stream)
+        med, _, _ = S.spcn_band_percentiles(img, w_fit, 1024, p, ws=ws_b)
+        sp = torch.empty(2, dtype=torch.float32, device=dev)
+        ws_s = S.workspace(S.workspace_size(S.OP_SAMPLE_PERCENTILE, 0, 0, n_samples), dev)
+        ms_samp = timed(lambda: S.spcn_sample_percentile(img, w_fit, n_samples, 2024, p, p99_out=sp, ws=ws_s),
+                        args.steps, args.warmup, stream)
+        _, st_g = S.spcn_normalize(img, w_fit, w_tgt, scale_tgt, p, out=out)
+        res["extras"]["percentile_modes"] = {
+            "global_hist": [round(float(v), 5) for v in st_g["p99_src"].cpu()],
+            "band_median_1024_rows": [round(float(v), 5) for v in med.cpu()], "band_ms": round(ms_band, 4),
+            "sample_200k": [round(float(v), 5) for v in sp.cpu()], "sample_ms": round(ms_samp, 4)}
+        log(f"[bench] percentile modes {res['extras']['percentile_modes']}")
     if args.extras and args.workload == "slide":
         del img, out
         torch.cuda.empty_cache()

@@ -85,6 +85,8 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_FORWARD_F32       5
 #define SPCN_OP_BACKWARD_F32      6
 #define SPCN_OP_ESTIMATE_I0       7
+#define SPCN_OP_SAMPLE_PERCENTILE 8   /* n_samples */
+#define SPCN_OP_BAND_PERCENTILES  9   /* n_items = number of bands */
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
@@ -133,6 +135,43 @@ spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, cons
                          const float* w_tgt, const float* scale_tgt, const float* i0_out,
                          const spcn_params* p, const uint64_t* hist, uint8_t* out,
                          const spcn_norm_stats* st, hipStream_t stream);
+
+/* Paper-compatible percentiles of Eq. 3 (alternatives to the exact global histogram percentile of
+ * spcn_normalize; feed any of them to spcn_recolor_p99).
+ *
+ * spcn_band_percentiles: median of per-patch percentiles (Sec. 3.2 items 3-4: the slide processed
+ * in longitudinal patches, the percentile taken as the median over patches).  Patches are bands of
+ * band_rows full rows (the last one shorter); each band's percentile is the histogram percentile
+ * of spcn_normalize over the band's non-white pixels (exact counts, p->hist_hi range); the median
+ * over the bands holding non-white pixels is the middle value, or the mean of the two middle
+ * values for an even count (0 and SPCN_FLAG_NO_TISSUE if none).
+ *   band_rows  >= 1; at most 65536 bands
+ *   band_p99   device [n_bands][2] per-band percentiles, or NULL;  p99_out device [2] medians
+ *   flags_out  device [2] or NULL
+ *   ws         spcn_workspace_size(SPCN_OP_BAND_PERCENTILES, 0, n_bands, 0) bytes */
+spcn_status spcn_band_percentiles(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                  const spcn_params* p, int64_t band_rows, float* band_p99,
+                                  float* p99_out, int32_t* flags_out, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+
+/* spcn_sample_percentile: percentile of the sub-sampled non-white pixels (Sec. 3.1 item 2): the
+ * densities (Eq. 2 with w fixed, p->lambda) of the first n_samples non-white pixels in the draw
+ * order of spcn_estimate_basis (same seed, same draws), and per stain their nearest-rank
+ * p->percentile: the k-th smallest with k = max(1, ceil(q n)).  Densities are computed in FP64.
+ *   n_samples 1 .. 1048576;  p99_out device [2];  flags_out device [2] or NULL (SHORT, NO_TISSUE)
+ *   ws        spcn_workspace_size(SPCN_OP_SAMPLE_PERCENTILE, 0, 0, n_samples) bytes */
+spcn_status spcn_sample_percentile(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                   const spcn_params* p, int64_t n_samples, uint64_t seed,
+                                   float* p99_out, int32_t* flags_out, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/* Pass 2 of spcn_normalize with the source percentiles given (device [2], from any of the modes
+ * above or from the caller): s_j = scale_tgt_j / p99_src_j, or 1 (SPCN_FLAG_BIN0) where p99_src_j is
+ * not > 0.  scale_out [2] and flags_out [2] (device) may be NULL.  No workspace. */
+spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                             const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                             const spcn_params* p, const float* p99_src, uint8_t* out,
+                             float* scale_out, int32_t* flags_out, hipStream_t stream);
 
 /* Basis estimation (Eq. 2 with both factors free; Sec. 3.1 items 2-3, Sec. 3.2 item 2): draws
  * n_samples non-white pixels with a counter-based SplitMix64 stream (candidate t -> pixel

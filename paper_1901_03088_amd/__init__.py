@@ -27,7 +27,7 @@ SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
 FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT, FLAG_NO_BACKGROUND = \
     1, 2, 4, 8, 16, 32, 64, 128
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
-    OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0 = range(8)
+    OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES = range(10)
 HIST_BINS = 256
 OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
@@ -61,6 +61,9 @@ _SIGS = {
     "spcn_estimate_basis_batched": (C.c_int, [_vp, _i32, _i64, _P, _f, _i64, _u64, _i32, _vp, _vp, _vp, _vp,
                                               _vp, _sz, _vp]),
     "spcn_estimate_i0": (C.c_int, [_vp, _i64, _i64, _i64, _u64, _i32, _f, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_band_percentiles": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_sample_percentile": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _u64, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_recolor_p99": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _vp]),
     "spcn_normalize_batched": (C.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_f32": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -263,6 +266,59 @@ def spcn_estimate_i0(img: torch.Tensor, n_samples: int = 100000, seed: int = 0, 
     _check(_L.spcn_estimate_i0(_ptr(img), H, W_, int(n_samples), C.c_uint64(seed & (2**64 - 1)), int(white_sum),
                                float(percentile), _ptr(i0_out), _ptr(flags), wsp, wsn, _stream()), "spcn_estimate_i0")
     return i0_out, flags
+
+
+def spcn_band_percentiles(img: torch.Tensor, w: torch.Tensor, band_rows: int, p: spcn_params | None = None,
+                          ws=None):
+    """Median over row bands of per-band percentiles.  Returns (median [2], band_p99 [n_bands, 2],
+    flags [2]) on the device."""
+    _dev(img, torch.uint8, "img"); _dev(w, torch.float32, "w")
+    p = p or params()
+    H, W_ = int(img.shape[0]), int(img.shape[1])
+    dev = img.device
+    nb = (H + band_rows - 1) // band_rows
+    med = torch.empty(2, dtype=torch.float32, device=dev)
+    bands = torch.empty((nb, 2), dtype=torch.float32, device=dev)
+    flags = torch.empty(2, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(workspace_size(OP_BAND_PERCENTILES, 0, nb, 0), dev)
+    wsp, wsn = _ws_ptr(ws)
+    _check(_L.spcn_band_percentiles(_ptr(img), H, W_, _ptr(w), C.byref(p), int(band_rows), _ptr(bands), _ptr(med),
+                                    _ptr(flags), wsp, wsn, _stream()), "spcn_band_percentiles")
+    return med, bands, flags
+
+
+def spcn_sample_percentile(img: torch.Tensor, w: torch.Tensor, n_samples: int, seed: int,
+                           p: spcn_params | None = None, p99_out=None, ws=None):
+    """Percentile of the sub-sampled non-white pixels' densities.  Returns (p99 [2], flags [2])."""
+    _dev(img, torch.uint8, "img"); _dev(w, torch.float32, "w")
+    p = p or params()
+    H, W_ = int(img.shape[0]), int(img.shape[1])
+    dev = img.device
+    p99_out = p99_out if p99_out is not None else torch.empty(2, dtype=torch.float32, device=dev)
+    flags = torch.empty(2, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(workspace_size(OP_SAMPLE_PERCENTILE, 0, 0, n_samples), dev)
+    wsp, wsn = _ws_ptr(ws)
+    _check(_L.spcn_sample_percentile(_ptr(img), H, W_, _ptr(w), C.byref(p), int(n_samples),
+                                     C.c_uint64(seed & (2**64 - 1)), _ptr(p99_out), _ptr(flags), wsp, wsn, _stream()),
+           "spcn_sample_percentile")
+    return p99_out, flags
+
+
+def spcn_recolor_p99(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
+                     p99_src: torch.Tensor, p: spcn_params | None = None, i0_out=None, out=None):
+    """Pass 2 with given source percentiles (device [2]).  Returns (out, scale [2], flags [2])."""
+    _dev(src, torch.uint8, "src"); _dev(p99_src, torch.float32, "p99_src")
+    p = p or params()
+    H, W_ = int(src.shape[0]), int(src.shape[1])
+    out = out if out is not None else torch.empty_like(src)
+    scale = torch.empty(2, dtype=torch.float32, device=src.device)
+    flags = torch.empty(2, dtype=torch.int32, device=src.device)
+    io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
+    _check(_L.spcn_recolor_p99(_ptr(src), H, W_, _ptr(w_src), _ptr(w_tgt), _ptr(scale_tgt), io, C.byref(p),
+                               _ptr(p99_src), _ptr(out), _ptr(scale), _ptr(flags), _stream()), "spcn_recolor_p99")
+    return out, scale, flags
 
 
 def tile_table(srcs, outs=None) -> torch.Tensor:

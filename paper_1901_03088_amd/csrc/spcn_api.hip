@@ -150,6 +150,10 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
             return f32_backward_workspace_bytes(n_px, n_items);
         case SPCN_OP_ESTIMATE_I0:
             return n_samples <= kMaxI0Samples ? i0_workspace_bytes(n_samples) : 0;
+        case SPCN_OP_SAMPLE_PERCENTILE:
+            return n_samples <= kMaxI0Samples ? sample_pctl_workspace_bytes(n_samples) : 0;
+        case SPCN_OP_BAND_PERCENTILES:
+            return n_items <= kMaxBands ? band_workspace_bytes(n_items) : 0;
         default:
             return 0;
     }
@@ -266,6 +270,63 @@ spcn_status spcn_estimate_i0(const uint8_t* img, int64_t height, int64_t width, 
     hipError_t e = launch_estimate_i0(img, height * width, white_sum, n_samples, seed, (double)percentile / 100.0,
                                       i0_out, flags_out, ws, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_estimate_i0 launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_band_percentiles(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                  const spcn_params* p, int64_t band_rows, float* band_p99, float* p99_out,
+                                  int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_image(img, height, width, "img"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w) return fail(SPCN_E_ARG, "w is NULL");
+    if (!p99_out) return fail(SPCN_E_ARG, "p99_out is NULL");
+    if (band_rows < 1) return fail(SPCN_E_ARG, "band_rows = %lld must be >= 1", (long long)band_rows);
+    const int64_t n_bands = (height + band_rows - 1) / band_rows;
+    if (n_bands > kMaxBands)
+        return fail(SPCN_E_ARG, "%lld bands exceed the limit of %lld", (long long)n_bands, (long long)kMaxBands);
+    SPCN_CHECK(check_ws(ws, ws_bytes, band_workspace_bytes(n_bands)));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_band_percentiles(img, height, width, w, make_params(p), band_rows, band_p99, p99_out,
+                                           flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_band_percentiles launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_sample_percentile(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                   const spcn_params* p, int64_t n_samples, uint64_t seed, float* p99_out,
+                                   int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_image(img, height, width, "img"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w) return fail(SPCN_E_ARG, "w is NULL");
+    if (!p99_out) return fail(SPCN_E_ARG, "p99_out is NULL");
+    if (n_samples < 1 || n_samples > kMaxI0Samples)
+        return fail(SPCN_E_ARG, "n_samples = %lld must lie in [1, %lld]", (long long)n_samples, (long long)kMaxI0Samples);
+    SPCN_CHECK(check_ws(ws, ws_bytes, sample_pctl_workspace_bytes(n_samples)));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_sample_percentile(img, height * width, w, make_params(p), n_samples, seed, p99_out,
+                                            flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_sample_percentile launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                             const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                             const spcn_params* p, const float* p99_src, uint8_t* out, float* scale_out,
+                             int32_t* flags_out, hipStream_t stream) {
+    SPCN_CHECK(check_image(src, height, width, "src"));
+    SPCN_CHECK(check_image(out, height, width, "out"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w_src || !w_tgt || !scale_tgt) return fail(SPCN_E_ARG, "w_src, w_tgt and scale_tgt must be non-NULL");
+    if (!p99_src) return fail(SPCN_E_ARG, "p99_src is NULL");
+    float io[3];
+    for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_recolor_p99(src, height * width, w_src, w_tgt, scale_tgt, io, make_params(p), out, p99_src,
+                                      scale_out, flags_out, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_recolor_p99 launch");
     return SPCN_OK;
 }
 

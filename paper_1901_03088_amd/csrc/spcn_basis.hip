@@ -775,6 +775,85 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
     return hipGetLastError();
 }
 
+// ------------------------------------------------- percentile of the sub-sampled pixels
+
+// FP64 densities (Eq. 2, W fixed, the density lambda) of the sampled pixels, planar [2][n_s].
+__global__ __launch_bounds__(256) void k_sample_dens(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
+                                                     const float* w, float lambda, float i00, float i01, float i02,
+                                                     double* H) {
+    __shared__ double s_od[3 * kHistBins];
+    __shared__ Basis64 B;
+    const float i0[3] = {i00, i01, i02};
+    if (threadIdx.x == 0) derive_basis(w, lambda, B);
+    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
+        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)i0[c], k);
+    __syncthreads();
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t* p = img + 3 * idx[i];
+        double h0 = 0.0, h1 = 0.0;
+        if (B.ok) solve64(B, s_od[p[0]], s_od[kHistBins + p[1]], s_od[2 * kHistBins + p[2]], h0, h1);
+        H[i] = h0;
+        H[ns + i] = h1;
+    }
+}
+
+// Nearest-rank percentile of each stain's sampled densities (one workgroup).
+__global__ __launch_bounds__(1024) void k_sample_pctl(const BasisWork* bw, const double* H, double q, float* p99_out,
+                                                      int32_t* flags_out) {
+    __shared__ uint32_t s_hist[256];
+    __shared__ int s_misc[2];
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    for (int j = 0; j < 2; ++j) {
+        double P = 0.0;
+        if (n > 0) {
+            int64_t k = (int64_t)ceil(q * (double)n);
+            k = k < 1 ? 1 : (k > n ? n : k);
+            const double* Hj = H + j * ns;
+            P = block_select(n, k, [&](int64_t i) { return Hj[i]; }, s_hist, s_misc);
+        }
+        if (threadIdx.x == 0) {
+            p99_out[j] = (float)P;
+            if (flags_out) flags_out[j] = (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
+        }
+        __syncthreads();
+    }
+}
+
+size_t sample_pctl_workspace_bytes(int64_t n_s) {
+    if (n_s <= 0) return 0;
+    return i0_workspace_bytes(n_s) + align256((size_t)2 * n_s * sizeof(double));
+}
+
+hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, int64_t n_s,
+                                    uint64_t seed, float* p99_out, int32_t* flags_out, void* ws, const DevInfo& dev,
+                                    hipStream_t s) {
+    uint8_t* p = static_cast<uint8_t*>(ws);
+    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
+    const int64_t nbmax = max_round_blocks(n_s);
+    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
+    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
+    double* H = reinterpret_cast<double*>(p);
+    const int64_t max_cand = 64 * n_s;
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr);
+    int64_t t0 = 0;
+    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
+        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
+        SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
+                     counts, idx};
+        hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        t0 += rc;
+    }
+    hipLaunchKernelGGL(k_sample_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
+                       img, (const int64_t*)idx, (const BasisWork*)bw, w, pk.lambda, pk.i0[0], pk.i0[1], pk.i0[2], H);
+    hipLaunchKernelGGL(k_sample_pctl, dim3(1), dim3(1024), 0, s, (const BasisWork*)bw, (const double*)H, pk.q64,
+                       p99_out, flags_out);
+    return hipGetLastError();
+}
+
 size_t basis_batched_workspace_bytes(int64_t, int64_t) { return 0; }
 
 hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, const ParamsK& pk,

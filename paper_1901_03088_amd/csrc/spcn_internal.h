@@ -69,6 +69,19 @@ size_t basis_batched_workspace_bytes(int64_t n_tiles, int64_t n_samples);
 int64_t basis_tile_max_samples();
 constexpr int64_t kMaxBasisSamples = 262144;
 constexpr int64_t kMaxI0Samples = 1048576;
+constexpr int64_t kMaxBands = 65536;
+size_t sample_pctl_workspace_bytes(int64_t n_samples);
+hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, int64_t n_s,
+                                    uint64_t seed, float* p99_out, int32_t* flags_out, void* ws, const DevInfo& dev,
+                                    hipStream_t s);
+size_t band_workspace_bytes(int64_t n_bands);
+hipError_t launch_band_percentiles(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                   const ParamsK& pk, int64_t band_rows, float* band_out, float* median_out,
+                                   int32_t* flags_out, void* ws, const DevInfo& dev, hipStream_t s);
+hipError_t launch_recolor_p99(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
+                              const float* scale_tgt, const float i0_out[3], const ParamsK& pk, uint8_t* out,
+                              const float* p99_in, float* scale_out, int32_t* flags_out, const DevInfo& dev,
+                              hipStream_t s);
 size_t i0_workspace_bytes(int64_t n_samples);
 hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
                               double q, float* i0_out, int32_t* flags_out, void* ws, hipStream_t s);

@@ -453,6 +453,28 @@ __device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P
     }
 }
 
+// Contiguous run of cnt units (buffer resource rs over its bytes, src_run its first byte): each
+// thread takes units tid, tid + nthreads, ..., UNROLL of them per iteration with one iteration of
+// prefetch.
+template <int UNROLL, bool U16>
+__device__ void p1f_run(P1FLds& S, const P1Params& pp, __amdgpu_buffer_rsrc_t rs, const uint8_t* src_run, int cnt,
+                        int tid, int nthreads) {
+    const P1FLane L = p1f_lane(tid);
+    const int stride = nthreads * UNROLL;
+    u32x3 cur[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (int lb0 = tid; lb0 < cnt; lb0 += stride) {
+        u32x3 nxt[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j)   // prefetch; past the run the loads return zeros
+            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb0 + stride + j * nthreads), 0, 0);
+        p1f_units<UNROLL, U16, false>(S, pp, L, cur, lb0, cnt, nthreads, src_run);
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+    }
+}
+
 // Grid-stride form: the image's units form tiles of nthreads * UNROLL units; workgroup b takes tiles
 // b, b + gridDim.x, ... so that the whole grid sweeps the image front to back together.
 template <int UNROLL, bool U16, bool ZROW>

@@ -100,6 +100,7 @@ struct P2Args {
     float hist_hi[2];
     double q;
     const uint64_t* hist;
+    const float* p99_in;       // given source percentiles [2] (then hist is not read), or NULL
     float* p99_out;
     float* scale_out;
     int32_t* flags_out;
@@ -112,12 +113,19 @@ __device__ void p2_prologue(const P2Args& a, P2Lds<COPIES>& T, FinalShared& F, B
     if (threadIdx.x == 0) derive_basis(a.w_src, a.lambda, B);
     __syncthreads();
     p2_tables(T, B, a.i0);
-    block_percentiles(a.hist, a.q, a.hist_hi, F);
+    if (a.p99_in) {
+        if (threadIdx.x < 2) F.P[threadIdx.x] = (double)a.p99_in[threadIdx.x];
+    } else {
+        block_percentiles(a.hist, a.q, a.hist_hi, F);
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double s[2];
         int fl[2];
         for (int j = 0; j < 2; ++j) {
-            fl[j] = stain_flags(F, j, B.ok);
+            // a given percentile that is not > 0 keeps the stain unscaled, like a bin-0 percentile
+            fl[j] = a.p99_in ? ((F.P[j] > 0.0 ? 0 : SPCN_FLAG_BIN0) | (B.ok ? 0 : SPCN_FLAG_BASIS))
+                             : stain_flags(F, j, B.ok);
             s[j] = stain_scale((double)a.scale_tgt[j], F.P[j], fl[j]);
         }
         make_recolour(K, a.w_tgt, s, a.i0_out, B);
@@ -273,6 +281,27 @@ hipError_t launch_recolor(const uint8_t* src, int64_t n_px, const float* w_src, 
     b.lambda = pk.lambda; b.hist_hi[0] = pk.hist_hi[0]; b.hist_hi[1] = pk.hist_hi[1];
     b.q = pk.q64; b.hist = hist;
     b.p99_out = p99_out; b.scale_out = scale_out; b.flags_out = flags_out;
+    const int bpc = option(SPCN_OPT_P2_BLOCKS_PER_CU);
+    switch (option(SPCN_OPT_P2_VARIANT)) {
+        case 0: return run_pass2<1, 256>(b, bpc, dev, s);
+        case 1: return run_pass2<4, 256>(b, bpc, dev, s);
+        case 2: return run_pass2<16, 1024>(b, 1, dev, s);
+        case 3: return run_pass2g<1, 256>(b, bpc, dev, s);
+        case 4: return run_pass2g<1, 512>(b, bpc, dev, s);
+        default: return run_pass2g<16, 1024>(b, 1, dev, s);
+    }
+}
+
+hipError_t launch_recolor_p99(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
+                              const float* scale_tgt, const float i0_out[3], const ParamsK& pk, uint8_t* out,
+                              const float* p99_in, float* scale_out, int32_t* flags_out, const DevInfo& dev,
+                              hipStream_t s) {
+    P2Args b{};
+    b.src = src; b.out = out; b.n_px = n_px; b.w_src = w_src; b.w_tgt = w_tgt; b.scale_tgt = scale_tgt;
+    for (int c = 0; c < 3; ++c) { b.i0[c] = pk.i0[c]; b.i0_out[c] = i0_out[c]; }
+    b.lambda = pk.lambda; b.hist_hi[0] = pk.hist_hi[0]; b.hist_hi[1] = pk.hist_hi[1];
+    b.q = pk.q64; b.hist = nullptr; b.p99_in = p99_in;
+    b.p99_out = nullptr; b.scale_out = scale_out; b.flags_out = flags_out;
     const int bpc = option(SPCN_OPT_P2_BLOCKS_PER_CU);
     switch (option(SPCN_OPT_P2_VARIANT)) {
         case 0: return run_pass2<1, 256>(b, bpc, dev, s);
