@@ -346,6 +346,23 @@ def main() -> int:
             "band_median_1024_rows": [round(float(v), 5) for v in med.cpu()], "band_ms": round(ms_band, 4),
             "sample_200k": [round(float(v), 5) for v in sp.cpu()], "sample_ms": round(ms_samp, 4)}
         log(f"[bench] percentile modes {res['extras']['percentile_modes']}")
+        # out-of-core: the first 8192 rows of the slide from pinned host memory, chunks of 512 rows
+        rows = min(Hh, 8192)
+        host = torch.empty((rows, Ww, 3), dtype=torch.uint8, pin_memory=True)
+        host.copy_(img[:rows])
+        host_out = torch.empty_like(host, pin_memory=True)
+        ws_st = S.workspace(S.workspace_size(S.OP_STREAM_NORMALIZE, Ww, 512, 0), dev)
+        cin, cout = torch.cuda.Stream(), torch.cuda.Stream()
+        ms_st = timed(lambda: S.spcn_normalize_streamed(host, w_fit, w_tgt, scale_tgt, p, chunk_rows=512,
+                                                        host_out=host_out, ws=ws_st, copy_in=cin, copy_out=cout),
+                      max(2, args.steps // 2), 1, stream)
+        npx = rows * Ww
+        res["extras"]["streamed_host_slide"] = {
+            "rows": rows, "pixels": npx, "chunk_rows": 512, "ms": round(ms_st, 3),
+            "Mpx_s_pcie_inclusive": round(npx / ms_st / 1e3, 1),
+            "link_GBs_h2d": round(6 * npx / ms_st / 1e6, 1), "link_GBs_d2h": round(3 * npx / ms_st / 1e6, 1)}
+        log(f"[bench] streamed {res['extras']['streamed_host_slide']}")
+        del host, host_out, ws_st
     if args.extras and args.workload == "slide":
         del img, out
         torch.cuda.empty_cache()

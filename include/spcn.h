@@ -87,6 +87,7 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_ESTIMATE_I0       7
 #define SPCN_OP_SAMPLE_PERCENTILE 8   /* n_samples */
 #define SPCN_OP_BAND_PERCENTILES  9   /* n_items = number of bands */
+#define SPCN_OP_STREAM_NORMALIZE 10   /* n_px = image width, n_items = chunk_rows */
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
@@ -135,6 +136,28 @@ spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, cons
                          const float* w_tgt, const float* scale_tgt, const float* i0_out,
                          const spcn_params* p, const uint64_t* hist, uint8_t* out,
                          const spcn_norm_stats* st, hipStream_t stream);
+
+/* Out-of-core spcn_normalize for a slide in host memory (the paper's divide and conquer of WSIs,
+ * Sec. 3.2 item 3, here for slides larger than, or arriving outside, device memory).  The slide is
+ * processed in chunks of chunk_rows rows: pass 1 copies each chunk to the device and adds it to one
+ * exact non-white histogram, pass 2 copies it again, recolours it and copies the result back.
+ * Copies run on copy_in / copy_out and overlap the kernels on `compute`; all work is enqueued
+ * without host synchronisation and `compute` completes after the last copy.  The result equals
+ * spcn_normalize of the whole slide byte for byte.
+ *   host_src, host_out  uint8 HWC, 3*height*width bytes of pinned host memory (hipHostMalloc or
+ *                       equivalent; pageable memory serialises the copies)
+ *   chunk_rows          rows per chunk, at most 2^30 pixels per chunk
+ *   st                  optional device statistics (hist is ignored: the histogram lives in ws)
+ *   ws                  device workspace of spcn_workspace_size(SPCN_OP_STREAM_NORMALIZE, width,
+ *                       chunk_rows, 0) bytes: the histogram and four chunk staging buffers
+ *   compute, copy_in, copy_out  streams; copy_in and copy_out must differ from compute (they may
+ *                       be the same stream).  Overlapping calls on one device must be serialised. */
+spcn_status spcn_normalize_streamed(const uint8_t* host_src, uint8_t* host_out, int64_t height,
+                                    int64_t width, const float* w_src, const float* w_tgt,
+                                    const float* scale_tgt, const float* i0_out,
+                                    const spcn_params* p, int64_t chunk_rows,
+                                    const spcn_norm_stats* st, void* ws, size_t ws_bytes,
+                                    hipStream_t compute, hipStream_t copy_in, hipStream_t copy_out);
 
 /* Paper-compatible percentiles of Eq. 3 (alternatives to the exact global histogram percentile of
  * spcn_normalize; feed any of them to spcn_recolor_p99).

@@ -27,7 +27,8 @@ SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
 FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT, FLAG_NO_BACKGROUND = \
     1, 2, 4, 8, 16, 32, 64, 128
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
-    OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES = range(10)
+    OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES, \
+    OP_STREAM_NORMALIZE = range(11)
 HIST_BINS = 256
 OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
@@ -64,6 +65,8 @@ _SIGS = {
     "spcn_band_percentiles": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_sample_percentile": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _u64, _vp, _vp, _vp, _sz, _vp]),
     "spcn_recolor_p99": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _vp]),
+    "spcn_normalize_streamed": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _i64, _vp, _vp, _sz, _vp,
+                                          _vp, _vp]),
     "spcn_normalize_batched": (C.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_f32": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -319,6 +322,37 @@ def spcn_recolor_p99(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor
     _check(_L.spcn_recolor_p99(_ptr(src), H, W_, _ptr(w_src), _ptr(w_tgt), _ptr(scale_tgt), io, C.byref(p),
                                _ptr(p99_src), _ptr(out), _ptr(scale), _ptr(flags), _stream()), "spcn_recolor_p99")
     return out, scale, flags
+
+
+def spcn_normalize_streamed(host_src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor,
+                            scale_tgt: torch.Tensor, p: spcn_params | None = None, chunk_rows: int = 1024,
+                            i0_out=None, host_out=None, ws=None, copy_in=None, copy_out=None):
+    """Normalises a pinned host (H, W, 3) uint8 tensor through the device in row chunks.  Returns
+    (host_out, dict(p99_src, scale, flags) on the device); host_out is complete once the current
+    stream is."""
+    if host_src.device.type != "cpu" or not host_src.is_pinned() or host_src.dtype != torch.uint8:
+        raise ValueError("host_src must be a pinned CPU uint8 tensor")
+    if not host_src.is_contiguous() or host_src.dim() != 3 or host_src.shape[2] != 3:
+        raise ValueError("host_src must be a contiguous (H, W, 3) tensor")
+    p = p or params()
+    dev = w_src.device
+    H, W_ = int(host_src.shape[0]), int(host_src.shape[1])
+    host_out = host_out if host_out is not None else torch.empty_like(host_src, pin_memory=True)
+    if ws is None:
+        ws = workspace(workspace_size(OP_STREAM_NORMALIZE, W_, chunk_rows, 0), dev)
+    wsp, wsn = _ws_ptr(ws)
+    res = {"p99_src": torch.empty(2, dtype=torch.float32, device=dev),
+           "scale": torch.empty(2, dtype=torch.float32, device=dev),
+           "flags": torch.empty(2, dtype=torch.int32, device=dev)}
+    st = spcn_norm_stats(0, res["p99_src"].data_ptr(), res["scale"].data_ptr(), res["flags"].data_ptr())
+    copy_in = copy_in or torch.cuda.Stream(device=dev)
+    copy_out = copy_out or copy_in
+    io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
+    _check(_L.spcn_normalize_streamed(C.c_void_p(host_src.data_ptr()), C.c_void_p(host_out.data_ptr()), H, W_,
+                                      _ptr(w_src), _ptr(w_tgt), _ptr(scale_tgt), io, C.byref(p), int(chunk_rows),
+                                      C.byref(st), wsp, wsn, _stream(), C.c_void_p(copy_in.cuda_stream),
+                                      C.c_void_p(copy_out.cuda_stream)), "spcn_normalize_streamed")
+    return host_out, res
 
 
 def tile_table(srcs, outs=None) -> torch.Tensor:

@@ -154,6 +154,8 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
             return n_samples <= kMaxI0Samples ? sample_pctl_workspace_bytes(n_samples) : 0;
         case SPCN_OP_BAND_PERCENTILES:
             return n_items <= kMaxBands ? band_workspace_bytes(n_items) : 0;
+        case SPCN_OP_STREAM_NORMALIZE:
+            return stream_workspace_bytes(n_px, n_items);
         default:
             return 0;
     }
@@ -327,6 +329,35 @@ spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, 
     hipError_t e = launch_recolor_p99(src, height * width, w_src, w_tgt, scale_tgt, io, make_params(p), out, p99_src,
                                       scale_out, flags_out, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_recolor_p99 launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_normalize_streamed(const uint8_t* host_src, uint8_t* host_out, int64_t height, int64_t width,
+                                    const float* w_src, const float* w_tgt, const float* scale_tgt,
+                                    const float* i0_out, const spcn_params* p, int64_t chunk_rows,
+                                    const spcn_norm_stats* st, void* ws, size_t ws_bytes, hipStream_t compute,
+                                    hipStream_t copy_in, hipStream_t copy_out) {
+    if (!host_src || !host_out) return fail(SPCN_E_ARG, "host_src and host_out must be non-NULL");
+    if (height <= 0 || width <= 0) return fail(SPCN_E_ARG, "height and width must be positive");
+    if (height > ((int64_t)1 << 36) / width) return fail(SPCN_E_ARG, "image of %lld x %lld pixels is too large",
+                                                         (long long)height, (long long)width);
+    SPCN_CHECK(check_params(p, true));
+    if (!w_src || !w_tgt || !scale_tgt) return fail(SPCN_E_ARG, "w_src, w_tgt and scale_tgt must be non-NULL");
+    if (chunk_rows < 1 || chunk_rows * width > ((int64_t)1 << 30))
+        return fail(SPCN_E_ARG, "chunk_rows = %lld must be >= 1 with at most 2^30 pixels per chunk",
+                    (long long)chunk_rows);
+    SPCN_CHECK(check_ws(ws, ws_bytes, stream_workspace_bytes(width, chunk_rows)));
+    if (copy_in == compute || copy_out == compute)
+        return fail(SPCN_E_ARG, "copy streams must differ from the compute stream");
+    float io[3];
+    for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_stream_normalize(host_src, host_out, height, width, w_src, w_tgt, scale_tgt, io,
+                                           make_params(p), chunk_rows, ws, st ? st->p99_src : nullptr,
+                                           st ? st->scale : nullptr, st ? st->flags : nullptr, dev, compute, copy_in,
+                                           copy_out);
+    if (e != hipSuccess) return hip_fail(e, "spcn_normalize_streamed");
     return SPCN_OK;
 }
 

@@ -70,6 +70,16 @@ int64_t basis_tile_max_samples();
 constexpr int64_t kMaxBasisSamples = 262144;
 constexpr int64_t kMaxI0Samples = 1048576;
 constexpr int64_t kMaxBands = 65536;
+hipError_t launch_zero_hist(uint64_t* hist, hipStream_t s);
+// pass 1 adding to hist (not cleared)
+hipError_t launch_count(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, uint64_t* hist,
+                        const DevInfo& dev, hipStream_t s);
+size_t stream_workspace_bytes(int64_t width, int64_t chunk_rows);
+hipError_t launch_stream_normalize(const uint8_t* host_src, uint8_t* host_out, int64_t height, int64_t width,
+                                   const float* w_src, const float* w_tgt, const float* scale_tgt,
+                                   const float i0_out[3], const ParamsK& pk, int64_t chunk_rows, void* ws,
+                                   float* p99_out, float* scale_out, int32_t* flags_out, const DevInfo& dev,
+                                   hipStream_t compute, hipStream_t copy_in, hipStream_t copy_out);
 size_t sample_pctl_workspace_bytes(int64_t n_samples);
 hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, int64_t n_s,
                                     uint64_t seed, float* p99_out, int32_t* flags_out, void* ws, const DevInfo& dev,

@@ -253,6 +253,16 @@ static hipError_t launch_pass1(const uint8_t* img, int64_t n_px, const float* w,
     }
 }
 
+hipError_t launch_zero_hist(uint64_t* hist, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, hist, 2 * kHistBins);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, uint64_t* hist,
+                        const DevInfo& dev, hipStream_t s) {
+    return launch_pass1(img, n_px, w, pk, hist, dev, s);
+}
+
 hipError_t launch_densities(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
                             float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out,
                             const DevInfo& dev, hipStream_t s) {

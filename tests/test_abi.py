@@ -148,3 +148,18 @@ def test_estimate_i0_rejects(lib, kw, frag):
 def test_estimate_i0_workspace_size(lib):
     assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, 100000) > 100000 * 8
     assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, (1 << 20) + 1) == 0
+
+
+def test_streamed_rejects(lib):
+    p = lib.params()
+    ok = dict(src=C.c_void_p(1 << 20), out=C.c_void_p(2 << 20), h=64, w=64, rows=16, wsn=1 << 26,
+              comp=C.c_void_p(0), cin=C.c_void_p(8), cout=C.c_void_p(8))
+    def call(**kw):
+        a = dict(ok); a.update(kw)
+        return lib._L.spcn_normalize_streamed(a["src"], a["out"], a["h"], a["w"], C.c_void_p(1 << 24),
+                                              C.c_void_p(1 << 24), C.c_void_p(1 << 24), None, C.byref(p), a["rows"],
+                                              None, C.c_void_p(1 << 28), a["wsn"], a["comp"], a["cin"], a["cout"])
+    for kw, frag in ((dict(src=None), "host_src"), (dict(rows=0), "chunk_rows"), (dict(wsn=64), "workspace"),
+                     (dict(cin=C.c_void_p(0)), "copy streams"), (dict(h=0), "height")):
+        assert call(**kw) in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
+        assert frag in lib._L.spcn_last_error().decode(), (kw, lib._L.spcn_last_error())
