@@ -214,14 +214,23 @@ __device__ inline void initial_basis(const float* w_init, double* W) {
 // significant-digit radix select over their bit patterns (monotone for x >= 0), block-wide.
 template <class F>
 __device__ double block_select(int64_t n, int64_t k, F val, uint32_t* s_hist, int* s_misc) {
+    // s_hist: [16][256], one digit histogram per wavefront (values that share their leading
+    // digits all hit one bin: per-wavefront copies keep the atomics of different waves apart)
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint64_t prefix = 0, pmask = 0;
     int64_t kk = k;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int b = threadIdx.x; b < 256; b += blockDim.x) s_hist[b] = 0;
+        for (int b = threadIdx.x; b < nw * 256; b += blockDim.x) s_hist[b] = 0;
         __syncthreads();
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
             uint64_t u = (uint64_t)__double_as_longlong(val(i));
-            if ((u & pmask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255], 1u);
+            if ((u & pmask) == prefix) atomicAdd(&s_hist[wave * 256 + ((u >> shift) & 255)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            uint32_t t = 0;
+            for (int w = 0; w < nw; ++w) t += s_hist[w * 256 + threadIdx.x];
+            s_hist[threadIdx.x] = t;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -465,7 +474,7 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
 // densities of the samples (one workgroup).
 __global__ __launch_bounds__(1024) void k_nmf_finish(BasisWork* bw, const double* V, double lambda, double q,
                                                      float* w_out, float* sample_p99, int32_t* flags_out) {
-    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_hist[16 * 256];
     __shared__ int s_misc[2];
     __shared__ double s_W[6];
     if (threadIdx.x == 0) {
@@ -707,35 +716,51 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
 
 // ------------------------------------------------------- channel-wise background intensity
 
-// Nearest-rank percentile of each channel over the sampled background pixels (one workgroup):
-// k = max(1, ceil(q n)) in FP64, the smallest value whose cumulative count reaches k.
-__global__ __launch_bounds__(1024) void k_i0_select(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
-                                                    double q, float* i0_out, int32_t* flags_out) {
-    __shared__ uint32_t s_hist[3][kHistBins];
+// Per-channel histogram of the sampled background pixels: workgroups take strided samples, count
+// into per-wavefront LDS copies (background values crowd into a few bins) and add to the global
+// [3][256] counts.
+__global__ __launch_bounds__(1024) void k_i0_hist(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
+                                                  uint32_t* ghist) {
+    __shared__ uint32_t s_hist[16][3 * kHistBins];
+    const int t = threadIdx.x, wave = t >> 6;
+    for (int i = t; i < 16 * 3 * kHistBins; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
+    __syncthreads();
+    const int64_t n = bw->n_acc;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + t; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t* p = img + 3 * idx[i];
+        atomicAdd(&s_hist[wave][p[0]], 1u);
+        atomicAdd(&s_hist[wave][kHistBins + p[1]], 1u);
+        atomicAdd(&s_hist[wave][2 * kHistBins + p[2]], 1u);
+    }
+    __syncthreads();
+    for (int b = t; b < 3 * kHistBins; b += blockDim.x) {
+        uint32_t sum = 0;
+        for (int w = 0; w < 16; ++w) sum += s_hist[w][b];
+        if (sum) atomicAdd(ghist + b, sum);
+    }
+}
+
+__global__ void k_i0_clear(uint32_t* ghist) {
+    for (int i = threadIdx.x; i < 3 * kHistBins; i += blockDim.x) ghist[i] = 0u;
+}
+
+// Nearest-rank percentile of each channel (one workgroup): k = max(1, ceil(q n)) in FP64, the
+// smallest value whose cumulative count reaches k.
+__global__ __launch_bounds__(256) void k_i0_select(const uint32_t* ghist, const BasisWork* bw, double q,
+                                                   float* i0_out, int32_t* flags_out) {
     __shared__ uint32_t s_cum[3][kHistBins];
     const int t = threadIdx.x;
-    for (int i = t; i < 3 * kHistBins; i += blockDim.x) s_hist[i / kHistBins][i % kHistBins] = 0u;
+    if (t < 3) {   // 3 x 256 serial prefix sums
+        uint32_t run = 0;
+        for (int k = 0; k < kHistBins; ++k) { run += ghist[t * kHistBins + k]; s_cum[t][k] = run; }
+    }
     __syncthreads();
     const int64_t n = bw->n_acc, ns = bw->n_s;
-    for (int64_t i = t; i < n; i += blockDim.x) {
-        const uint8_t* p = img + 3 * idx[i];
-        atomicAdd(&s_hist[0][p[0]], 1u);
-        atomicAdd(&s_hist[1][p[1]], 1u);
-        atomicAdd(&s_hist[2][p[2]], 1u);
-    }
-    __syncthreads();
-    if (t < 3) {   // 3 x 256 serial prefix sums: negligible next to the sampling
-        uint32_t run = 0;
-        for (int k = 0; k < kHistBins; ++k) { run += s_hist[t][k]; s_cum[t][k] = run; }
-    }
-    __syncthreads();
     if (n > 0) {
         int64_t k = (int64_t)ceil(q * (double)n);
         k = k < 1 ? 1 : (k > n ? n : k);
-        if (t < 3 * kHistBins) {
-            const int c = t / kHistBins, v = t % kHistBins;
-            if ((int64_t)s_cum[c][v] >= k && (v == 0 || (int64_t)s_cum[c][v - 1] < k)) i0_out[c] = (float)v;
-        }
+        for (int c = 0; c < 3; ++c)
+            if ((int64_t)s_cum[c][t] >= k && (t == 0 || (int64_t)s_cum[c][t - 1] < k)) i0_out[c] = (float)t;
     } else if (t < 3) {
         i0_out[t] = 255.0f;
     }
@@ -747,7 +772,8 @@ size_t i0_workspace_bytes(int64_t n_s) {
     if (n_s <= 0) return 0;
     const int64_t nb = max_round_blocks(n_s);
     return align256(sizeof(BasisWork)) + align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t)) +
-           align256((size_t)(nb + 1) * sizeof(int32_t)) + align256((size_t)n_s * sizeof(int64_t));
+           align256((size_t)(nb + 1) * sizeof(int32_t)) + align256((size_t)n_s * sizeof(int64_t)) +
+           align256((size_t)3 * kHistBins * sizeof(uint32_t));
 }
 
 hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
@@ -757,9 +783,11 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
     const int64_t nbmax = max_round_blocks(n_s);
     int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
     int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
-    int64_t* idx = reinterpret_cast<int64_t*>(p);
+    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
+    uint32_t* ghist = reinterpret_cast<uint32_t*>(p);
     const int64_t max_cand = 64 * n_s;
     hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr);
+    hipLaunchKernelGGL(k_i0_clear, dim3(1), dim3(256), 0, s, ghist);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
@@ -770,7 +798,9 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
         hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
         t0 += rc;
     }
-    hipLaunchKernelGGL(k_i0_select, dim3(1), dim3(1024), 0, s, img, (const int64_t*)idx, (const BasisWork*)bw, q,
+    hipLaunchKernelGGL(k_i0_hist, dim3((unsigned)hmin((n_s + 1023) / 1024, 128)), dim3(1024), 0, s, img,
+                       (const int64_t*)idx, (const BasisWork*)bw, ghist);
+    hipLaunchKernelGGL(k_i0_select, dim3(1), dim3(256), 0, s, (const uint32_t*)ghist, (const BasisWork*)bw, q,
                        i0_out, flags_out);
     return hipGetLastError();
 }
@@ -801,7 +831,7 @@ __global__ __launch_bounds__(256) void k_sample_dens(const uint8_t* img, const i
 // Nearest-rank percentile of each stain's sampled densities (one workgroup).
 __global__ __launch_bounds__(1024) void k_sample_pctl(const BasisWork* bw, const double* H, double q, float* p99_out,
                                                       int32_t* flags_out) {
-    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_hist[16 * 256];
     __shared__ int s_misc[2];
     const int64_t n = bw->n_acc, ns = bw->n_s;
     for (int j = 0; j < 2; ++j) {
