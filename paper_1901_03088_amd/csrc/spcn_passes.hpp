@@ -280,6 +280,7 @@ struct P1FLds {
     int4 mem[2 * kHistBins * 16];   // 2 regions x 256 slots x 256 B
     uint32_t zero[2][64];           // bin-0 counts, one word per lane: bin 0 is often shared by most
                                     // lanes of a wavefront (an absent stain), so it gets its own row
+    double od[3][kHistBins];        // FP64 optical densities of Eq. 1 for the near-edge path
     Basis64 B;
     int shift;                      // fixed-point resolution u (<= 16)
 };
@@ -314,8 +315,9 @@ __device__ void p1f_setup(P1FLds& S, const float* w, const P1Params& pp, bool ze
         const int k = tid;
         const double sig0 = ldexp(256.0 / (double)pp.hist_hi[0], u), sig1 = ldexp(256.0 / (double)pp.hist_hi[1], u);
         char* base = reinterpret_cast<char*>(S.mem);
+        for (int c = 0; c < 3; ++c) S.od[c][k] = od_u8((double)pp.i0[c], k);
         for (int c = 0; c < 3; ++c) {
-            const double od = S.B.ok ? od_u8((double)pp.i0[c], k) : 0.0;
+            const double od = S.B.ok ? S.od[c][k] : 0.0;
             const int g = c == 0 ? kGuardUnits - 2 * kGuardUnits : 0;   // shifted guard (see above)
             int4 e;
             e.x = __double2int_rn((S.B.pc[0][c] * od + (c == 0 ? S.B.pconst[0] : 0.0)) * sig0) + g;
@@ -339,8 +341,7 @@ __device__ __forceinline__ bool p1f_near(int32_t y, uint32_t nmask) {
 __device__ __forceinline__ void p1f_exact(P1FLds& S, const P1Params& pp, uint32_t R, uint32_t G, uint32_t Bc,
                                           uint32_t lh) {
     double d0, d1;
-    solve64(S.B, od_u8((double)pp.i0[0], (int)R), od_u8((double)pp.i0[1], (int)G), od_u8((double)pp.i0[2], (int)Bc),
-            d0, d1);
+    solve64(S.B, S.od[0][R], S.od[1][G], S.od[2][Bc], d0, d1);
     const double e0 = floor(d0 * (256.0 / (double)pp.hist_hi[0])), e1 = floor(d1 * (256.0 / (double)pp.hist_hi[1]));
     char* base = reinterpret_cast<char*>(S.mem);
     atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(e0 >= 255.0 ? 255 : (int)e0, lh)), 1u);
@@ -438,19 +439,23 @@ __device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P
             }
         }
     }
-    if (near_waves) {   // rare: settle the near-edge pixels of these units in FP64
-#pragma unroll 1
-        for (int b = 0; b < 4 * UNROLL; ++b) {
-            const int lu = lb0 + (b >> 2) * nthreads;
-            if (lu >= cnt) continue;
-            const uint8_t* p = src_run + 3 * (4 * (int64_t)lu + (b & 3));
-            const uint32_t R = p[0], G = p[1], Bc = p[2];
-            if ((int32_t)(R + G + Bc) >= thr) continue;
-            int32_t y0, y1;
-            p1f_sums(S, R, G, Bc, L.r16, y0, y1);
-            if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
+    if (near_waves) {   // rare: settle the near-edge pixels of these units in FP64 (bytes from registers)
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) {
+            if (lb0 + j * nthreads >= cnt) continue;
+            uint32_t px[4][3];
+            bytes_of_unit(cur[j], px);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t R = px[q][0], G = px[q][1], Bc = px[q][2];
+                if ((int32_t)(R + G + Bc) >= thr) continue;
+                int32_t y0, y1;
+                p1f_sums(S, R, G, Bc, L.r16, y0, y1);
+                if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
+            }
         }
     }
+    (void)src_run;
 }
 
 // Contiguous run of cnt units (buffer resource rs over its bytes, src_run its first byte): each
