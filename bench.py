@@ -74,8 +74,8 @@ def cpu_baseline(img_dev, W_src, W_tgt, scale_tgt, min_seconds: float = 10.0, ba
 
 
 P1_KERNELS = ["k_pass1<1, 64, 4, 4>", "k_pass1<2, 64, 4, 4>", "k_pass1<4, 32, 4, 4>", "k_pass1<8, 16, 4, 4>",
-              "k_pass1<1, 32, 2, 8>", "k_pass1<2, 16, 2, 8>", "k_pass1g<4, false>", "k_pass1g<2, false>",
-              "k_pass1g<4, true>", "k_pass1g<2, true>"]
+              "k_pass1<1, 32, 2, 8>", "k_pass1<2, 16, 2, 8>", "k_pass1g<true, 1024, 4, 4>",
+              "k_pass1g<true, 1024, 2, 4>", "k_pass1g<false, 768, 2, 6>", "k_pass1g<false, 512, 2, 4>"]
 P2_KERNELS = ["k_pass2<1, 256>", "k_pass2<4, 256>", "k_pass2<16, 1024>", "k_pass2g<1, 256>", "k_pass2g<1, 512>",
               "k_pass2g<16, 1024>"]
 TRAFFIC_SOURCES = ["paper_1901_03088_amd/csrc/spcn_passes.hpp", "paper_1901_03088_amd/csrc/spcn_u8.hip",

@@ -300,7 +300,8 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
  *                              2 = (4, 32, 4, 1), 3 = (8, 16, 4, 1), 4 = (1, 32, 2, 2),
  *                              5 = (2, 16, 2, 2); 6, 7 = byte-permute table layout (8 copies,
  *                              16 columns), grid-stride tiles, 4 or 2 units per thread and
- *                              iteration; 8, 9 = the same with bin-0 counts in a lane-private row
+ *                              iteration; 8, 9 = narrow byte-permute layout (4 copies, 8 columns,
+ *                              64 KB) with two 768- or 512-thread workgroups per CU
  *   SPCN_OPT_P2_VARIANT        pass-2 table copies / workgroup size, contiguous chunks: 0 = (1, 256),
  *                              1 = (4, 256), 2 = (16, 1024); grid-stride tiles: 3 = (1, 256),
  *                              4 = (1, 512), 5 = (16, 1024)

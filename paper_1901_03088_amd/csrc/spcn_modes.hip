@@ -39,7 +39,7 @@ __global__ void k_band_zero(unsigned long long* h, int64_t n) {
 }
 
 __global__ __launch_bounds__(BH_THREADS, 4) void k_band_hist(const BandArgs a) {
-    __shared__ P1FLds S;
+    __shared__ P1FLds<true> S;
     p1f_setup(S, a.w, a.pp, true);
     const int band = blockIdx.x / a.parts, part = blockIdx.x % a.parts;
     const int64_t r0 = (int64_t)band * a.band_rows;
@@ -50,12 +50,11 @@ __global__ __launch_bounds__(BH_THREADS, 4) void k_band_hist(const BandArgs a) {
     const int64_t per = (units + a.parts - 1) / a.parts;
     const int64_t u0 = min(units, (int64_t)part * per);
     const int cnt = (int)(min(units, u0 + per) - u0);
-    const uint8_t* run = a.img + 3 * a0 + 12 * u0;
     const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.img + 3 * a0, u0, cnt);
     if (S.shift == 16)
-        p1f_run<BH_UNROLL, true>(S, a.pp, rs, run, cnt, threadIdx.x, BH_THREADS);
+        p1f_run<true, BH_UNROLL, true>(S, a.pp, rs, cnt, threadIdx.x, BH_THREADS);
     else
-        p1f_run<BH_UNROLL, false>(S, a.pp, rs, run, cnt, threadIdx.x, BH_THREADS);
+        p1f_run<true, BH_UNROLL, false>(S, a.pp, rs, cnt, threadIdx.x, BH_THREADS);
     if (part == 0 && threadIdx.x == 0) {
         if (a1 > a0) {
             p1f_tail(S, a.pp, a.img + 3 * p0, (int)(a0 - p0));

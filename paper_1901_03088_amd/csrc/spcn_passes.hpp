@@ -264,9 +264,12 @@ __device__ void p1_merge(P1Lds<COPIES, COLS>& S, unsigned long long* ghist) {
 
 // ---------------------------------------------------------------- pass 1, byte-permute layout
 // The same exact counting with a table layout chosen so that every LDS address is one v_perm_b32
-// away from the pixel's dword: slot k (256 B) belongs to byte value k.
-//   region 0 (64 KB): R entry copy r at r*16, G entry copy r at 128 + r*16      (r = lane & 7)
-//   region 1 (64 KB): B entry copy r at r*16; the histogram words of bin k at 128 + j*64 + col*4
+// away from the pixel's dword: slot k (256 B) belongs to byte value k.  Two layouts:
+//   wide (two 64 KB regions, 8 table copies, 16 histogram columns):
+//     region 0: R entry copy r at r*16, G entry copy r at 128 + r*16                (r = lane & 7)
+//     region 1: B entry copy r at r*16; histogram words of bin k at 128 + j*64 + col*4
+//   narrow (one 64 KB region, 4 copies, 8 columns; two workgroups fit on a CU):
+//     R copy r at r*16, G at 64 + r*16, B at 128 + r*16, histogram at 192 + j*32 + col*4  (r = lane & 3)
 // An address is (value << 8) | (region << 16) | lane bits; the perm takes the value byte from the
 // pixel's dword and the lane/region bytes from a per-lane constant.  With 2^16 fixed-point units
 // (when the basis allows it, see table_shift) the bin is byte 2 of the clamped sum, so a bin
@@ -276,33 +279,41 @@ __device__ void p1_merge(P1Lds<COPIES, COLS>& S, unsigned long long* ghist) {
 // in the other layout) is near an edge k >= 1 iff y >= 0 and its low u bits are >= 2^u - 4, i.e.
 // iff (y & (sign | bits 2..u-1)) == bits 2..u-1, one AND and one compare.  Away from edges the bin
 // of y equals the bin of x, so bins are taken from y directly.
+template <bool WIDE>
+struct P1FLayout {
+    static constexpr int kCopies = WIDE ? 8 : 4;
+    static constexpr int kCols = WIDE ? 16 : 8;
+    static constexpr uint32_t kBytes = WIDE ? 2u * kHistBins * 256u : kHistBins * 256u;
+    static constexpr uint32_t kG = WIDE ? 128u : 64u;              // G entries within the slot
+    static constexpr uint32_t kBRegion = WIDE ? 0x10000u : 0u;     // region of the B entries
+    static constexpr uint32_t kB = WIDE ? 0u : 128u;               // B entries within the slot
+    static constexpr uint32_t kHRegion = WIDE ? 0x10000u : 0u;     // region of the histogram
+    static constexpr uint32_t kH = WIDE ? 128u : 192u;             // histogram words within the slot
+    static constexpr uint32_t kStain1 = 4u * kCols;                // stain 1 after stain 0's columns
+};
+
+template <bool WIDE>
 struct P1FLds {
-    int4 mem[2 * kHistBins * 16];   // 2 regions x 256 slots x 256 B
-    uint32_t zero[2][64];           // bin-0 counts, one word per lane: bin 0 is often shared by most
-                                    // lanes of a wavefront (an absent stain), so it gets its own row
+    int4 mem[P1FLayout<WIDE>::kBytes / 16];
     double od[3][kHistBins];        // FP64 optical densities of Eq. 1 for the near-edge path
     Basis64 B;
     int shift;                      // fixed-point resolution u (<= 16)
 };
-
-constexpr uint32_t kZeroRow = 2u * kHistBins * 256u;   // byte offset of P1FLds::zero from mem
-static_assert(offsetof(P1FLds, zero) == kZeroRow, "zero row follows the two table regions");
-
-constexpr uint32_t kRegion1 = 0x10000u;
-constexpr uint32_t kHistOff = 128u;
 
 // selector placing byte p of S0 in byte 1, S1's bytes 0 and 2 in bytes 0 and 2, zero in byte 3
 __device__ __forceinline__ constexpr uint32_t perm_sel(int p) { return 0x0c020000u | ((uint32_t)(4 + p) << 8); }
 
 __device__ __forceinline__ uint32_t p1f_hist_addr(int bin, uint32_t lh) { return ((uint32_t)bin << 8) | lh; }
 
-__device__ void p1f_setup(P1FLds& S, const float* w, const P1Params& pp, bool zero_hist) {
+template <bool WIDE>
+__device__ void p1f_setup(P1FLds<WIDE>& S, const float* w, const P1Params& pp, bool zero_hist) {
+    using Y = P1FLayout<WIDE>;
     const int tid = threadIdx.x;
     uint32_t* words = reinterpret_cast<uint32_t*>(S.mem);
     if (zero_hist) {
-        for (int i = tid; i < kHistBins * 32; i += blockDim.x)
-            words[(kRegion1 + (uint32_t)(i >> 5) * 256u + kHistOff) / 4 + (i & 31)] = 0u;
-        for (int i = tid; i < 128; i += blockDim.x) S.zero[i >> 6][i & 63] = 0u;
+        constexpr int per = 2 * Y::kCols;     // histogram words per slot
+        for (int i = tid; i < kHistBins * per; i += blockDim.x)
+            words[(Y::kHRegion + (uint32_t)(i / per) * 256u + Y::kH) / 4 + (i % per)] = 0u;
     }
     if (tid == 0) {
         derive_basis(w, pp.lambda, S.B);
@@ -324,8 +335,8 @@ __device__ void p1f_setup(P1FLds& S, const float* w, const P1Params& pp, bool ze
             e.y = __double2int_rn((S.B.q[0][c] * od + (c == 0 ? S.B.fconst[0] : 0.0)) * sig0) + g;
             e.z = __double2int_rn((S.B.pc[1][c] * od + (c == 0 ? S.B.pconst[1] : 0.0)) * sig1) + g;
             e.w = __double2int_rn((S.B.q[1][c] * od + (c == 0 ? S.B.fconst[1] : 0.0)) * sig1) + g;
-            const uint32_t off = (c == 2 ? kRegion1 : 0u) + (c == 1 ? 128u : 0u) + ((uint32_t)k << 8);
-            for (int r = 0; r < 8; ++r) *reinterpret_cast<int4*>(base + off + r * 16) = e;
+            const uint32_t off = (c == 0 ? 0u : c == 1 ? Y::kG : (Y::kBRegion | Y::kB)) + ((uint32_t)k << 8);
+            for (int r = 0; r < Y::kCopies; ++r) *reinterpret_cast<int4*>(base + off + r * 16) = e;
         }
     }
     __syncthreads();
@@ -338,61 +349,60 @@ __device__ __forceinline__ bool p1f_near(int32_t y, uint32_t nmask) {
 }
 
 // FP64 decision for one pixel known to be non-white; adds to the exact bins.
-__device__ __forceinline__ void p1f_exact(P1FLds& S, const P1Params& pp, uint32_t R, uint32_t G, uint32_t Bc,
+template <bool WIDE>
+__device__ __forceinline__ void p1f_exact(P1FLds<WIDE>& S, const P1Params& pp, uint32_t R, uint32_t G, uint32_t Bc,
                                           uint32_t lh) {
     double d0, d1;
     solve64(S.B, S.od[0][R], S.od[1][G], S.od[2][Bc], d0, d1);
     const double e0 = floor(d0 * (256.0 / (double)pp.hist_hi[0])), e1 = floor(d1 * (256.0 / (double)pp.hist_hi[1]));
     char* base = reinterpret_cast<char*>(S.mem);
     atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(e0 >= 255.0 ? 255 : (int)e0, lh)), 1u);
-    atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(e1 >= 255.0 ? 255 : (int)e1, lh) + 64), 1u);
+    atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(e1 >= 255.0 ? 255 : (int)e1, lh) +
+                                          P1FLayout<WIDE>::kStain1), 1u);
 }
 
 // Fixed-point (shifted) sums of one pixel from its three bytes (cold path and tail).
-__device__ __forceinline__ void p1f_sums(const P1FLds& S, uint32_t R, uint32_t G, uint32_t Bc, uint32_t r16,
+template <bool WIDE>
+__device__ __forceinline__ void p1f_sums(const P1FLds<WIDE>& S, uint32_t R, uint32_t G, uint32_t Bc, uint32_t r16,
                                          int32_t& x0, int32_t& x1) {
+    using Y = P1FLayout<WIDE>;
     const char* base = reinterpret_cast<const char*>(S.mem);
     const int4 a = *reinterpret_cast<const int4*>(base + ((R << 8) | r16));
-    const int4 b = *reinterpret_cast<const int4*>(base + ((G << 8) | r16) + 128);
-    const int4 c = *reinterpret_cast<const int4*>(base + (kRegion1 | (Bc << 8) | r16));
+    const int4 b = *reinterpret_cast<const int4*>(base + ((G << 8) | r16) + Y::kG);
+    const int4 c = *reinterpret_cast<const int4*>(base + (Y::kBRegion | (Bc << 8) | r16) + Y::kB);
     x0 = min(a.x + b.x + c.x, a.y + b.y + c.y);
     x1 = min(a.z + b.z + c.z, a.w + b.w + c.w);
 }
 
 // Per-lane constants of the byte-permute layout.
 struct P1FLane {
-    uint32_t r16, la, lb, lh, lh1, lz, lz1;
+    uint32_t r16, la, lb, lh, lh1;
 };
 
+template <bool WIDE>
 __device__ __forceinline__ P1FLane p1f_lane(int tid) {
+    using Y = P1FLayout<WIDE>;
     P1FLane L;
-    L.r16 = (uint32_t)(tid & 7) << 4;
+    L.r16 = (uint32_t)(tid & (Y::kCopies - 1)) << 4;
     L.la = L.r16;
-    L.lb = kRegion1 | L.r16;
-    L.lh = kRegion1 | (kHistOff + ((uint32_t)(tid & 15) << 2));   // stain 0 column word
-    L.lh1 = L.lh + 64u;                                             // stain 1
-    L.lz = kZeroRow + ((uint32_t)(tid & 63) << 2);
-    L.lz1 = L.lz + 256u;
+    L.lb = Y::kBRegion | L.r16;
+    L.lh = Y::kHRegion | (Y::kH + ((uint32_t)(tid & (Y::kCols - 1)) << 2));   // stain 0 column word
+    L.lh1 = L.lh + Y::kStain1;                                                 // stain 1
     return L;
 }
 
 // Counts the non-white pixels among UNROLL units of one thread: unit j is unit lb0 + j * nthreads
-// of a run of cnt units starting at src_run (for the byte-wise re-reads of near-edge pixels).
-template <int UNROLL, bool U16, bool ZROW>
-__device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P1FLane& L, const u32x3 (&cur)[UNROLL],
-                                          int lb0, int cnt, int nthreads, const uint8_t* src_run) {
+// of a run of cnt units (cur holds their bytes).
+template <bool WIDE, int UNROLL, bool U16>
+__device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L,
+                                          const u32x3 (&cur)[UNROLL], int lb0, int cnt, int nthreads) {
+    using Y = P1FLayout<WIDE>;
     const int u = U16 ? 16 : S.shift;
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(u);
     char* base = reinterpret_cast<char*>(S.mem);
     auto rd = [&](uint32_t addr) -> int4 { return *reinterpret_cast<const int4*>(base + addr); };
-    // ZROW: bin 0 (and below) -> this lane's zero-row word; otherwise the clamped bin's column word
-    auto bin_addr = [&](int32_t y, uint32_t lh, uint32_t lz) -> uint32_t {
-        if (ZROW) {
-            const uint32_t a = U16 ? __builtin_amdgcn_perm((uint32_t)min(y, 0xFFFFFF), lh, perm_sel(2))
-                                   : p1f_hist_addr(min(y >> u, kHistBins - 1), lh);
-            return y < (1 << u) ? lz : a;
-        }
+    auto bin_addr = [&](int32_t y, uint32_t lh) -> uint32_t {
         return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
                    : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
     };
@@ -400,12 +410,12 @@ __device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
         const bool valid = lb0 + j * nthreads < cnt;
-        const uint32_t X = cur[j].x, Y = cur[j].y, Z = cur[j].z;
+        const uint32_t X = cur[j].x, Y0 = cur[j].y, Z = cur[j].z;
         // R + G + B of the four pixels (byte dot products)
         int32_t sum[4];
         sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
-        sum[1] = (int32_t)__builtin_amdgcn_udot4(Y, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
-        sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y, 0x01010000u, 0u, false), false);
+        sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
+        sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
         sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
         bool tis[4];
         bool any = false;
@@ -417,15 +427,15 @@ __device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P
         if (any) {
             // table addresses: (word holding the byte, byte position) per pixel and channel
             const uint32_t aR[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(0)), __builtin_amdgcn_perm(X, L.la, perm_sel(3)),
-                                    __builtin_amdgcn_perm(Y, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
-            const uint32_t aG[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(1)), __builtin_amdgcn_perm(Y, L.la, perm_sel(0)),
-                                    __builtin_amdgcn_perm(Y, L.la, perm_sel(3)), __builtin_amdgcn_perm(Z, L.la, perm_sel(2))};
-            const uint32_t aB[4] = {__builtin_amdgcn_perm(X, L.lb, perm_sel(2)), __builtin_amdgcn_perm(Y, L.lb, perm_sel(1)),
+                                    __builtin_amdgcn_perm(Y0, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
+            const uint32_t aG[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(1)), __builtin_amdgcn_perm(Y0, L.la, perm_sel(0)),
+                                    __builtin_amdgcn_perm(Y0, L.la, perm_sel(3)), __builtin_amdgcn_perm(Z, L.la, perm_sel(2))};
+            const uint32_t aB[4] = {__builtin_amdgcn_perm(X, L.lb, perm_sel(2)), __builtin_amdgcn_perm(Y0, L.lb, perm_sel(1)),
                                     __builtin_amdgcn_perm(Z, L.lb, perm_sel(0)), __builtin_amdgcn_perm(Z, L.lb, perm_sel(3))};
             int32_t y0[4], y1[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int4 a = rd(aR[q]), b = rd(aG[q] + 128), c = rd(aB[q]);
+                const int4 a = rd(aR[q]), b = rd(aG[q] + Y::kG), c = rd(aB[q] + Y::kB);
                 y0[q] = min(a.x + b.x + c.x, a.y + b.y + c.y);
                 y1[q] = min(a.z + b.z + c.z, a.w + b.w + c.w);
             }
@@ -434,8 +444,8 @@ __device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P
                 const bool nr = p1f_near(y0[q], nmask) | p1f_near(y1[q], nmask);
                 near_waves |= __ballot(tis[q] & nr);
                 const uint32_t inc = (tis[q] & !nr) ? 1u : 0u;
-                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh, L.lz)), inc);
-                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1, L.lz1)), inc);
+                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
+                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
             }
         }
     }
@@ -455,16 +465,14 @@ __device__ __forceinline__ void p1f_units(P1FLds& S, const P1Params& pp, const P
             }
         }
     }
-    (void)src_run;
 }
 
-// Contiguous run of cnt units (buffer resource rs over its bytes, src_run its first byte): each
-// thread takes units tid, tid + nthreads, ..., UNROLL of them per iteration with one iteration of
-// prefetch.
-template <int UNROLL, bool U16>
-__device__ void p1f_run(P1FLds& S, const P1Params& pp, __amdgpu_buffer_rsrc_t rs, const uint8_t* src_run, int cnt,
-                        int tid, int nthreads) {
-    const P1FLane L = p1f_lane(tid);
+// Contiguous run of cnt units (buffer resource rs over its bytes): each thread takes units tid,
+// tid + nthreads, ..., UNROLL of them per iteration with one iteration of prefetch.
+template <bool WIDE, int UNROLL, bool U16>
+__device__ void p1f_run(P1FLds<WIDE>& S, const P1Params& pp, __amdgpu_buffer_rsrc_t rs, int cnt, int tid,
+                        int nthreads) {
+    const P1FLane L = p1f_lane<WIDE>(tid);
     const int stride = nthreads * UNROLL;
     u32x3 cur[UNROLL];
 #pragma unroll
@@ -474,7 +482,7 @@ __device__ void p1f_run(P1FLds& S, const P1Params& pp, __amdgpu_buffer_rsrc_t rs
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j)   // prefetch; past the run the loads return zeros
             nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb0 + stride + j * nthreads), 0, 0);
-        p1f_units<UNROLL, U16, false>(S, pp, L, cur, lb0, cnt, nthreads, src_run);
+        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, lb0, cnt, nthreads);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
     }
@@ -482,9 +490,10 @@ __device__ void p1f_run(P1FLds& S, const P1Params& pp, __amdgpu_buffer_rsrc_t rs
 
 // Grid-stride form: the image's units form tiles of nthreads * UNROLL units; workgroup b takes tiles
 // b, b + gridDim.x, ... so that the whole grid sweeps the image front to back together.
-template <int UNROLL, bool U16, bool ZROW>
-__device__ void p1f_tiles(P1FLds& S, const P1Params& pp, const uint8_t* src, int64_t n_units, int tid, int nthreads) {
-    const P1FLane L = p1f_lane(tid);
+template <bool WIDE, int UNROLL, bool U16>
+__device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* src, int64_t n_units, int tid,
+                          int nthreads) {
+    const P1FLane L = p1f_lane<WIDE>(tid);
     const int64_t tu = (int64_t)nthreads * UNROLL;
     const int64_t n_tiles = (n_units + tu - 1) / tu;
     int64_t t = blockIdx.x;
@@ -503,46 +512,45 @@ __device__ void p1f_tiles(P1FLds& S, const P1Params& pp, const uint8_t* src, int
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
         const int cnt = (int)min(tu, n_units - t * tu);
-        p1f_units<UNROLL, U16, ZROW>(S, pp, L, cur, tid, cnt, nthreads, src + 12 * t * tu);
+        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
     }
 }
 
 // Tail pixels (fewer than 4 after the last full unit) counted by one thread.
-__device__ void p1f_tail(P1FLds& S, const P1Params& pp, const uint8_t* px, int n) {
+template <bool WIDE>
+__device__ void p1f_tail(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* px, int n) {
     const int u = S.shift;
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(u);
-    const int tid = threadIdx.x;
-    const uint32_t r16 = (uint32_t)(tid & 7) << 4;
-    const uint32_t lh = kRegion1 | (kHistOff + ((uint32_t)(tid & 15) << 2));
+    const P1FLane L = p1f_lane<WIDE>(threadIdx.x);
     char* base = reinterpret_cast<char*>(S.mem);
     for (int i = 0; i < n; ++i) {
         const uint32_t R = px[3 * i], G = px[3 * i + 1], Bc = px[3 * i + 2];
         if ((int32_t)(R + G + Bc) >= thr) continue;
         int32_t y0, y1;
-        p1f_sums(S, R, G, Bc, r16, y0, y1);
+        p1f_sums(S, R, G, Bc, L.r16, y0, y1);
         if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) {
-            p1f_exact(S, pp, R, G, Bc, lh);
+            p1f_exact(S, pp, R, G, Bc, L.lh);
         } else {
-            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(min(max(y0 >> u, 0), kHistBins - 1), lh)), 1u);
-            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(min(max(y1 >> u, 0), kHistBins - 1), lh) + 64), 1u);
+            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(min(max(y0 >> u, 0), kHistBins - 1), L.lh)), 1u);
+            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_hist_addr(min(max(y1 >> u, 0), kHistBins - 1), L.lh1)), 1u);
         }
     }
 }
 
 // Adds the workgroup's LDS histogram to a global [2][256] uint64 histogram (barrier before).
-__device__ void p1f_merge(P1FLds& S, unsigned long long* ghist) {
+template <bool WIDE>
+__device__ void p1f_merge(P1FLds<WIDE>& S, unsigned long long* ghist) {
+    using Y = P1FLayout<WIDE>;
     __syncthreads();
     const uint32_t* words = reinterpret_cast<const uint32_t*>(S.mem);
     for (int t = threadIdx.x; t < 2 * kHistBins; t += blockDim.x) {
         const int j = t >> 8, k = t & (kHistBins - 1);
-        const uint32_t* row = words + (kRegion1 + (uint32_t)k * 256u + kHistOff + (uint32_t)j * 64u) / 4;
+        const uint32_t* row = words + (Y::kHRegion + (uint32_t)k * 256u + Y::kH + (uint32_t)j * Y::kStain1) / 4;
         uint32_t sum = 0;
-        for (int l = 0; l < 16; ++l) sum += row[(l + t) & 15];   // rotated: no bank conflicts
-        if (k == 0)
-            for (int l = 0; l < 64; ++l) sum += S.zero[j][l];
+        for (int l = 0; l < Y::kCols; ++l) sum += row[(l + t) & (Y::kCols - 1)];   // rotated: no bank conflicts
         if (sum) atomicAdd(ghist + t, (unsigned long long)sum);
     }
 }

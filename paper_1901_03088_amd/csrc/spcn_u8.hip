@@ -173,16 +173,17 @@ __global__ __launch_bounds__(THREADS) void k_pass2g(const P2Args a) {
         p2_tail(T, Kr, a.src + 12 * n_units, a.out + 12 * n_units, (int)(a.n_px - 4 * n_units));
 }
 
-// Grid-stride pass 1 with the byte-permute layout (see p1f_units); same counts as k_pass1.
-template <int UNROLL, bool ZROW>
-__global__ __launch_bounds__(P1_THREADS, 4) void k_pass1g(const P1Args a) {
-    __shared__ P1FLds S;
+// Grid-stride pass 1 with the byte-permute layouts (see p1f_units); same counts as k_pass1.
+// WIDE: one 1024-thread workgroup per CU; narrow: two 768-thread workgroups per CU.
+template <bool WIDE, int THREADS, int UNROLL, int WAVES>
+__global__ __launch_bounds__(THREADS, WAVES) void k_pass1g(const P1Args a) {
+    __shared__ P1FLds<WIDE> S;
     p1f_setup(S, a.w, a.pp, true);
     const int64_t n_units = a.n_px >> 2;
     if (S.shift == 16)
-        p1f_tiles<UNROLL, true, ZROW>(S, a.pp, a.src, n_units, threadIdx.x, P1_THREADS);
+        p1f_tiles<WIDE, UNROLL, true>(S, a.pp, a.src, n_units, threadIdx.x, THREADS);
     else
-        p1f_tiles<UNROLL, false, ZROW>(S, a.pp, a.src, n_units, threadIdx.x, P1_THREADS);
+        p1f_tiles<WIDE, UNROLL, false>(S, a.pp, a.src, n_units, threadIdx.x, THREADS);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         p1f_tail(S, a.pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
     p1f_merge(S, a.hist);
@@ -198,11 +199,12 @@ hipError_t run_pass1(const P1Args& a, const DevInfo& dev, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int UNROLL, bool ZROW>
-hipError_t run_pass1g(const P1Args& a, const DevInfo& dev, hipStream_t s) {
-    int64_t tiles = ((a.n_px >> 2) + (int64_t)P1_THREADS * UNROLL - 1) / ((int64_t)P1_THREADS * UNROLL);
-    int grid = (int)(tiles < 1 ? 1 : (tiles < dev.cus ? tiles : dev.cus));
-    hipLaunchKernelGGL((k_pass1g<UNROLL, ZROW>), dim3(grid), dim3(P1_THREADS), 0, s, a);
+template <bool WIDE, int THREADS, int UNROLL, int WAVES>
+hipError_t run_pass1g(const P1Args& a, int per_cu, const DevInfo& dev, hipStream_t s) {
+    int64_t tiles = ((a.n_px >> 2) + (int64_t)THREADS * UNROLL - 1) / ((int64_t)THREADS * UNROLL);
+    int64_t cap = (int64_t)dev.cus * per_cu;
+    int grid = (int)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
+    hipLaunchKernelGGL((k_pass1g<WIDE, THREADS, UNROLL, WAVES>), dim3(grid), dim3(THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -246,10 +248,10 @@ static hipError_t launch_pass1(const uint8_t* img, int64_t n_px, const float* w,
         case 3: return run_pass1<8, 16, 4, 4>(a, dev, s);
         case 4: return run_pass1<1, 32, 2, 8>(a, dev, s);
         case 5: return run_pass1<2, 16, 2, 8>(a, dev, s);
-        case 6: return run_pass1g<4, false>(a, dev, s);
-        case 7: return run_pass1g<2, false>(a, dev, s);
-        case 8: return run_pass1g<4, true>(a, dev, s);
-        default: return run_pass1g<2, true>(a, dev, s);
+        case 6: return run_pass1g<true, 1024, 4, 4>(a, 1, dev, s);
+        case 7: return run_pass1g<true, 1024, 2, 4>(a, 1, dev, s);
+        case 8: return run_pass1g<false, 768, 2, 6>(a, 2, dev, s);
+        default: return run_pass1g<false, 512, 2, 4>(a, 2, dev, s);
     }
 }
 
