@@ -20,9 +20,9 @@ namespace spcn {
 namespace {
 
 constexpr int RUN_THREADS = 1024;
-constexpr int RUN_UNROLL = 2;
+constexpr int RUN_UNROLL = 2;                 // pass-2 units per thread and iteration
+constexpr int RUN_P1_UNROLL = 1;              // pass-1 units per thread and iteration
 constexpr int MIN_CHUNK_LOG2 = 12;           // smallest work item: 4096 units = 16384 pixels
-constexpr int B_COPIES = 4, B_COLS = 32;      // pass-1 table copies / histogram columns
 constexpr uint32_t SPIN_LIMIT = 1u << 26;
 constexpr int MAX_TILES = 8192;
 
@@ -93,7 +93,8 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
     const int t = blockIdx.x;
     if (threadIdx.x == 0) {
         derive_basis(a.w_src + 6 * t, a.pp.lambda, B);
-        s_shift = table_shift(B, a.pp.i0, a.pp.hist_hi);
+        const int u = table_shift(B, a.pp.i0, a.pp.hist_hi);
+        s_shift = u < 16 ? u : 16;                 // the byte-permute layout works in <= 2^16 units
         const spcn_tile T = a.tiles[t];
         const int64_t n_px = T.height * T.width;
         TileInfo I;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
     const double sig0 = ldexp(256.0 / (double)a.pp.hist_hi[0], u), sig1 = ldexp(256.0 / (double)a.pp.hist_hi[1], u);
     for (int c = 0; c < 3; ++c) {
         const double od = B.ok ? od_u8((double)a.pp.i0[c], k) : 0.0;
-        const int g = c == 0 ? kGuardUnits : 0;
+        const int g = c == 0 ? kGuardUnits - 2 * kGuardUnits : 0;   // shifted guard of the byte-permute layout
         int4 e;
         e.x = __double2int_rn((B.pc[0][c] * od + (c == 0 ? B.pconst[0] : 0.0)) * sig0) + g;
         e.y = __double2int_rn((B.q[0][c] * od + (c == 0 ? B.fconst[0] : 0.0)) * sig0) + g;
@@ -211,7 +212,7 @@ struct RunArgs {
 };
 
 struct RunLds {
-    P1Lds<B_COPIES, B_COLS> p1;
+    P1FLds<true> p1;
     P2Lds<1> p2;
     FinalShared F;
     RecolourConsts K;
@@ -244,16 +245,28 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
 
         if (first) {
             // ---- pass 1 of one chunk: tables of the tile, LDS histogram, merge, maybe finalise
+            using Y = P1FLayout<true>;
             const int4* gt = a.w.tab + (int64_t)t * 3 * kHistBins;
-            for (int i = tid; i < 3 * kHistBins * B_COPIES; i += RUN_THREADS) S.p1.tab[i] = gt[i / B_COPIES];
-            for (int i = tid; i < 2 * kHistBins * B_COLS; i += RUN_THREADS) S.p1.hist[i] = 0u;
+            char* pb = reinterpret_cast<char*>(S.p1.mem);
+            for (int i = tid; i < 3 * kHistBins * Y::kCopies; i += RUN_THREADS) {
+                const int c = i / (kHistBins * Y::kCopies), k = (i / Y::kCopies) % kHistBins, r = i % Y::kCopies;
+                const uint32_t off = (c == 0 ? 0u : c == 1 ? Y::kG : (Y::kBRegion | Y::kB)) + ((uint32_t)k << 8);
+                *reinterpret_cast<int4*>(pb + off + r * 16) = gt[c * kHistBins + k];
+            }
+            uint32_t* words = reinterpret_cast<uint32_t*>(S.p1.mem);
+            for (int i = tid; i < kHistBins * 2 * Y::kCols; i += RUN_THREADS)
+                words[(Y::kHRegion + (uint32_t)(i / (2 * Y::kCols)) * 256u + Y::kH) / 4 + (i % (2 * Y::kCols))] = 0u;
+            for (int i = tid; i < 3 * kHistBins; i += RUN_THREADS)
+                S.p1.od[i / kHistBins][i % kHistBins] = od_u8((double)a.pp.i0[i / kHistBins], i % kHistBins);
             if (tid == 0) { S.p1.B = a.w.basis[t]; S.p1.shift = I.shift; }
             __syncthreads();
-            if (cnt > 0 && !I.bad)
-                p1_chunk<B_COPIES, B_COLS, RUN_UNROLL>(S.p1, a.pp, chunk_rsrc(T.src, u0, cnt), T.src + 12 * u0, cnt,
-                                                       tid, RUN_THREADS);
-            if (last_chunk && tid == 0 && I.tail && !I.bad) p1_tail(S.p1, a.pp, T.src + 12 * I.units, I.tail);
-            p1_merge(S.p1, reinterpret_cast<unsigned long long*>(a.w.hist + (int64_t)t * 2 * kHistBins));
+            if (cnt > 0 && !I.bad) {
+                const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(T.src, u0, cnt);
+                if (I.shift == 16) p1f_run<true, RUN_P1_UNROLL, true>(S.p1, a.pp, rs, cnt, tid, RUN_THREADS);
+                else p1f_run<true, RUN_P1_UNROLL, false>(S.p1, a.pp, rs, cnt, tid, RUN_THREADS);
+            }
+            if (last_chunk && tid == 0 && I.tail && !I.bad) p1f_tail(S.p1, a.pp, T.src + 12 * I.units, I.tail);
+            p1f_merge(S.p1, reinterpret_cast<unsigned long long*>(a.w.hist + (int64_t)t * 2 * kHistBins));
             __syncthreads();
             if (tid == 0) {
                 const uint32_t prev = __hip_atomic_fetch_add(&a.w.done[t], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
