@@ -340,8 +340,14 @@ def main() -> int:
         ws_s = S.workspace(S.workspace_size(S.OP_SAMPLE_PERCENTILE, 0, 0, n_samples), dev)
         ms_samp = timed(lambda: S.spcn_sample_percentile(img, w_fit, n_samples, 2024, p, p99_out=sp, ws=ws_s),
                         args.steps, args.warmup, stream)
+        ex = torch.empty(2, dtype=torch.float32, device=dev)
+        ws_x = S.workspace(S.workspace_size(S.OP_EXACT_PERCENTILE, 0, 0, 0), dev)
+        ms_exact = timed(lambda: S.spcn_exact_percentile(img, w_fit, p, p99_out=ex, ws=ws_x), args.steps, args.warmup,
+                         stream)
+        del ws_x
         _, st_g = S.spcn_normalize(img, w_fit, w_tgt, scale_tgt, p, out=out)
         res["extras"]["percentile_modes"] = {
+            "exact_order_statistic": [round(float(v), 5) for v in ex.cpu()], "exact_ms": round(ms_exact, 4),
             "global_hist": [round(float(v), 5) for v in st_g["p99_src"].cpu()],
             "band_median_1024_rows": [round(float(v), 5) for v in med.cpu()], "band_ms": round(ms_band, 4),
             "sample_200k": [round(float(v), 5) for v in sp.cpu()], "sample_ms": round(ms_samp, 4)}

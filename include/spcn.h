@@ -88,6 +88,7 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_SAMPLE_PERCENTILE 8   /* n_samples */
 #define SPCN_OP_BAND_PERCENTILES  9   /* n_items = number of bands */
 #define SPCN_OP_STREAM_NORMALIZE 10   /* n_px = image width, n_items = chunk_rows */
+#define SPCN_OP_EXACT_PERCENTILE 11   /* no size arguments: a fixed 256 MiB (+ 40 KiB) */
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
@@ -187,6 +188,21 @@ spcn_status spcn_sample_percentile(const uint8_t* img, int64_t height, int64_t w
                                    const spcn_params* p, int64_t n_samples, uint64_t seed,
                                    float* p99_out, int32_t* flags_out, void* ws, size_t ws_bytes,
                                    hipStream_t stream);
+
+/* spcn_exact_percentile: the exact order statistic of Eq. 3 over all non-white pixels (Sec. 3.1
+ * item 2), with no histogram interpolation: per stain the k-th smallest density (Eq. 2 with w fixed,
+ * p->lambda, evaluated in FP64), k = max(1, ceil(q n)) over the n non-white pixels (nearest rank).
+ * Two reads of the image: the exact histogram of spcn_densities (p->hist_hi only places the bins;
+ * any range gives the same value) finds the bin that holds rank k; a second pass counts the colours
+ * of the pixels in that bin, and a radix selection over the FP64 densities of those colours picks
+ * the value.
+ *   p99_out   device [2]: the selected FP64 density rounded to FP32 (0 without tissue)
+ *   flags_out device [2] or NULL: SPCN_FLAG_NO_TISSUE, SPCN_FLAG_BASIS
+ *   ws        spcn_workspace_size(SPCN_OP_EXACT_PERCENTILE, 0, 0, 0) bytes (about 256 MiB, whatever the
+ *             image size); calls that share a workspace must not overlap */
+spcn_status spcn_exact_percentile(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                  const spcn_params* p, float* p99_out, int32_t* flags_out, void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
 
 /* Pass 2 of spcn_normalize with the source percentiles given (device [2], from any of the modes
  * above or from the caller): s_j = scale_tgt_j / p99_src_j, or 1 (SPCN_FLAG_BIN0) where p99_src_j is

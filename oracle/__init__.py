@@ -65,6 +65,8 @@ def lib():
         L.orc_sample_percentile.restype = C.c_int
         L.orc_sample_percentile.argtypes = [_u8, C.c_int64, _d, _d, C.c_double, C.c_int, C.c_uint64, C.c_int64,
                                             C.c_int64, C.c_double, _d, _i64]
+        L.orc_exact_percentile_u8.restype = C.c_int
+        L.orc_exact_percentile_u8.argtypes = [_u8, C.c_int64, _d, _d, C.c_double, C.c_int, C.c_double, _d, _i64]
         L.orc_estimate_i0.restype = C.c_int64
         L.orc_estimate_i0.argtypes = [_u8, C.c_int64, C.c_int, C.c_uint64, C.c_int64, C.c_int64, C.c_double, _d]
         L.orc_nmf_objective.restype = C.c_double
@@ -248,6 +250,15 @@ def sample_percentile(img, W, n_s, seed, i0=(255, 255, 255), lam=0.01, white_sum
                                     C.c_uint64(seed & (2**64 - 1)), int(n_s), int(max_cand), q_of(percentile),
                                     _p(P, _d), _p(kept, _i64))
     return P, int(kept[0]), int(f)
+
+
+def exact_percentile(img, W, i0=(255, 255, 255), lam=0.01, white_sum=660, percentile=99.0):
+    """Nearest-rank percentile of the densities of all non-white pixels.  Returns (P (2,), n, flags)."""
+    a = _img(img); n = a.shape[0]
+    P = np.zeros(2); nt = np.zeros(1, dtype=np.int64)
+    f = lib().orc_exact_percentile_u8(_p(a, _u8), n, _p(basis(W), _d), _p(_vec(i0, 3), _d), float(lam),
+                                      int(white_sum), q_of(percentile), _p(P, _d), _p(nt, _i64))
+    return P, int(nt[0]), int(f)
 
 
 def estimate_i0(img, n_s=100000, seed=0, white_sum=660, percentile=80.0, max_cand=None, default=(255.0, 255.0, 255.0)):

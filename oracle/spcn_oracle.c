@@ -334,6 +334,20 @@ int orc_sample_percentile(const uint8_t* img, int64_t n_px, const double W[6], c
     return ORC_OK;
 }
 
+int orc_exact_percentile_u8(const uint8_t* img, int64_t n_px, const double W[6], const double i0[3],
+                            double lambda, int white_sum, double q, double P[2], int64_t* n_tissue) {
+    double* H = (double*)malloc(sizeof(double) * 2 * (size_t)(n_px > 0 ? n_px : 1));
+    uint8_t* mask = (uint8_t*)malloc((size_t)(n_px > 0 ? n_px : 1));
+    orc_densities_u8(img, n_px, W, i0, lambda, white_sum, H, mask);
+    int64_t n = 0;
+    for (int64_t i = 0; i < n_px; ++i) n += mask[i];
+    if (n_tissue) *n_tissue = n;
+    int flags = ORC_OK;
+    for (int j = 0; j < 2; ++j) flags |= orc_percentile_exact(H + j * n_px, mask, n_px, q, &P[j], NULL);
+    free(H); free(mask);
+    return flags;
+}
+
 static int cmp_int(const void* a, const void* b) {
     int x = *(const int*)a, y = *(const int*)b;
     return (x > y) - (x < y);

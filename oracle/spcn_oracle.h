@@ -98,6 +98,13 @@ int orc_sample_percentile(const uint8_t* img, int64_t n_px, const double W[6], c
                           double lambda, int white_sum, uint64_t seed, int64_t n_s, int64_t max_cand,
                           double q, double P[2], int64_t* kept);
 
+/* Exact percentile of all non-white pixels (Eq. 3 over the pixels of Sec. 3.1 item 2, no histogram):
+ * per stain the nearest-rank q order statistic of the FP64 densities (Eq. 2, W fixed) of the
+ * non-white pixels.  *n_tissue receives their number; with none, P = 0 and ORC_NO_TISSUE is
+ * returned. */
+int orc_exact_percentile_u8(const uint8_t* img, int64_t n_px, const double W[6], const double i0[3],
+                            double lambda, int white_sum, double q, double P[2], int64_t* n_tissue);
+
 /* Per-pixel normalized intensity before rounding (used by the tests to locate rounding ties). */
 void orc_reconstruct_pixel(const double h[2], const double W_tgt[6], const double s[2],
                            const double i0_out[3], double y[3]);

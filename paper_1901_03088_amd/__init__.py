@@ -28,7 +28,7 @@ FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_
     1, 2, 4, 8, 16, 32, 64, 128
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
     OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES, \
-    OP_STREAM_NORMALIZE = range(11)
+    OP_STREAM_NORMALIZE, OP_EXACT_PERCENTILE = range(12)
 HIST_BINS = 256
 OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
@@ -64,6 +64,7 @@ _SIGS = {
     "spcn_estimate_i0": (C.c_int, [_vp, _i64, _i64, _i64, _u64, _i32, _f, _vp, _vp, _vp, _sz, _vp]),
     "spcn_band_percentiles": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_sample_percentile": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _u64, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_exact_percentile": (C.c_int, [_vp, _i64, _i64, _vp, _P, _vp, _vp, _vp, _sz, _vp]),
     "spcn_recolor_p99": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _vp]),
     "spcn_normalize_streamed": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _i64, _vp, _vp, _sz, _vp,
                                           _vp, _vp]),
@@ -306,6 +307,23 @@ def spcn_sample_percentile(img: torch.Tensor, w: torch.Tensor, n_samples: int, s
     _check(_L.spcn_sample_percentile(_ptr(img), H, W_, _ptr(w), C.byref(p), int(n_samples),
                                      C.c_uint64(seed & (2**64 - 1)), _ptr(p99_out), _ptr(flags), wsp, wsn, _stream()),
            "spcn_sample_percentile")
+    return p99_out, flags
+
+
+def spcn_exact_percentile(img: torch.Tensor, w: torch.Tensor, p: spcn_params | None = None, p99_out=None,
+                          ws=None):
+    """Exact nearest-rank percentile of the densities of all non-white pixels.  Returns (p99 [2], flags [2])."""
+    _dev(img, torch.uint8, "img"); _dev(w, torch.float32, "w")
+    p = p or params()
+    H, W_ = int(img.shape[0]), int(img.shape[1])
+    dev = img.device
+    p99_out = p99_out if p99_out is not None else torch.empty(2, dtype=torch.float32, device=dev)
+    flags = torch.empty(2, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(workspace_size(OP_EXACT_PERCENTILE, 0, 0, 0), dev)
+    wsp, wsn = _ws_ptr(ws)
+    _check(_L.spcn_exact_percentile(_ptr(img), H, W_, _ptr(w), C.byref(p), _ptr(p99_out), _ptr(flags), wsp, wsn,
+                                    _stream()), "spcn_exact_percentile")
     return p99_out, flags
 
 

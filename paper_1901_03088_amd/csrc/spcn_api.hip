@@ -156,6 +156,8 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
             return n_items <= kMaxBands ? band_workspace_bytes(n_items) : 0;
         case SPCN_OP_STREAM_NORMALIZE:
             return stream_workspace_bytes(n_px, n_items);
+        case SPCN_OP_EXACT_PERCENTILE:
+            return exact_workspace_bytes();
         default:
             return 0;
     }
@@ -310,6 +312,21 @@ spcn_status spcn_sample_percentile(const uint8_t* img, int64_t height, int64_t w
     hipError_t e = launch_sample_percentile(img, height * width, w, make_params(p), n_samples, seed, p99_out,
                                             flags_out, ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_sample_percentile launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_exact_percentile(const uint8_t* img, int64_t height, int64_t width, const float* w,
+                                  const spcn_params* p, float* p99_out, int32_t* flags_out, void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_image(img, height, width, "img"));
+    SPCN_CHECK(check_params(p, true));
+    if (!w) return fail(SPCN_E_ARG, "w is NULL");
+    if (!p99_out) return fail(SPCN_E_ARG, "p99_out is NULL");
+    SPCN_CHECK(check_ws(ws, ws_bytes, exact_workspace_bytes()));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_exact_percentile(img, height * width, w, make_params(p), p99_out, flags_out, ws, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_exact_percentile launch");
     return SPCN_OK;
 }
 

@@ -74,6 +74,10 @@ hipError_t launch_zero_hist(uint64_t* hist, hipStream_t s);
 // pass 1 adding to hist (not cleared)
 hipError_t launch_count(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, uint64_t* hist,
                         const DevInfo& dev, hipStream_t s);
+// exact order statistic over all non-white pixels (colour table + radix selection)
+size_t exact_workspace_bytes();
+hipError_t launch_exact_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
+                                   float* p99_out, int32_t* flags_out, void* ws, const DevInfo& dev, hipStream_t s);
 size_t stream_workspace_bytes(int64_t width, int64_t chunk_rows);
 hipError_t launch_stream_normalize(const uint8_t* host_src, uint8_t* host_out, int64_t height, int64_t width,
                                    const float* w_src, const float* w_tgt, const float* scale_tgt,

@@ -163,3 +163,20 @@ def test_streamed_rejects(lib):
                      (dict(cin=C.c_void_p(0)), "copy streams"), (dict(h=0), "height")):
         assert call(**kw) in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
         assert frag in lib._L.spcn_last_error().decode(), (kw, lib._L.spcn_last_error())
+
+
+def test_exact_percentile_rejects(lib):
+    """Argument checks of spcn_exact_percentile run on the host before any launch."""
+    p = lib.params()
+    need = lib.workspace_size(lib.OP_EXACT_PERCENTILE, 0, 0, 0)
+    assert need >= 2 * (1 << 24) * 8
+    img, w, out, ws = C.c_void_p(1 << 20), C.c_void_p(1 << 24), C.c_void_p(1 << 25), C.c_void_p(1 << 28)
+    for args, frag in (((None, 8, 8, w, C.byref(p), out, None, ws, need, None), "img is NULL"),
+                       ((img, 8, 8, None, C.byref(p), out, None, ws, need, None), "w is NULL"),
+                       ((img, 8, 8, w, C.byref(p), None, None, ws, need, None), "p99_out is NULL"),
+                       ((img, 0, 8, w, C.byref(p), out, None, ws, need, None), "height and width"),
+                       ((img, 8, 8, w, C.byref(p), out, None, ws, need - 1, None), "workspace"),
+                       ((img, 8, 8, w, C.byref(p), out, None, None, need, None), "workspace")):
+        st = lib._L.spcn_exact_percentile(*args)
+        assert st in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
+        assert frag in lib._L.spcn_last_error().decode()

@@ -115,3 +115,77 @@ def test_modes_against_global_on_config1(S):
     print(f"\n[modes] global {g} band-median {med.cpu().numpy()} sample {sp.cpu().numpy()}")
     assert np.allclose(med.cpu().numpy(), g, rtol=0.1)
     assert np.allclose(sp.cpu().numpy(), g, rtol=0.1)
+
+
+def _close32(g, o):
+    """FP64 values on both sides (closed form on the GPU, enumeration in the oracle), reported as
+    FP32: equal unless the two FP64 results straddle an FP32 rounding boundary (one ulp)."""
+    o32 = np.asarray(o).astype(np.float32)
+    return np.all(np.abs(np.asarray(g, np.float32) - o32) <= np.spacing(np.maximum(np.abs(o32), np.float32(1e-30))))
+
+
+@pytest.mark.parametrize("seed,h,w,kw", [
+    (0, 1024, 1024, {}),
+    (1, 333, 257, {}),                                   # ragged: tail of 1 pixel
+    (2, 1, 3, {}),                                       # three pixels, all in the tail
+    (3, 50, 7, dict(percentile=50.0)),
+    (4, 200, 300, dict(percentile=100.0)),
+    (5, 256, 256, dict(hist_hi=(0.25, 0.25))),           # rank k in the overflow bin
+    (6, 256, 200, dict(lam=0.0)),
+    (7, 128, 128, dict(white_sum=0)),                    # every pixel counts
+    (8, 300, 200, dict(hist_hi=(16.0, 16.0), percentile=1.0)),
+])
+def test_exact_percentile_matches_oracle(S, orc, seed, h, w, kw):
+    d = synth.make_image(seed, h, w, device=DEV)
+    p = S.params(**kw)
+    W = S.as_basis(d["W"], DEV)
+    P, flags = S.spcn_exact_percentile(d["img"], W, p)
+    torch.cuda.synchronize()
+    o_P, n, o_f = orc.exact_percentile(d["img"].cpu().numpy(), orc.f32(orc.basis(d["W"])),
+                                       lam=orc.f32(p.lambda_), white_sum=p.white_sum, percentile=p.percentile)
+    print(f"\n[exact] seed {seed} {h}x{w} {kw}: n {n} gpu {P.cpu().numpy()} oracle {o_P}")
+    assert _close32(P.cpu().numpy(), o_P), (P, o_P)
+    assert (flags.cpu().numpy() & S.FLAG_NO_TISSUE).any() == bool(o_f & 1)
+
+
+def test_exact_percentile_special_images(S, orc):
+    """Constant colour (every rank is that colour's density), no tissue, and two calls in a row on
+    one workspace (the colour table is cleared by each call)."""
+    W = S.as_basis(synth.reference_basis(), DEV)
+    Wn = orc.f32(orc.basis(synth.reference_basis()))
+    ws = S.workspace(S.workspace_size(S.OP_EXACT_PERCENTILE, 0, 0, 0), DEV)
+    col = torch.tensor([140, 80, 160], dtype=torch.uint8, device=DEV).expand(64, 96, 3).contiguous()
+    for q in (0.5, 99.0, 100.0):
+        P, fl = S.spcn_exact_percentile(col, W, S.params(percentile=q), ws=ws)
+        torch.cuda.synchronize()
+        Hc, _ = orc.densities_u8(col[:1, :1].cpu().numpy(), Wn)
+        assert _close32(P.cpu().numpy(), Hc[:, 0]) and int(fl.cpu().numpy().max()) == 0
+    white = torch.full((32, 32, 3), 250, dtype=torch.uint8, device=DEV)
+    P, fl = S.spcn_exact_percentile(white, W, ws=ws)
+    torch.cuda.synchronize()
+    assert P.cpu().tolist() == [0.0, 0.0] and (fl.cpu().numpy() & S.FLAG_NO_TISSUE).all()
+    for seed, hw in ((11, (512, 384)), (12, (100, 77))):
+        d = synth.make_image(seed, *hw, device=DEV)
+        P, _ = S.spcn_exact_percentile(d["img"], S.as_basis(d["W"], DEV), ws=ws)
+        torch.cuda.synchronize()
+        o_P, _, _ = orc.exact_percentile(d["img"].cpu().numpy(), orc.f32(orc.basis(d["W"])), lam=orc.f32(0.01))
+        assert _close32(P.cpu().numpy(), o_P)
+
+
+def test_exact_percentile_on_config1(S, orc):
+    """8192^2 image: the exact order statistic against numpy's selection over the oracle's FP64
+    densities of all tissue pixels, and within one bin width of the histogram percentile."""
+    d = synth.config1(device=DEV)
+    p = S.params()
+    W = S.as_basis(d["W"], DEV)
+    P, fl = S.spcn_exact_percentile(d["img"], W, p)
+    _, st = S.spcn_normalize(d["img"], W, W, torch.ones(2, device=DEV), p)
+    torch.cuda.synchronize()
+    H, m = orc.densities_u8(d["img"].cpu().numpy(), orc.f32(orc.basis(d["W"])), lam=orc.f32(p.lambda_))
+    t = m.astype(bool)
+    o_P = np.array([np.percentile(H[j][t], 99, method="inverted_cdf") for j in range(2)])
+    del H
+    g = P.cpu().numpy()
+    print(f"\n[exact] config1: gpu {g} oracle {o_P} histogram {st['p99_src'].cpu().numpy()}")
+    assert _close32(g, o_P)
+    assert np.all(np.abs(g - st["p99_src"].cpu().numpy()) <= 4.0 / 256)

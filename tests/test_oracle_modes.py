@@ -92,3 +92,41 @@ def test_recolor_given_percentiles(orc):
     one = orc.recolor_u8(img, Ws, Wt, sc, [0.0, 0.0])
     ref = orc.recolor_u8(img, Ws, Wt, [1.0, 1.0], [1.0, 1.0])
     assert np.array_equal(one, ref)
+
+
+def test_exact_percentile_pins(orc):
+    """The exact order statistic over all non-white pixels: numpy's inverted-CDF percentile of the
+    tissue densities; within one bin width of the histogram percentile (Eq. 3 read through the
+    histogram); white pixels do not enter; q = 100 gives the maximum, a tiny q the minimum; a
+    constant colour gives its own density for any q; no tissue gives 0 and the flag."""
+    d = synth.make_image(5, 97, 131)
+    img = d["img"].numpy()
+    W = orc.f32(orc.basis(d["W"]))
+    P, n, f = orc.exact_percentile(img, W)
+    H, m = orc.densities_u8(img, W)
+    t = m.astype(bool)
+    assert n == int(t.sum()) and f == 0
+    for j in range(2):
+        assert P[j] == np.percentile(H[j][t], 99, method="inverted_cdf")
+        # nearest rank by a plain sort of the tissue densities
+        vals = sorted(H[j][t].tolist())
+        k = max(1, int(np.ceil(orc.q_of(99.0) * n)))
+        assert P[j] == vals[k - 1]
+    Ph = global_P(orc, img, W)
+    assert np.all(np.abs(P - Ph) <= 4.0 / 256)
+    Pmax, _, _ = orc.exact_percentile(img, W, percentile=100.0)
+    Pmin, _, _ = orc.exact_percentile(img, W, percentile=1e-6)
+    assert np.array_equal(Pmax, H[:, t].max(1)) and np.array_equal(Pmin, H[:, t].min(1))
+    # extra white rows change nothing
+    img_w = np.concatenate([img, np.full((13, 131, 3), 250, np.uint8)])
+    assert np.array_equal(orc.exact_percentile(img_w, W)[0], P)
+    # white_sum = 0: every pixel counts
+    P0, n0, _ = orc.exact_percentile(img, W, white_sum=0)
+    assert n0 == img.shape[0] * img.shape[1]
+    assert P0[0] == np.percentile(H[0], 99, method="inverted_cdf")
+    col = np.broadcast_to(np.array((140, 80, 160), np.uint8), (9, 11, 3)).copy()
+    Hc, _ = orc.densities_u8(col[:1, :1], W)
+    for q in (0.5, 50.0, 100.0):
+        assert np.array_equal(orc.exact_percentile(col, W, percentile=q)[0], Hc[:, 0])
+    Pw, nw, fw = orc.exact_percentile(np.full((5, 5, 3), 252, np.uint8), W)
+    assert nw == 0 and fw & 1 and list(Pw) == [0.0, 0.0]
