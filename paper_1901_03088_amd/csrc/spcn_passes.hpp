@@ -406,7 +406,11 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
         return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
                    : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
     };
-    uint64_t near_waves = 0;   // wave-uniform: some lane has a near-edge non-white pixel
+    // Lanes without a non-white pixel skip the table reads and histogram adds (exec mask).  Every lane
+    // predicate is a plain compare whose ballot is its scalar mask; the masks are combined in scalar
+    // registers and turned into the 0/1 increment by one select (a ballot of a combined predicate
+    // would cost two vector instructions per pixel).
+    uint64_t near_waves = 0;   // lanes with a near-edge non-white pixel
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
         const bool valid = lb0 + j * nthreads < cnt;
@@ -417,14 +421,9 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
         sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
         sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
         sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
-        bool tis[4];
-        bool any = false;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            tis[q] = valid && sum[q] < thr;
-            any |= tis[q];
-        }
-        if (any) {
+        const int32_t darkest = min(min(sum[0], sum[1]), min(sum[2], sum[3]));
+        const uint64_t valid_lanes = __ballot(valid);
+        if (valid && darkest < thr) {   // this lane has a non-white pixel
             // table addresses: (word holding the byte, byte position) per pixel and channel
             const uint32_t aR[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(0)), __builtin_amdgcn_perm(X, L.la, perm_sel(3)),
                                     __builtin_amdgcn_perm(Y0, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
@@ -441,9 +440,12 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const bool nr = p1f_near(y0[q], nmask) | p1f_near(y1[q], nmask);
-                near_waves |= __ballot(tis[q] & nr);
-                const uint32_t inc = (tis[q] & !nr) ? 1u : 0u;
+                // ballots of plain compares are their scalar masks: the predicates are combined in
+                // scalar registers and turned into the 0/1 increment by one select
+                const uint64_t white = __ballot(sum[q] >= thr);
+                const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
+                near_waves |= nr & ~white & valid_lanes;
+                const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
                 atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
                 atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
             }
@@ -488,34 +490,52 @@ __device__ void p1f_run(P1FLds<WIDE>& S, const P1Params& pp, __amdgpu_buffer_rsr
     }
 }
 
-// Grid-stride form: the image's units form tiles of nthreads * UNROLL units; workgroup b takes tiles
-// b, b + gridDim.x, ... so that the whole grid sweeps the image front to back together.
+// Grid-stride form: the image's units form tiles of nthreads * UNROLL units.  Workgroup b takes the
+// tiles of sequence positions b, b + gridDim.x, ...; position t holds tile (t * scatter) mod n_tiles.
+// With scatter = 1 the grid sweeps the image front to back; a scatter near 0.618 n_tiles (coprime
+// with n_tiles, so the map is a permutation) spreads the tiles in flight over the whole image, so
+// compute-heavy tissue tiles and memory-bound background tiles run side by side instead of in
+// alternating phases.  step = (gridDim.x * scatter) mod n_tiles advances a workgroup's tile.
 template <bool WIDE, int UNROLL, bool U16>
 __device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* src, int64_t n_units, int tid,
-                          int nthreads) {
+                          int nthreads, int64_t scatter, int64_t step) {
     const P1FLane L = p1f_lane<WIDE>(tid);
     const int64_t tu = (int64_t)nthreads * UNROLL;
     const int64_t n_tiles = (n_units + tu - 1) / tu;
     int64_t t = blockIdx.x;
     if (t >= n_tiles) return;
-    auto tile_rs = [&](int64_t tt) {   // one descriptor built from selected fields (stays scalar)
+    int64_t ph = (t * scatter) % n_tiles;       // tile at sequence position t
+    auto tile_rs = [&](int64_t tt, int64_t tile) {   // one descriptor built from selected fields (stays scalar)
         const bool in = tt < n_tiles;
-        return chunk_rsrc(src, in ? tt * tu : 0, in ? min(tu, n_units - tt * tu) : 0);
+        return chunk_rsrc(src, in ? tile * tu : 0, in ? min(tu, n_units - tile * tu) : 0);
     };
-    __amdgpu_buffer_rsrc_t rs = tile_rs(t);
+    __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
     u32x3 cur[UNROLL];
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
     for (; t < n_tiles; t += gridDim.x) {
-        const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x);   // empty past the end: loads return zeros
+        int64_t pn = ph + step;
+        if (pn >= n_tiles) pn -= n_tiles;
+        const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);   // empty past the end: loads return zeros
         u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
-        const int cnt = (int)min(tu, n_units - t * tu);
+        const int cnt = (int)min(tu, n_units - ph * tu);
         p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+        ph = pn;
     }
+}
+
+// Multiplier of the tile permutation above: 1 when the grid covers every tile at once, else the
+// first integer from floor(0.618 n_tiles) up that is coprime with n_tiles.
+inline int64_t tile_scatter(int64_t n_tiles, int64_t grid) {
+    if (n_tiles <= grid || n_tiles < 3) return 1;
+    auto gcd = [](int64_t a, int64_t b) { while (b) { const int64_t r = a % b; a = b; b = r; } return a; };
+    int64_t k = (int64_t)(0.6180339887498949 * (double)n_tiles);
+    while (gcd(k, n_tiles) != 1) ++k;
+    return k;
 }
 
 // Tail pixels (fewer than 4 after the last full unit) counted by one thread.

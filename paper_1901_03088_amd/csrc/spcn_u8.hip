@@ -26,6 +26,7 @@ struct P1Args {
     const float* w;
     P1Params pp;
     unsigned long long* hist;      // global [2][256]
+    int64_t scatter, step;         // tile permutation of the grid-stride kernels (p1f_tiles)
 };
 
 // WAVES: minimum waves per SIMD the compiler must allow (register budget); 4 = one workgroup per CU,
@@ -181,9 +182,9 @@ __global__ __launch_bounds__(THREADS, WAVES) void k_pass1g(const P1Args a) {
     p1f_setup(S, a.w, a.pp, true);
     const int64_t n_units = a.n_px >> 2;
     if (S.shift == 16)
-        p1f_tiles<WIDE, UNROLL, true>(S, a.pp, a.src, n_units, threadIdx.x, THREADS);
+        p1f_tiles<WIDE, UNROLL, true>(S, a.pp, a.src, n_units, threadIdx.x, THREADS, a.scatter, a.step);
     else
-        p1f_tiles<WIDE, UNROLL, false>(S, a.pp, a.src, n_units, threadIdx.x, THREADS);
+        p1f_tiles<WIDE, UNROLL, false>(S, a.pp, a.src, n_units, threadIdx.x, THREADS, a.scatter, a.step);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         p1f_tail(S, a.pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
     p1f_merge(S, a.hist);
@@ -204,7 +205,10 @@ hipError_t run_pass1g(const P1Args& a, int per_cu, const DevInfo& dev, hipStream
     int64_t tiles = ((a.n_px >> 2) + (int64_t)THREADS * UNROLL - 1) / ((int64_t)THREADS * UNROLL);
     int64_t cap = (int64_t)dev.cus * per_cu;
     int grid = (int)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
-    hipLaunchKernelGGL((k_pass1g<WIDE, THREADS, UNROLL, WAVES>), dim3(grid), dim3(THREADS), 0, s, a);
+    P1Args b = a;
+    b.scatter = tile_scatter(tiles, grid);
+    b.step = tiles > 0 ? ((int64_t)grid * b.scatter) % tiles : 0;
+    hipLaunchKernelGGL((k_pass1g<WIDE, THREADS, UNROLL, WAVES>), dim3(grid), dim3(THREADS), 0, s, b);
     return hipGetLastError();
 }
 
