@@ -317,11 +317,11 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
  *                              5 = (2, 16, 2, 2); 6, 7 = byte-permute table layout (8 copies,
  *                              16 columns), grid-stride tiles, 4 or 2 units per thread and
  *                              iteration; 8, 9 = narrow byte-permute layout (4 copies, 8 columns,
- *                              64 KB) with two 768- or 512-thread workgroups per CU
+ *                              64 KB) with two 768- or 512-thread workgroups per CU (default 6)
  *   SPCN_OPT_P2_VARIANT        pass-2 table copies / workgroup size, contiguous chunks: 0 = (1, 256),
  *                              1 = (4, 256), 2 = (16, 1024); grid-stride tiles: 3 = (1, 256),
- *                              4 = (1, 512), 5 = (16, 1024)
- *   SPCN_OPT_P2_BLOCKS_PER_CU  pass-2 workgroups per compute unit, 1..16
+ *                              4 = (1, 512), 5 = (16, 1024) (default 3)
+ *   SPCN_OPT_P2_BLOCKS_PER_CU  pass-2 workgroups per compute unit, 1..16 (default 8)
  *   SPCN_OPT_BATCH_CHUNK       batched normalisation: log2 of the 4-pixel units in one work item,
  *                              12..16 (default 15 = 131072 pixels)
  * spcn_set_option returns SPCN_E_ARG for an unknown option or a value out of range. */

@@ -109,7 +109,7 @@ def test_workspace_sizes(lib):
 def test_options_ranges(lib):
     """Tuning options: defaults, accepted ranges, rejection of unknown options and bad values."""
     saved = [lib.get_option(o) for o in range(4)]
-    assert saved == [0, 0, 8, 15]
+    assert saved == [6, 3, 8, 15]
     try:
         for opt, lo, hi in ((lib.OPT_P1_VARIANT, 0, 9), (lib.OPT_P2_VARIANT, 0, 5),
                             (lib.OPT_P2_BLOCKS_PER_CU, 1, 16), (lib.OPT_BATCH_CHUNK, 12, 16)):

@@ -106,14 +106,21 @@ def test_histogram_exhaustive_rgb_cube(S, orc, case):
         p = S.params(white_sum=0, hist_hi=(1.0, 0.5))
     img = torch.from_numpy(cube).to(DEV)
     w = S.as_basis(W, DEV)
-    _, hist, p99, _ = S.spcn_densities(img, w, p, want_h=False)
-    torch.cuda.synchronize()
     H, m = orc.densities_u8(cube, orc.f32(orc.basis(W)), list(p.i0), orc.f32(p.lambda_), p.white_sum)
     ohist = orc.histogram(H, m, list(p.hist_hi), 256)
-    ghist = hist.cpu().numpy().astype(np.uint64)
-    diff = (ghist.astype(np.int64) - ohist.astype(np.int64))
-    print(f"[cube {case}] total={int(ohist.sum())} abs diff sum={int(np.abs(diff).sum())}", flush=True)
-    assert np.array_equal(ghist, ohist)
+    saved = S.get_option(S.OPT_P1_VARIANT)
+    try:
+        for v in range(10):   # every pass-1 layout and tile order (the cube spans many tiles of each)
+            S.set_option(S.OPT_P1_VARIANT, v)
+            _, hist, p99, _ = S.spcn_densities(img, w, p, want_h=False)
+            torch.cuda.synchronize()
+            ghist = hist.cpu().numpy().astype(np.uint64)
+            diff = (ghist.astype(np.int64) - ohist.astype(np.int64))
+            print(f"[cube {case} variant {v}] total={int(ohist.sum())} abs diff sum={int(np.abs(diff).sum())}",
+                  flush=True)
+            assert np.array_equal(ghist, ohist), v
+    finally:
+        S.set_option(S.OPT_P1_VARIANT, saved)
 
 
 # ------------------------------------------------------------------ fused normalisation
