@@ -139,7 +139,6 @@ __device__ inline void nmf_basis(const double* W, double lambda, NmfBasis& B) {
 // f = G^-1 b, p_j = b_j / g_jj (valid because g01 >= 0 for a non-negative W).  Columns of zero
 // norm give zero densities.
 __device__ inline void nmf_solve(const NmfBasis& B, double v0, double v1, double v2, double& h0, double& h1) {
-#pragma clang fp contract(off)
     const double* W = B.w;
     double b0 = W[0] * v0; b0 = b0 + W[1] * v1; b0 = b0 + W[2] * v2; b0 = b0 - B.half_lambda;
     double b1 = W[3] * v0; b1 = b1 + W[4] * v1; b1 = b1 + W[5] * v2; b1 = b1 - B.half_lambda;
