@@ -271,8 +271,10 @@ spcn_status spcn_estimate_i0(const uint8_t* img, int64_t height, int64_t width, 
         return fail(SPCN_E_ARG, "percentile = %g must lie in (0, 100]", (double)percentile);
     if (!i0_out) return fail(SPCN_E_ARG, "i0_out is NULL");
     SPCN_CHECK(check_ws(ws, ws_bytes, i0_workspace_bytes(n_samples)));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_estimate_i0(img, height * width, white_sum, n_samples, seed, (double)percentile / 100.0,
-                                      i0_out, flags_out, ws, stream);
+                                      i0_out, flags_out, ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_estimate_i0 launch");
     return SPCN_OK;
 }

@@ -273,25 +273,29 @@ struct SampleArgs {
     int64_t* idx;           // [n_s] kept pixel indices
 };
 
+// Grid-stride over the round's candidate groups (SAMPLE_BLOCK candidates each), so that a round
+// made unnecessary by earlier ones costs one small launch.
 __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_round(SampleArgs a) {
     __shared__ int s_wave[SAMPLE_BLOCK / 64];
     if (a.bw->n_acc >= a.bw->n_s) return;                  // earlier rounds found enough
-    const int64_t t = a.t0 + (int64_t)blockIdx.x * SAMPLE_BLOCK + threadIdx.x;
-    bool keep = false;
-    int64_t pix = 0;
-    if (t < a.t_end) {
-        pix = candidate_pixel(a.seed, (uint64_t)t, a.n_px);
-        if (a.background) {
-            const uint8_t* q = a.img + 3 * pix;
-            keep = (int32_t)q[0] + (int32_t)q[1] + (int32_t)q[2] > a.white_sum;
-        } else {
-            keep = non_white(a.img, pix, a.white_sum);
+    for (int64_t b = blockIdx.x; b < a.nb; b += gridDim.x) {
+        const int64_t t = a.t0 + b * SAMPLE_BLOCK + threadIdx.x;
+        bool keep = false;
+        int64_t pix = 0;
+        if (t < a.t_end) {
+            pix = candidate_pixel(a.seed, (uint64_t)t, a.n_px);
+            if (a.background) {
+                const uint8_t* q = a.img + 3 * pix;
+                keep = (int32_t)q[0] + (int32_t)q[1] + (int32_t)q[2] > a.white_sum;
+            } else {
+                keep = non_white(a.img, pix, a.white_sum);
+            }
         }
+        int total;
+        const int r = block_rank(keep, s_wave, &total);
+        if (keep) a.staging[b * SAMPLE_BLOCK + r] = pix;
+        if (threadIdx.x == 0) a.counts[b] = total;
     }
-    int total;
-    int r = block_rank(keep, s_wave, &total);
-    if (keep) a.staging[(int64_t)blockIdx.x * SAMPLE_BLOCK + r] = pix;
-    if (threadIdx.x == 0) a.counts[blockIdx.x] = total;
 }
 
 // Exclusive scan of the round's per-workgroup counts (one workgroup), in place: counts[b] becomes
@@ -344,11 +348,21 @@ __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_copy(SampleArgs a) {
     const int base = bw->base;
     const int64_t room = bw->n_s - base;
     if (room <= 0) return;
-    const int b = blockIdx.x;
-    const int64_t off = a.counts[b];
-    const int64_t c = a.counts[b + 1] - off;   // kept in this workgroup
-    const int i = threadIdx.x;
-    if (i < c && off + i < room) a.idx[base + off + i] = a.staging[(int64_t)b * SAMPLE_BLOCK + i];
+    for (int64_t b = blockIdx.x; b < a.nb; b += gridDim.x) {
+        const int64_t off = a.counts[b];
+        const int64_t c = a.counts[b + 1] - off;   // kept in this candidate group
+        const int i = threadIdx.x;
+        if (i < c && off + i < room) a.idx[base + off + i] = a.staging[b * SAMPLE_BLOCK + i];
+    }
+}
+
+// One sampling round: draw, scan, append (the three kernels above).
+static void launch_round(const SampleArgs& a, const DevInfo& dev, hipStream_t s) {
+    const int64_t cap = (int64_t)dev.cus * 4;
+    const unsigned grid = (unsigned)(a.nb < cap ? a.nb : cap);
+    hipLaunchKernelGGL(k_sample_round, dim3(grid), dim3(SAMPLE_BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_sample_copy, dim3(grid), dim3(SAMPLE_BLOCK), 0, s, a);
 }
 
 __global__ void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init) {
@@ -697,9 +711,7 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
         SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
                      counts, idx};
-        hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
-        hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        launch_round(a, dev, s);
         t0 += rc;
     }
     hipLaunchKernelGGL(k_od_gather, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s, img, idx,
@@ -776,7 +788,8 @@ size_t i0_workspace_bytes(int64_t n_s) {
 }
 
 hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
-                              double q, float* i0_out, int32_t* flags_out, void* ws, hipStream_t s) {
+                              double q, float* i0_out, int32_t* flags_out, void* ws, const DevInfo& dev,
+                              hipStream_t s) {
     uint8_t* p = static_cast<uint8_t*>(ws);
     BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
     const int64_t nbmax = max_round_blocks(n_s);
@@ -792,9 +805,7 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
         SampleArgs a{img, n_px, white_sum, seed, 1, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
                      counts, idx};
-        hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
-        hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        launch_round(a, dev, s);
         t0 += rc;
     }
     hipLaunchKernelGGL(k_i0_hist, dim3((unsigned)hmin((n_s + 1023) / 1024, 128)), dim3(1024), 0, s, img,
@@ -871,9 +882,7 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
         SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
                      counts, idx};
-        hipLaunchKernelGGL(k_sample_round, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, s, a);
-        hipLaunchKernelGGL(k_sample_copy, dim3((unsigned)a.nb), dim3(SAMPLE_BLOCK), 0, s, a);
+        launch_round(a, dev, s);
         t0 += rc;
     }
     hipLaunchKernelGGL(k_sample_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,

@@ -98,7 +98,8 @@ hipError_t launch_recolor_p99(const uint8_t* src, int64_t n_px, const float* w_s
                               hipStream_t s);
 size_t i0_workspace_bytes(int64_t n_samples);
 hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
-                              double q, float* i0_out, int32_t* flags_out, void* ws, hipStream_t s);
+                              double q, float* i0_out, int32_t* flags_out, void* ws, const DevInfo& dev,
+                              hipStream_t s);
 hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, const ParamsK& pk,
                                          float lambda_nmf, int64_t n_samples, uint64_t seed,
                                          int32_t n_iter, const float* w_init, float* w_out,
