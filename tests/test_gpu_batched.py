@@ -138,3 +138,59 @@ def test_batched_pipeline_graph_replay(S, orc):
         for t in range(len(shapes)):
             assert torch.equal(eager[t], outs[t]), (rep, t)
         assert torch.equal(Wg, W_eager)
+
+
+def test_batched_full_size(S, orc):
+    """The 512-tile workload (sides 256..2048 in steps of 64, 698 Mpixel) through the benchmark's
+    pipeline: every tile's basis fit from 4096 samples against the oracle's fit on the same samples,
+    every tile's percentile and flags equal to the oracle's (exact histograms), and 2048 seeded
+    output pixels per tile recoloured by the oracle one by one."""
+    import math
+    p = S.params()
+    shapes = synth.tile_shapes(512)
+    tiles, srcs, outs = make_batch(shapes)
+    tgt = synth.target_image(device=DEV)
+    wt = S.as_basis(tgt["W"], DEV)
+    _, _, sc, _ = S.spcn_densities(tgt["img"], wt, p, want_h=False)
+    table = S.tile_table(srcs, outs)
+    total = sum(h * w for h, w in shapes)
+    W, _, fl_fit = S.spcn_estimate_basis_batched(table, len(shapes), 4096, seed=30000, p=p, lambda_nmf=0.1,
+                                                 n_iter=50)
+    st = S.spcn_normalize_batched(table, len(shapes), total, W, wt, sc, p)
+    torch.cuda.synchronize()
+    Wc = W.cpu().numpy(); p99 = st["p99"].cpu().numpy(); flags = st["flags"].cpu().numpy()
+    assert (fl_fit.cpu().numpy() == 0).all()
+    scn = sc.cpu().numpy().astype(np.float64)
+    Wtn = orc.f32(orc.basis(tgt["W"]))
+    H0 = np.array([0.65, 0.70, 0.29]); E0 = np.array([0.07, 0.99, 0.11])
+    W_init = orc.f32(np.stack([H0 / np.linalg.norm(H0), E0 / np.linalg.norm(E0)], axis=1))
+    rng = np.random.default_rng(9)
+    worst_ang, n_px, n_off = 0.0, 0, 0
+    for t in range(len(shapes)):
+        img = srcs[t].cpu().numpy()
+        idx = orc.sample_tissue(img, 4096, 30000 + t, p.white_sum)
+        Wo, _, _ = orc.nmf(orc.od_samples(img, idx, list(p.i0)), orc.f32(0.1), 50, W_init, p.percentile)
+        a = np.asarray(Wc[t], np.float64).reshape(2, 3); b = np.asarray(Wo, np.float64).reshape(2, 3)
+        for j in range(2):
+            worst_ang = max(worst_ang, math.acos(min(1.0, a[j] @ b[j] / (np.linalg.norm(a[j]) * np.linalg.norm(b[j])))))
+        Wn = orc.f32(orc.basis(Wc[t]))
+        H, m = orc.densities_u8(img, Wn, list(p.i0), orc.f32(p.lambda_), p.white_sum)
+        hist = orc.histogram(H, m, list(p.hist_hi), 256)
+        del H
+        P, fl = [], []
+        for j in range(2):
+            Pj, f, _ = orc.percentile_hist(hist[j], float(p.hist_hi[j]), orc.q_of(p.percentile))
+            P.append(Pj); fl.append(f)
+        assert np.array_equal(p99[t], np.array(P).astype(np.float32)), t
+        assert np.array_equal(flags[t], np.array(fl)), t
+        flat = img.reshape(-1, 3)
+        sel = rng.integers(0, flat.shape[0], 2048)
+        o = orc.recolor_u8(flat[sel].reshape(-1, 1, 3), Wn, Wtn, scn, np.array(P), lam=orc.f32(p.lambda_))
+        g = outs[t].cpu().numpy().reshape(-1, 3)[sel]
+        d = np.abs(o.reshape(-1, 3).astype(np.int32) - g.astype(np.int32)).max(axis=1)
+        assert (d <= 1).all(), t
+        n_px += d.size; n_off += int((d > 0).sum())
+    print(f"\n[batched 512] worst basis angle {worst_ang:.2e} rad; sampled pixels {n_px}, off by one {n_off}",
+          flush=True)
+    assert worst_ang < 1e-6
+    assert n_off / n_px <= 0.02
