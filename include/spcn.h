@@ -146,7 +146,7 @@ spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, cons
  * without host synchronisation and `compute` completes after the last copy.  The result equals
  * spcn_normalize of the whole slide byte for byte.
  *   host_src, host_out  uint8 HWC, 3*height*width bytes of pinned host memory (hipHostMalloc or
- *                       equivalent; pageable memory serialises the copies)
+ *                       equivalent; pageable memory serialises the copies); they must not overlap
  *   chunk_rows          rows per chunk, at most 2^30 pixels per chunk
  *   st                  optional device statistics (hist is ignored: the histogram lives in ws)
  *   ws                  device workspace of spcn_workspace_size(SPCN_OP_STREAM_NORMALIZE, width,
@@ -206,7 +206,8 @@ spcn_status spcn_exact_percentile(const uint8_t* img, int64_t height, int64_t wi
 
 /* Pass 2 of spcn_normalize with the source percentiles given (device [2], from any of the modes
  * above or from the caller): s_j = scale_tgt_j / p99_src_j, or 1 (SPCN_FLAG_BIN0) where p99_src_j is
- * not > 0.  scale_out [2] and flags_out [2] (device) may be NULL.  No workspace. */
+ * not > 0.  Other arguments as for spcn_normalize (out may not alias src).  scale_out [2] and
+ * flags_out [2] (device) may be NULL.  No workspace. */
 spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
                              const float* w_tgt, const float* scale_tgt, const float* i0_out,
                              const spcn_params* p, const float* p99_src, uint8_t* out,

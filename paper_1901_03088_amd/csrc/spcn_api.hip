@@ -32,24 +32,23 @@ spcn_status hip_fail(hipError_t e, const char* what) {
     return fail(SPCN_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
+// Compute-unit count of the current device, queried once per device (thread-safe: a relaxed atomic
+// per device, 0 until known; concurrent first calls may both query, and store the same value).
 spcn_status dev_info(DevInfo* out) {
-    static int cached_id[64];
-    static int cached_cus[64];
-    static bool have[64] = {false};
+    static std::atomic<int> cached_cus[64];
     int id = 0;
     hipError_t e = hipGetDevice(&id);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (id < 0 || id >= 64) return fail(SPCN_E_UNSUPPORTED, "device id %d out of range", id);
-    if (!have[id]) {
-        int cus = 0;
+    int cus = cached_cus[id].load(std::memory_order_relaxed);
+    if (cus == 0) {
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, id);
         if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(MultiprocessorCount)");
-        cached_cus[id] = cus > 0 ? cus : 1;
-        cached_id[id] = id;
-        have[id] = true;
+        cus = cus > 0 ? cus : 1;
+        cached_cus[id].store(cus, std::memory_order_relaxed);
     }
-    out->id = cached_id[id];
-    out->cus = cached_cus[id];
+    out->id = id;
+    out->cus = cus;
     return SPCN_OK;
 }
 
@@ -341,8 +340,13 @@ spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, 
     SPCN_CHECK(check_params(p, true));
     if (!w_src || !w_tgt || !scale_tgt) return fail(SPCN_E_ARG, "w_src, w_tgt and scale_tgt must be non-NULL");
     if (!p99_src) return fail(SPCN_E_ARG, "p99_src is NULL");
+    const int64_t n = height * width;
+    if ((const void*)src < (const void*)(out + 3 * n) && (const void*)out < (const void*)(src + 3 * n))
+        return fail(SPCN_E_ARG, "out must not overlap src");
     float io[3];
     for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_recolor_p99(src, height * width, w_src, w_tgt, scale_tgt, io, make_params(p), out, p99_src,
@@ -368,8 +372,13 @@ spcn_status spcn_normalize_streamed(const uint8_t* host_src, uint8_t* host_out, 
     SPCN_CHECK(check_ws(ws, ws_bytes, stream_workspace_bytes(width, chunk_rows)));
     if (copy_in == compute || copy_out == compute)
         return fail(SPCN_E_ARG, "copy streams must differ from the compute stream");
+    const int64_t n = height * width;
+    if ((const void*)host_src < (const void*)(host_out + 3 * n) && (const void*)host_out < (const void*)(host_src + 3 * n))
+        return fail(SPCN_E_ARG, "host_out must not overlap host_src");
     float io[3];
     for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
+    for (int c = 0; c < 3; ++c)
+        if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_stream_normalize(host_src, host_out, height, width, w_src, w_tgt, scale_tgt, io,

@@ -160,7 +160,8 @@ def test_streamed_rejects(lib):
                                               C.c_void_p(1 << 24), C.c_void_p(1 << 24), None, C.byref(p), a["rows"],
                                               None, C.c_void_p(1 << 28), a["wsn"], a["comp"], a["cin"], a["cout"])
     for kw, frag in ((dict(src=None), "host_src"), (dict(rows=0), "chunk_rows"), (dict(wsn=64), "workspace"),
-                     (dict(cin=C.c_void_p(0)), "copy streams"), (dict(h=0), "height")):
+                     (dict(cin=C.c_void_p(0)), "copy streams"), (dict(h=0), "height"),
+                     (dict(out=C.c_void_p((1 << 20) + 4)), "overlap")):
         assert call(**kw) in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
         assert frag in lib._L.spcn_last_error().decode(), (kw, lib._L.spcn_last_error())
 
@@ -180,3 +181,14 @@ def test_exact_percentile_rejects(lib):
         st = lib._L.spcn_exact_percentile(*args)
         assert st in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
         assert frag in lib._L.spcn_last_error().decode()
+
+
+def test_recolor_p99_rejects(lib):
+    p = lib.params()
+    src, w, sc, P = C.c_void_p(1 << 20), C.c_void_p(1 << 24), C.c_void_p(1 << 25), C.c_void_p(1 << 26)
+    def call(out, io=None):
+        return lib._L.spcn_recolor_p99(src, 16, 16, w, w, sc, io, C.byref(p), P, out, None, None, None)
+    assert call(C.c_void_p((1 << 20) + 12)) == lib.SPCN_E_ARG
+    assert "overlap" in lib._L.spcn_last_error().decode()
+    assert call(C.c_void_p(1 << 22), (C.c_float * 3)(255.0, -1.0, 255.0)) == lib.SPCN_E_ARG
+    assert "i0_out" in lib._L.spcn_last_error().decode()
