@@ -88,7 +88,7 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_SAMPLE_PERCENTILE 8   /* n_samples */
 #define SPCN_OP_BAND_PERCENTILES  9   /* n_items = number of bands */
 #define SPCN_OP_STREAM_NORMALIZE 10   /* n_px = image width, n_items = chunk_rows */
-#define SPCN_OP_EXACT_PERCENTILE 11   /* no size arguments: a fixed 256 MiB (+ 40 KiB) */
+#define SPCN_OP_EXACT_PERCENTILE 11   /* no size arguments: a fixed 2^28 + 37120 bytes */
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
