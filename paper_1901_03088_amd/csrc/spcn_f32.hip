@@ -10,19 +10,22 @@
 //   k_fw_bin      per (sample, stain): the coarse bin holding rank k = max(1, ceil(q n)) and the rank
 //                 inside it;
 //   k_fw_collect  appends (value, index) of every non-white pixel in that bin to a candidate list;
-//   k_fw_select   per (sample, stain): sorts the candidates (value, then index), takes the rank; if the
-//                 list overflowed, an exact radix select over the whole sample instead; writes P,
-//                 the selected index (smallest index holding P), scale and recolouring constants;
+//   k_fw_select   per (sample, stain): radix selection of the rank among the candidates' values, then
+//                 the smallest index holding that value; if the list overflowed, the same selection
+//                 over the whole sample; writes P, the selected index, scale and recolouring constants;
 //   k_fw_recon    Eqs. 3-4 from the stored densities.
 // Backward (W_src fixed; the mask and the rank selection are piecewise constant)
 //   k_bw_main     per pixel: ubar_c = -y_c gbar_c; hbar_j = s_j sum_c Wt[c,j] ubar_c; on the active set F
 //                 of the pixel's KKT system vbar = W_F G_FF^-1 hbar_F; xbar_c = -vbar_c / x_c where the
-//                 OD is not clamped; per-workgroup FP64 partial sums of dWt and ds;
+//                 OD is not clamped; partial sums of dWt and ds (FP32 over a thread's few pixels, FP64
+//                 across threads and workgroups);
 //   k_bw_reduce   per sample: ordered sums -> dWt, dS = ds / P; the percentile's adjoint
 //                 Pbar_j = -(s_j / P_j) ds_j enters through the selected pixel's density (added to
 //                 its input gradient).
 #include "spcn_internal.h"
 #include "spcn_device.hpp"
+
+#include <cmath>
 
 namespace spcn {
 
@@ -40,11 +43,12 @@ struct F32Basis {          // FP32 constants of one sample's solve and recolouri
     float a[2];            // g01/g00, g01/g11
     float w[6];            // source basis (backward)
     float g00, g01, g11, det;
+    float r_det, r00, r11;  // reciprocals of det, g00, g11 (0 for a singular basis)
     float i0[3], log2i0[3];
     int ok;
 };
 
-__device__ inline void f32_basis(const float* w, float lambda, const float i0[3], F32Basis& F) {
+__device__ inline void f32_basis(const float* w, float lambda, const float i0[3], const float log2i0[3], F32Basis& F) {
     Basis64 B;
     derive_basis(w, lambda, B);
     for (int j = 0; j < 2; ++j) {
@@ -54,7 +58,10 @@ __device__ inline void f32_basis(const float* w, float lambda, const float i0[3]
     }
     for (int i = 0; i < 6; ++i) F.w[i] = w[i];
     F.g00 = (float)B.g00; F.g01 = (float)B.g01; F.g11 = (float)B.g11; F.det = (float)B.det;
-    for (int c = 0; c < 3; ++c) { F.i0[c] = i0[c]; F.log2i0[c] = (float)log2((double)i0[c]); }
+    F.r_det = B.ok ? (float)(1.0 / B.det) : 0.0f;
+    F.r00 = B.g00 > 0.0 ? (float)(1.0 / B.g00) : 0.0f;
+    F.r11 = B.g11 > 0.0 ? (float)(1.0 / B.g11) : 0.0f;
+    for (int c = 0; c < 3; ++c) { F.i0[c] = i0[c]; F.log2i0[c] = log2i0[c]; }
     F.ok = B.ok;
 }
 
@@ -109,6 +116,7 @@ struct FwArgs {
     const float* w_tgt; int64_t w_tgt_stride;
     const float* scale_tgt; int64_t scale_stride;
     float i0[3], i0_out[3], lambda;
+    float log2i0[3], log2io[3];   // log2 of i0 and i0_out (host-computed)
     int32_t white_sum;
     double q;
     float* hstore;           // [n][2][n_px]
@@ -129,6 +137,27 @@ __global__ void k_fw_clear(FwArgs a) {
     }
 }
 
+// V pixels per thread and iteration: 4 when every plane is 16-byte aligned (n_px % 4 == 0 and aligned
+// base pointers; one 16-byte access per plane), else 1.
+template <int V>
+struct Vec;
+template <>
+struct Vec<1> {
+    static __device__ __forceinline__ void load(const float* p, float (&v)[1]) { v[0] = *p; }
+    static __device__ __forceinline__ void store(float* p, const float (&v)[1]) { *p = v[0]; }
+};
+template <>
+struct Vec<4> {
+    static __device__ __forceinline__ void load(const float* p, float (&v)[4]) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+    static __device__ __forceinline__ void store(float* p, const float (&v)[4]) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+
+template <int V>
 __global__ __launch_bounds__(FT) void k_fw_dens(FwArgs a) {
     __shared__ uint32_t s_hist[2 * NBIN];
     __shared__ F32Basis F;
@@ -136,23 +165,34 @@ __global__ __launch_bounds__(FT) void k_fw_dens(FwArgs a) {
     const int64_t s = blockIdx.y;
     for (int i = threadIdx.x; i < 2 * NBIN; i += FT) s_hist[i] = 0u;
     if (threadIdx.x == 0) {
-        f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, F);
+        f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, a.log2i0, F);
         s_count = 0;
     }
     __syncthreads();
     const float* x = a.x + s * 3 * a.n_px;
     float* hs = a.hstore + s * 2 * a.n_px;
     uint32_t cnt = 0;
-    for (int64_t i = blockIdx.x * (int64_t)FT + threadIdx.x; i < a.n_px; i += (int64_t)gridDim.x * FT) {
-        Px p;
-        solve_px(F, x[i], x[a.n_px + i], x[2 * a.n_px + i], a.white_sum, p);
-        hs[i] = p.tissue ? p.h0 : -p.h0;
-        hs[a.n_px + i] = p.tissue ? p.h1 : -p.h1;
-        if (p.tissue) {
-            ++cnt;
-            atomicAdd(&s_hist[coarse_bin(p.h0)], 1u);
-            atomicAdd(&s_hist[NBIN + coarse_bin(p.h1)], 1u);
+    const int64_t nq = a.n_px / V;
+    for (int64_t q = blockIdx.x * (int64_t)FT + threadIdx.x; q < nq; q += (int64_t)gridDim.x * FT) {
+        const int64_t i = q * V;
+        float x0[V], x1[V], x2[V], h0[V], h1[V];
+        Vec<V>::load(x + i, x0);
+        Vec<V>::load(x + a.n_px + i, x1);
+        Vec<V>::load(x + 2 * a.n_px + i, x2);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            Px p;
+            solve_px(F, x0[k], x1[k], x2[k], a.white_sum, p);
+            h0[k] = p.tissue ? p.h0 : -p.h0;
+            h1[k] = p.tissue ? p.h1 : -p.h1;
+            if (p.tissue) {
+                ++cnt;
+                atomicAdd(&s_hist[coarse_bin(p.h0)], 1u);
+                atomicAdd(&s_hist[NBIN + coarse_bin(p.h1)], 1u);
+            }
         }
+        Vec<V>::store(hs + i, h0);
+        Vec<V>::store(hs + a.n_px + i, h1);
     }
     atomicAdd(&s_count, cnt);
     __syncthreads();
@@ -168,56 +208,142 @@ __device__ inline int64_t pct_rank(double q, int64_t n) {
     return k < 1 ? 1 : (k > n ? n : k);
 }
 
+// Inclusive prefix sum of one value per thread over the first 256 threads of the workgroup (wave
+// scans, then the totals of the preceding waves); s_wsum holds 4 words.  Barriers inside.
+__device__ inline uint32_t scan256(uint32_t v, uint32_t* s_wsum) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t up = __shfl_up(incl, o);
+        if (lane >= o) incl += up;
+    }
+    if (tid < 256 && lane == 63) s_wsum[tid >> 6] = incl;
+    __syncthreads();
+    if (tid < 256)
+        for (int w = 0; w < (tid >> 6); ++w) incl += s_wsum[w];
+    __syncthreads();
+    return incl;
+}
+
 __global__ __launch_bounds__(FT) void k_fw_bin(FwArgs a) {
-    __shared__ uint32_t s_part[FT];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ int s_g;
+    __shared__ uint32_t s_below;
     const int64_t s = blockIdx.x >> 1;
     const int j = blockIdx.x & 1;
+    const int tid = threadIdx.x;
     const uint32_t* h = a.chist + (s * 2 + j) * NBIN;
-    const int per = NBIN / FT;
+    constexpr int per = NBIN / FT;             // bins per thread (FT == 256)
     uint32_t sum = 0;
-    for (int i = 0; i < per; ++i) sum += h[threadIdx.x * per + i];
-    s_part[threadIdx.x] = sum;
+#pragma unroll
+    for (int i = 0; i < per; ++i) sum += h[tid * per + i];
+    const int64_t n = a.st[s].n_tissue;
+    const int64_t k = n > 0 ? pct_rank(a.q, n) : 0;
+    const uint32_t incl = scan256(sum, s_wsum);
+    if (tid == 0) s_g = -1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t n = a.st[s].n_tissue;
+    if (n > 0 && (int64_t)(incl - sum) < k && k <= (int64_t)incl) { s_g = tid; s_below = incl - sum; }
+    __syncthreads();
+    if (tid < 64) {   // the crossing group's bins, one lane each
+        const int g = s_g;
         int32_t bin = -1, rin = 0;
-        if (n > 0) {
-            const int64_t k = pct_rank(a.q, n);
-            int64_t acc = 0;
-            int t = 0;
-            while (acc + (int64_t)s_part[t] < k) { acc += s_part[t]; ++t; }
-            int b = t * per;
-            while (acc + (int64_t)h[b] < k) { acc += h[b]; ++b; }
-            bin = b;
-            rin = (int32_t)(k - acc);
+        if (g >= 0) {
+            const uint32_t c = tid < per ? h[g * per + tid] : 0u;
+            uint32_t in = c;
+            for (int o = 1; o < per; o <<= 1) {
+                const uint32_t up = __shfl_up(in, o);
+                if (tid >= o) in += up;
+            }
+            const int64_t kk = k - s_below;
+            const bool mine = tid < per && (int64_t)(in - c) < kk && kk <= (int64_t)in;
+            const uint64_t m = __ballot(mine);
+            const int who = m ? __ffsll((unsigned long long)m) - 1 : 0;
+            const uint32_t before = __shfl(in - c, who);
+            bin = g * per + who;
+            rin = (int32_t)(kk - before);
         }
-        a.st[s].bin[j] = bin;
-        a.st[s].rank_in_bin[j] = rin;
+        if (tid == 0) {
+            a.st[s].bin[j] = bin;
+            a.st[s].rank_in_bin[j] = rin;
+        }
     }
 }
 
+template <int V>
 __global__ __launch_bounds__(FT) void k_fw_collect(FwArgs a) {
     const int64_t s = blockIdx.y;
     const int b0 = a.st[s].bin[0], b1 = a.st[s].bin[1];
     const float* hs = a.hstore + s * 2 * a.n_px;
-    for (int64_t i = blockIdx.x * (int64_t)FT + threadIdx.x; i < a.n_px; i += (int64_t)gridDim.x * FT) {
-        const float v0 = hs[i], v1 = hs[a.n_px + i];
-        if (!(__float_as_uint(v0) >> 31) && coarse_bin(v0) == b0) {
-            const uint32_t slot = atomicAdd(&a.st[s].n_cand[0], 1u);
-            if (slot < CAP) a.cand[(s * 2) * CAP + slot] = ((uint64_t)__float_as_uint(v0) << 32) | (uint64_t)i;
-        }
-        if (!(__float_as_uint(v1) >> 31) && coarse_bin(v1) == b1) {
-            const uint32_t slot = atomicAdd(&a.st[s].n_cand[1], 1u);
-            if (slot < CAP) a.cand[(s * 2 + 1) * CAP + slot] = ((uint64_t)__float_as_uint(v1) << 32) | (uint64_t)i;
+    const int64_t nq = a.n_px / V;
+    for (int64_t q = blockIdx.x * (int64_t)FT + threadIdx.x; q < nq; q += (int64_t)gridDim.x * FT) {
+        float v0[V], v1[V];
+        Vec<V>::load(hs + q * V, v0);
+        Vec<V>::load(hs + a.n_px + q * V, v1);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const uint64_t i = (uint64_t)(q * V + k);
+            if (!(__float_as_uint(v0[k]) >> 31) && coarse_bin(v0[k]) == b0) {
+                const uint32_t slot = atomicAdd(&a.st[s].n_cand[0], 1u);
+                if (slot < CAP) a.cand[(s * 2) * CAP + slot] = ((uint64_t)__float_as_uint(v0[k]) << 32) | i;
+            }
+            if (!(__float_as_uint(v1[k]) >> 31) && coarse_bin(v1[k]) == b1) {
+                const uint32_t slot = atomicAdd(&a.st[s].n_cand[1], 1u);
+                if (slot < CAP) a.cand[(s * 2 + 1) * CAP + slot] = ((uint64_t)__float_as_uint(v1[k]) << 32) | i;
+            }
         }
     }
 }
 
-// Exact selection for one (sample, stain).  Keys are (value bits, index): non-negative floats order
-// like their bit patterns, so sorting the 64-bit keys orders by value, then by index.
+// Exact selection for one (sample, stain): a radix selection (four 8-bit digits, most significant
+// first) of the rank among the candidate values (non-negative floats order like their bit patterns),
+// then the smallest index holding the selected value.  The candidates are every non-white pixel of
+// the coarse bin that holds the rank, so they hold every pixel of that value.  If the list
+// overflowed, the same selection runs over all of the sample's non-white values.
+// (blockDim.x >= 256; the digit holding rank kk is found by a parallel prefix sum of the 256 counts)
+template <typename Get>
+__device__ uint32_t radix_select(int64_t n_items, Get get, int64_t k, uint32_t* s_h, uint32_t* s_wsum, int* s_misc) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint32_t prefix = 0, pmask = 0;
+    int64_t kk = k;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += blockDim.x) s_h[b] = 0;
+        __syncthreads();
+        for (int64_t i = tid; i < n_items; i += blockDim.x) {
+            uint32_t u;
+            if (get(i, u) && (u & pmask) == prefix) atomicAdd(&s_h[(u >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        uint32_t cnt = 0, incl = 0;
+        if (tid < 256) {
+            cnt = s_h[tid];
+            incl = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t up = __shfl_up(incl, o);
+                if (lane >= o) incl += up;
+            }
+            if (lane == 63) s_wsum[tid >> 6] = incl;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            for (int w = 0; w < (tid >> 6); ++w) incl += s_wsum[w];
+            const uint32_t excl = incl - cnt;
+            if ((int64_t)excl < kk && kk <= (int64_t)incl) {   // exactly one digit holds rank kk
+                s_misc[0] = tid;
+                s_misc[1] = (int)(kk - excl);
+            }
+        }
+        __syncthreads();
+        prefix |= (uint32_t)s_misc[0] << shift;
+        pmask |= 255u << shift;
+        kk = s_misc[1];
+        __syncthreads();
+    }
+    return prefix;
+}
+
 __global__ __launch_bounds__(1024) void k_fw_select(FwArgs a) {
-    __shared__ uint64_t s_key[CAP];
     __shared__ uint32_t s_h[256];
+    __shared__ uint32_t s_wsum[4];
     __shared__ int s_misc[2];
     const int64_t s = blockIdx.x >> 1;
     const int j = blockIdx.x & 1;
@@ -228,74 +354,27 @@ __global__ __launch_bounds__(1024) void k_fw_select(FwArgs a) {
     int64_t sel = -1;
     if (n > 0) {
         const uint32_t nc = st.n_cand[j];
-        const int rin = st.rank_in_bin[j];
+        uint32_t bits;
         if (nc <= (uint32_t)CAP) {
-            int m = 1;
-            while (m < (int)nc) m <<= 1;
-            for (int i = tid; i < m; i += 1024) s_key[i] = i < (int)nc ? a.cand[(s * 2 + j) * CAP + i] : ~0ull;
-            __syncthreads();
-            for (int k = 2; k <= m; k <<= 1) {          // bitonic sort, ascending
-                for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                    for (int i = tid; i < m; i += 1024) {
-                        const int l = i ^ jj;
-                        if (l > i) {
-                            const uint64_t u = s_key[i], v = s_key[l];
-                            const bool up = (i & k) == 0;
-                            if ((u > v) == up) { s_key[i] = v; s_key[l] = u; }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            const uint64_t key = s_key[rin - 1];
-            P = __uint_as_float((uint32_t)(key >> 32));
-            // smallest index holding P: the first key with this value (keys sorted by value, index)
-            int first = rin - 1;
-            while (first > 0 && (uint32_t)(s_key[first - 1] >> 32) == (uint32_t)(key >> 32)) --first;
-            sel = (int64_t)(uint32_t)s_key[first];
-        } else {
-            // overflow: radix select of the rank over the sample's non-white values, then the
-            // smallest index holding the selected value
-            const float* hs = a.hstore + (s * 2 + j) * a.n_px;
-            const int64_t k = pct_rank(a.q, n);
-            uint32_t prefix = 0, pmask = 0;
-            int64_t kk = k;
-            for (int shift = 24; shift >= 0; shift -= 8) {
-                for (int b = tid; b < 256; b += 1024) s_h[b] = 0;
-                __syncthreads();
-                for (int64_t i = tid; i < a.n_px; i += 1024) {
-                    const float v = hs[i];
-                    if (__float_as_uint(v) >> 31) continue;
-                    const uint32_t u = __float_as_uint(v);
-                    if ((u & pmask) == prefix) atomicAdd(&s_h[(u >> shift) & 255], 1u);
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    int64_t acc = 0;
-                    int d = 0;
-                    for (; d < 256; ++d) {
-                        if (acc + (int64_t)s_h[d] >= kk) break;
-                        acc += s_h[d];
-                    }
-                    s_misc[0] = d;
-                    s_misc[1] = (int)(kk - acc);
-                }
-                __syncthreads();
-                prefix |= (uint32_t)s_misc[0] << shift;
-                pmask |= 255u << shift;
-                kk = s_misc[1];
-                __syncthreads();
-            }
-            P = __uint_as_float(prefix);
+            const uint64_t* cand = a.cand + (s * 2 + j) * CAP;
+            bits = radix_select((int64_t)nc, [&](int64_t i, uint32_t& u) { u = (uint32_t)(cand[i] >> 32); return true; },
+                                (int64_t)st.rank_in_bin[j], s_h, s_wsum, s_misc);
             if (tid == 0) s_misc[0] = 0x7FFFFFFF;
             __syncthreads();
-            for (int64_t i = tid; i < a.n_px; i += 1024) {
-                const float v = hs[i];
-                if (__float_as_uint(v) == prefix) atomicMin(&s_misc[0], (int)i);
-            }
+            for (int i = tid; i < (int)nc; i += blockDim.x)
+                if ((uint32_t)(cand[i] >> 32) == bits) atomicMin(&s_misc[0], (int)(uint32_t)cand[i]);
+        } else {
+            const float* hs = a.hstore + (s * 2 + j) * a.n_px;
+            bits = radix_select(a.n_px, [&](int64_t i, uint32_t& u) { u = __float_as_uint(hs[i]); return !(u >> 31); },
+                                pct_rank(a.q, n), s_h, s_wsum, s_misc);
+            if (tid == 0) s_misc[0] = 0x7FFFFFFF;
             __syncthreads();
-            sel = s_misc[0];
+            for (int64_t i = tid; i < a.n_px; i += blockDim.x)
+                if (__float_as_uint(hs[i]) == bits) atomicMin(&s_misc[0], (int)i);
         }
+        __syncthreads();
+        P = __uint_as_float(bits);
+        sel = s_misc[0];
     }
     if (tid == 0) {
         int fl = n == 0 ? SPCN_FLAG_NO_TISSUE : 0;
@@ -309,7 +388,7 @@ __global__ __launch_bounds__(1024) void k_fw_select(FwArgs a) {
         const float* wt = a.w_tgt + s * a.w_tgt_stride;
         for (int c = 0; c < 3; ++c) {
             st.M[c][j] = (float)(kLog2e * (double)wt[c + 3 * j] * (double)sj);
-            if (j == 0) st.L[c] = (float)log2((double)a.i0_out[c]);
+            if (j == 0) st.L[c] = a.log2io[c];
         }
         if (a.p99_out) a.p99_out[2 * s + j] = P;
         if (a.scale_out) a.scale_out[2 * s + j] = sj;
@@ -318,6 +397,7 @@ __global__ __launch_bounds__(1024) void k_fw_select(FwArgs a) {
     }
 }
 
+template <int V>
 __global__ __launch_bounds__(FT) void k_fw_recon(FwArgs a) {
     const int64_t s = blockIdx.y;
     const SampleState& st = a.st[s];
@@ -325,12 +405,22 @@ __global__ __launch_bounds__(FT) void k_fw_recon(FwArgs a) {
     for (int c = 0; c < 3; ++c) { M[c][0] = st.M[c][0]; M[c][1] = st.M[c][1]; L[c] = st.L[c]; }
     const float* hs = a.hstore + s * 2 * a.n_px;
     float* y = a.y + s * 3 * a.n_px;
-    for (int64_t i = blockIdx.x * (int64_t)FT + threadIdx.x; i < a.n_px; i += (int64_t)gridDim.x * FT) {
-        const float h0 = fabsf(hs[i]), h1 = fabsf(hs[a.n_px + i]);
+    const int64_t nq = a.n_px / V;
+    for (int64_t q = blockIdx.x * (int64_t)FT + threadIdx.x; q < nq; q += (int64_t)gridDim.x * FT) {
+        const int64_t i = q * V;
+        float h0[V], h1[V];
+        Vec<V>::load(hs + i, h0);
+        Vec<V>::load(hs + a.n_px + i, h1);
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float z = fmaf(-M[c][0], h0, L[c]);
-            z = fmaf(-M[c][1], h1, z);
-            y[c * a.n_px + i] = __builtin_amdgcn_exp2f(z);
+            float yc[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                float z = fmaf(-M[c][0], fabsf(h0[k]), L[c]);
+                z = fmaf(-M[c][1], fabsf(h1[k]), z);
+                yc[k] = __builtin_amdgcn_exp2f(z);
+            }
+            Vec<V>::store(y + c * a.n_px + i, yc);
         }
     }
 }
@@ -343,6 +433,7 @@ struct BwArgs {
     const float* w_tgt; int64_t w_tgt_stride;
     const float* scale_tgt; int64_t scale_stride;
     float i0[3], i0_out[3], lambda;
+    float log2i0[3], log2io[3];   // log2 of i0 and i0_out (host-computed)
     int32_t white_sum;
     const float* p99; const int64_t* sel; const int32_t* flags;
     const float* gy;
@@ -364,7 +455,7 @@ __device__ inline void bw_consts(const BwArgs& a, int64_t s, BwConsts& K) {
         K.s[j] = (fl & (SPCN_FLAG_NO_TISSUE | SPCN_FLAG_BIN0)) ? 1.0f : S / P;
     }
     for (int i = 0; i < 6; ++i) K.wt[i] = a.w_tgt[s * a.w_tgt_stride + i];
-    for (int c = 0; c < 3; ++c) K.log2io[c] = (float)log2((double)a.i0_out[c]);
+    for (int c = 0; c < 3; ++c) K.log2io[c] = a.log2io[c];
 }
 
 // Gradient of one pixel w.r.t. its inputs given hbar (both stains), on its active set.
@@ -373,59 +464,73 @@ __device__ __forceinline__ void pixel_vjp(const F32Basis& F, const Px& p, float 
     float z0 = 0.0f, z1 = 0.0f;
     const bool a0 = p.h0 > 0.0f, a1 = p.h1 > 0.0f;
     if (a0 && a1) {
-        z0 = (F.g11 * hb0 - F.g01 * hb1) / F.det;
-        z1 = (F.g00 * hb1 - F.g01 * hb0) / F.det;
+        z0 = (F.g11 * hb0 - F.g01 * hb1) * F.r_det;
+        z1 = (F.g00 * hb1 - F.g01 * hb0) * F.r_det;
     } else if (a0) {
-        z0 = hb0 / F.g00;
+        z0 = hb0 * F.r00;
     } else if (a1) {
-        z1 = hb1 / F.g11;
+        z1 = hb1 * F.r11;
     }
     const float xs[3] = {x0, x1, x2};
     for (int c = 0; c < 3; ++c) {
         const float vbar = F.w[c] * z0 + F.w[c + 3] * z1;
-        g[c] = p.live[c] ? -vbar / xs[c] : 0.0f;
+        g[c] = p.live[c] ? -vbar * __builtin_amdgcn_rcpf(xs[c]) : 0.0f;   // live: x_c > 1/255
     }
 }
 
+template <int V>
 __global__ __launch_bounds__(FT) void k_bw_main(BwArgs a) {
     __shared__ F32Basis F;
     __shared__ BwConsts K;
     __shared__ double s_red[FT / 64][8];
     const int64_t s = blockIdx.y;
     if (threadIdx.x == 0) {
-        f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, F);
+        f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, a.log2i0, F);
         bw_consts(a, s, K);
     }
     __syncthreads();
     const float* x = a.x + s * 3 * a.n_px;
     const float* gy = a.gy + s * 3 * a.n_px;
     float* gx = a.gx + s * 3 * a.n_px;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // dWt[c][j] at c + 3 j, then ds0, ds1
-    for (int64_t i = blockIdx.x * (int64_t)FT + threadIdx.x; i < a.n_px; i += (int64_t)gridDim.x * FT) {
-        const float x0 = x[i], x1 = x[a.n_px + i], x2 = x[2 * a.n_px + i];
-        Px p;
-        solve_px(F, x0, x1, x2, a.white_sum, p);
-        float ub[3];
-        float hb0 = 0.0f, hb1 = 0.0f;
+    // dWt[c][j] at c + 3 j, then ds0, ds1: FP32 over this thread's few pixels, FP64 from there on
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t nq = a.n_px / V;
+    for (int64_t q = blockIdx.x * (int64_t)FT + threadIdx.x; q < nq; q += (int64_t)gridDim.x * FT) {
+        const int64_t i = q * V;
+        float xv[3][V], gv[3][V], out[3][V];
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float z = fmaf(-K.wt[c] * K.s[0] * (float)kLog2e, p.h0, K.log2io[c]);
-            z = fmaf(-K.wt[c + 3] * K.s[1] * (float)kLog2e, p.h1, z);
-            const float y = __builtin_amdgcn_exp2f(z);
-            ub[c] = -y * gy[c * a.n_px + i];
-            acc[c] += (double)(ub[c] * K.s[0] * p.h0);
-            acc[c + 3] += (double)(ub[c] * K.s[1] * p.h1);
-            hb0 = fmaf(K.wt[c], ub[c], hb0);
-            hb1 = fmaf(K.wt[c + 3], ub[c], hb1);
+            Vec<V>::load(x + c * a.n_px + i, xv[c]);
+            Vec<V>::load(gy + c * a.n_px + i, gv[c]);
         }
-        acc[6] += (double)(hb0 * p.h0);
-        acc[7] += (double)(hb1 * p.h1);
-        float g[3];
-        pixel_vjp(F, p, K.s[0] * hb0, K.s[1] * hb1, x0, x1, x2, g);
-        gx[i] = g[0]; gx[a.n_px + i] = g[1]; gx[2 * a.n_px + i] = g[2];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            Px p;
+            solve_px(F, xv[0][k], xv[1][k], xv[2][k], a.white_sum, p);
+            float ub[3];
+            float hb0 = 0.0f, hb1 = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                float z = fmaf(-K.wt[c] * K.s[0] * (float)kLog2e, p.h0, K.log2io[c]);
+                z = fmaf(-K.wt[c + 3] * K.s[1] * (float)kLog2e, p.h1, z);
+                const float y = __builtin_amdgcn_exp2f(z);
+                ub[c] = -y * gv[c][k];
+                acc[c] = fmaf(ub[c] * K.s[0], p.h0, acc[c]);
+                acc[c + 3] = fmaf(ub[c] * K.s[1], p.h1, acc[c + 3]);
+                hb0 = fmaf(K.wt[c], ub[c], hb0);
+                hb1 = fmaf(K.wt[c + 3], ub[c], hb1);
+            }
+            acc[6] = fmaf(hb0, p.h0, acc[6]);
+            acc[7] = fmaf(hb1, p.h1, acc[7]);
+            float g[3];
+            pixel_vjp(F, p, K.s[0] * hb0, K.s[1] * hb1, xv[0][k], xv[1][k], xv[2][k], g);
+            for (int c = 0; c < 3; ++c) out[c][k] = g[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Vec<V>::store(gx + c * a.n_px + i, out[c]);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int q = 0; q < 8; ++q) {
-        double v = acc[q];
+        double v = (double)acc[q];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
         if (lane == 0) s_red[wave][q] = v;
     }
@@ -437,15 +542,29 @@ __global__ __launch_bounds__(FT) void k_bw_main(BwArgs a) {
     }
 }
 
-__global__ void k_bw_reduce(BwArgs a, int nblk) {
+__global__ __launch_bounds__(64) void k_bw_reduce(BwArgs a, int nblk) {
+    __shared__ double s_part[8][8];   // [block group][quantity]
+    __shared__ double s_t[8];
     const int64_t s = blockIdx.x;
+    {   // fixed association: group g sums blocks g, g + 8, ...; then the groups in order
+        const int q = threadIdx.x & 7, g = threadIdx.x >> 3;
+        double v = 0.0;
+        for (int b = g; b < nblk; b += 8) v += a.partial[(s * nblk + b) * 8 + q];
+        s_part[g][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double v = 0.0;
+        for (int g = 0; g < 8; ++g) v += s_part[g][threadIdx.x];
+        s_t[threadIdx.x] = v;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = 0; b < nblk; ++b)
-        for (int q = 0; q < 8; ++q) t[q] += a.partial[(s * nblk + b) * 8 + q];
+    double t[8];
+    for (int q = 0; q < 8; ++q) t[q] = s_t[q];
     for (int i = 0; i < 6; ++i) a.gw[6 * s + i] = (float)t[i];
     F32Basis F;
-    f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, F);
+    f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, a.log2i0, F);
     BwConsts K;
     bw_consts(a, s, K);
     const float* x = a.x + s * 3 * a.n_px;
@@ -470,7 +589,7 @@ __global__ void k_bw_reduce(BwArgs a, int nblk) {
 }
 
 int blocks_per_sample(int64_t n_px, int64_t n, const DevInfo& dev) {
-    int64_t want = (n_px + FT * 16 - 1) / (FT * 16);
+    int64_t want = (n_px + FT * 16 - 1) / (FT * 16);   // about 16 pixels per thread
     int64_t cap = ((int64_t)dev.cus * 8 + n - 1) / n;
     int64_t b = want < cap ? want : cap;
     if (b > BLOCKS_PER_SAMPLE_MAX) b = BLOCKS_PER_SAMPLE_MAX;
@@ -478,6 +597,8 @@ int blocks_per_sample(int64_t n_px, int64_t n, const DevInfo& dev) {
 }
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 }  // namespace
 
@@ -499,7 +620,10 @@ hipError_t launch_forward_f32(const F32Args& g, const ParamsK& pk, float* y, flo
     a.x = g.x; a.n = g.n; a.n_px = g.n_px;
     a.w_src = g.w_src; a.w_src_stride = g.w_src_stride; a.w_tgt = g.w_tgt; a.w_tgt_stride = g.w_tgt_stride;
     a.scale_tgt = g.scale_tgt; a.scale_stride = g.scale_stride;
-    for (int c = 0; c < 3; ++c) { a.i0[c] = pk.i0[c]; a.i0_out[c] = g.i0_out[c]; }
+    for (int c = 0; c < 3; ++c) {
+        a.i0[c] = pk.i0[c]; a.i0_out[c] = g.i0_out[c];
+        a.log2i0[c] = (float)std::log2((double)pk.i0[c]); a.log2io[c] = (float)std::log2((double)g.i0_out[c]);
+    }
     a.lambda = pk.lambda; a.white_sum = pk.white_sum; a.q = pk.q64;
     uint8_t* p = static_cast<uint8_t*>(ws);
     a.hstore = reinterpret_cast<float*>(p); p += a256((size_t)g.n * 2 * g.n_px * sizeof(float));
@@ -509,12 +633,18 @@ hipError_t launch_forward_f32(const F32Args& g, const ParamsK& pk, float* y, flo
     a.y = y; a.p99_out = p99_out; a.scale_out = scale_out; a.sel_idx = sel_idx; a.flags_out = flags_out;
     const int bps = blocks_per_sample(g.n_px, g.n, dev);
     const dim3 grid(bps, (unsigned)g.n);
+    // planes of n_px floats: 16-byte accesses when every plane starts 16-byte aligned
+    const bool v4 = g.n_px % 4 == 0 && aligned16(g.x) && aligned16(y) && aligned16(a.hstore);
     hipLaunchKernelGGL(k_fw_clear, dim3(dev.cus), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_fw_dens, grid, dim3(FT), 0, s, a);
+    const dim3 grid_d((bps + 1) / 2, (unsigned)g.n);   // half the workgroups: half the histogram merges
+    if (v4) hipLaunchKernelGGL(k_fw_dens<4>, grid_d, dim3(FT), 0, s, a);
+    else hipLaunchKernelGGL(k_fw_dens<1>, grid_d, dim3(FT), 0, s, a);
     hipLaunchKernelGGL(k_fw_bin, dim3((unsigned)(2 * g.n)), dim3(FT), 0, s, a);
-    hipLaunchKernelGGL(k_fw_collect, grid, dim3(FT), 0, s, a);
+    if (v4) hipLaunchKernelGGL(k_fw_collect<4>, grid, dim3(FT), 0, s, a);
+    else hipLaunchKernelGGL(k_fw_collect<1>, grid, dim3(FT), 0, s, a);
     hipLaunchKernelGGL(k_fw_select, dim3((unsigned)(2 * g.n)), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_fw_recon, grid, dim3(FT), 0, s, a);
+    if (v4) hipLaunchKernelGGL(k_fw_recon<4>, grid, dim3(FT), 0, s, a);
+    else hipLaunchKernelGGL(k_fw_recon<1>, grid, dim3(FT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -525,13 +655,18 @@ hipError_t launch_backward_f32(const F32Args& g, const ParamsK& pk, const float*
     a.x = g.x; a.n = g.n; a.n_px = g.n_px;
     a.w_src = g.w_src; a.w_src_stride = g.w_src_stride; a.w_tgt = g.w_tgt; a.w_tgt_stride = g.w_tgt_stride;
     a.scale_tgt = g.scale_tgt; a.scale_stride = g.scale_stride;
-    for (int c = 0; c < 3; ++c) { a.i0[c] = pk.i0[c]; a.i0_out[c] = g.i0_out[c]; }
+    for (int c = 0; c < 3; ++c) {
+        a.i0[c] = pk.i0[c]; a.i0_out[c] = g.i0_out[c];
+        a.log2i0[c] = (float)std::log2((double)pk.i0[c]); a.log2io[c] = (float)std::log2((double)g.i0_out[c]);
+    }
     a.lambda = pk.lambda; a.white_sum = pk.white_sum;
     a.p99 = p99; a.sel = sel_idx; a.flags = flags; a.gy = grad_y;
     a.gx = grad_x; a.gw = grad_w_tgt; a.gs = grad_scale;
     a.partial = static_cast<double*>(ws);
     const int bps = blocks_per_sample(g.n_px, g.n, dev);
-    hipLaunchKernelGGL(k_bw_main, dim3(bps, (unsigned)g.n), dim3(FT), 0, s, a);
+    const bool v4 = g.n_px % 4 == 0 && aligned16(g.x) && aligned16(grad_y) && aligned16(grad_x);
+    if (v4) hipLaunchKernelGGL(k_bw_main<4>, dim3(bps, (unsigned)g.n), dim3(FT), 0, s, a);
+    else hipLaunchKernelGGL(k_bw_main<1>, dim3(bps, (unsigned)g.n), dim3(FT), 0, s, a);
     hipLaunchKernelGGL(k_bw_reduce, dim3((unsigned)g.n), dim3(64), 0, s, a, bps);
     return hipGetLastError();
 }
