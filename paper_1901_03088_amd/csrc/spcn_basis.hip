@@ -27,8 +27,8 @@ namespace {
 
 constexpr int SAMPLE_BLOCK = 1024;     // candidates per workgroup and round
 constexpr int MAX_ROUNDS = 3;          // candidate budget 4, 12 and 48 times n_s
-constexpr int TILE_THREADS = 1024;
-constexpr int TILE_SPT = 4;            // samples per thread in the batched kernel (n_s <= 4096)
+constexpr int TILE_THREADS = 256;
+constexpr int TILE_SPT = 16;           // samples per thread in the batched kernel (n_s <= 4096)
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t t) {
     uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ull;
@@ -167,10 +167,11 @@ __device__ inline void w_step(double* W, const double* s) {
     for (int j = 0; j < 2; ++j) {
         if (!(A[j][j] > 0.0)) continue;                 // stain unused by every sample: keep w_j
         double u[3], nrm2 = 0.0;
+        const double rA = 1.0 / A[j][j];
         for (int c = 0; c < 3; ++c) {
             double WAj = W[c] * A[0][j] + W[c + 3] * A[1][j];
             double Bcj = s[3 + 2 * c + j];
-            double uc = W[c + 3 * j] + (Bcj - WAj) / A[j][j];
+            double uc = W[c + 3 * j] + (Bcj - WAj) * rA;
             u[c] = uc > 0.0 ? uc : 0.0;
             nrm2 = nrm2 + u[c] * u[c];
         }
@@ -412,6 +413,8 @@ struct FitArgs {
 __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
     __shared__ double s_red[9 * 16];
     __shared__ double s_sum[9];
+    __shared__ double s_W[6];        // W, updated by thread 0 (one W-step per workgroup, not per thread)
+    __shared__ NmfBasis s_B;         // the H-step constants of s_W
     __shared__ int s_abort;
     BasisWork* bw = a.bw;
     const int64_t n = bw->n_acc, ns = bw->n_s;
@@ -424,11 +427,13 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
         live[k] = i < n;
         for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? a.V[c * ns + i] : 0.0;
     }
-    double W[6];
-    for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 6; ++i) s_W[i] = bw->W[i];
+        nmf_basis(s_W, a.lambda, s_B);
+    }
+    __syncthreads();
     for (int it = 0; it < a.n_iter; ++it) {
-        NmfBasis B;
-        nmf_basis(W, a.lambda, B);
+        const NmfBasis B = s_B;
         double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < FIT_SPT; ++k) {
@@ -475,12 +480,14 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
                 for (int q = 0; q < 9; ++q) s_sum[q] = tot[q];
         }
         __syncthreads();
-        double sums[9];
-        for (int q = 0; q < 9; ++q) sums[q] = s_sum[q];
-        w_step(W, sums);           // every thread of every workgroup: the same update on the same sums
+        if (threadIdx.x == 0) {    // every workgroup: the same update on the same sums
+            w_step(s_W, s_sum);
+            nmf_basis(s_W, a.lambda, s_B);
+        }
+        __syncthreads();
     }
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int i = 0; i < 6; ++i) bw->W[i] = W[i];
+        for (int i = 0; i < 6; ++i) bw->W[i] = s_W[i];
 }
 
 // Unit columns, stain order, outputs; optionally the nearest-rank percentile of the fitted
@@ -544,6 +551,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
     __shared__ double s_red[9 * 16];
     __shared__ double s_sum[9];
     __shared__ double s_W[6];
+    __shared__ NmfBasis s_B;
     __shared__ uint32_t s_hist[256];
     __shared__ int s_misc[2];
     __shared__ int s_count;
@@ -577,7 +585,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
     }
     const int n = s_count;
 
-    // samples in registers: sample s lives in thread s % 1024, slot s / 1024
+    // samples in registers: sample s lives in thread s % TILE_THREADS, slot s / TILE_THREADS
     double v[TILE_SPT][3];
     bool live[TILE_SPT];
 #pragma unroll
@@ -588,11 +596,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
         for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? s_od[c * kHistBins + p[c]] : 0.0;
     }
 
-    double W[6];
-    for (int i = 0; i < 6; ++i) W[i] = s_W[i];
+    if (threadIdx.x == 0) nmf_basis(s_W, a.lambda, s_B);
+    __syncthreads();
     for (int it = 0; it < a.n_iter; ++it) {
-        NmfBasis B;
-        nmf_basis(W, a.lambda, B);
+        const NmfBasis B = s_B;
         double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < TILE_SPT; ++k) {
@@ -605,10 +612,14 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
             acc[7] += v[k][2] * h0; acc[8] += v[k][2] * h1;
         }
         block_sums(acc, s_red, s_sum);
-        double sums[9];
-        for (int q = 0; q < 9; ++q) sums[q] = s_sum[q];
-        w_step(W, sums);           // every thread performs the same update on the same sums
+        if (threadIdx.x == 0) {    // one W-step for the workgroup
+            w_step(s_W, s_sum);
+            nmf_basis(s_W, a.lambda, s_B);
+        }
+        __syncthreads();
     }
+    double W[6];
+    for (int i = 0; i < 6; ++i) W[i] = s_W[i];
     finish_basis(W);
     if (threadIdx.x == 0) {
         for (int i = 0; i < 6; ++i) a.w_out[6 * tile + i] = (float)W[i];
@@ -628,7 +639,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
             int64_t kth = (int64_t)ceil(a.q * (double)n);
             kth = kth < 1 ? 1 : (kth > n ? n : kth);
             // radix select over the register-resident values: thread-owned slots are visited by
-            // index i = slot * 1024 + thread, so val() is only called with this thread's indices
+            // index i = slot * TILE_THREADS + thread, so val() is only called with this thread's indices
             uint64_t prefix = 0, pmask = 0;
             int64_t kk = kth;
             for (int shift = 56; shift >= 0; shift -= 8) {
