@@ -54,6 +54,7 @@ struct BatchWs {
     uint64_t* hist;         // [n][512]
     uint32_t* done;         // [n]
     uint32_t* ready;        // [n]
+    double* od;             // [3][256] FP64 optical densities (Eq. 1), for the near-edge path
     int32_t* item_tile;     // [max items]
 };
 
@@ -75,6 +76,7 @@ __host__ __device__ inline BatchWs carve(void* ws, int64_t n, int64_t total_px) 
     w.hist = reinterpret_cast<uint64_t*>(p); p += a256(n * 2 * kHistBins * sizeof(uint64_t));
     w.done = reinterpret_cast<uint32_t*>(p); p += a256(n * sizeof(uint32_t));
     w.ready = reinterpret_cast<uint32_t*>(p); p += a256(n * sizeof(uint32_t));
+    w.od = reinterpret_cast<double*>(p); p += a256(3 * kHistBins * sizeof(double));
     w.item_tile = reinterpret_cast<int32_t*>(p); p += a256(max_items_for(n, total_px) * sizeof(int32_t));
     return w;
 }
@@ -114,6 +116,9 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
         a.w.ready[t] = 0;
     }
     for (int i = threadIdx.x; i < 2 * kHistBins; i += blockDim.x) a.w.hist[(int64_t)t * 2 * kHistBins + i] = 0;
+    if (t == 0)
+        for (int i = threadIdx.x; i < 3 * kHistBins; i += blockDim.x)
+            a.w.od[i] = od_u8((double)a.pp.i0[i / kHistBins], i % kHistBins);
     __syncthreads();
     const int k = threadIdx.x;
     const int u = s_shift;
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
             for (int i = tid; i < kHistBins * 2 * Y::kCols; i += RUN_THREADS)
                 words[(Y::kHRegion + (uint32_t)(i / (2 * Y::kCols)) * 256u + Y::kH) / 4 + (i % (2 * Y::kCols))] = 0u;
             for (int i = tid; i < 3 * kHistBins; i += RUN_THREADS)
-                S.p1.od[i / kHistBins][i % kHistBins] = od_u8((double)a.pp.i0[i / kHistBins], i % kHistBins);
+                S.p1.od[i / kHistBins][i % kHistBins] = a.w.od[i];   // computed once by k_tiles_setup
             if (tid == 0) { S.p1.B = a.w.basis[t]; S.p1.shift = I.shift; }
             __syncthreads();
             if (cnt > 0 && !I.bad) {
@@ -343,7 +348,8 @@ size_t batched_workspace_bytes(int64_t n_tiles, int64_t total_px) {
     size_t b = a256(sizeof(BatchHead)) + a256(n * sizeof(TileInfo)) + a256(n * sizeof(Basis64)) +
                a256(n * 3 * kHistBins * sizeof(int4)) + a256(n * 3 * kHistBins * sizeof(float2)) +
                a256(n * sizeof(RecolourConsts)) + a256(n * 2 * kHistBins * sizeof(uint64_t)) +
-               2 * a256(n * sizeof(uint32_t)) + a256(max_items_for(n, total_px) * sizeof(int32_t));
+               2 * a256(n * sizeof(uint32_t)) + a256(3 * kHistBins * sizeof(double)) +
+               a256(max_items_for(n, total_px) * sizeof(int32_t));
     return b;
 }
 
