@@ -30,10 +30,19 @@ def test_header_functions_all_exported(lib):
 
 
 def test_defaults_follow_the_paper(lib):
+    """Library defaults against the constants the paper fixes (tests/golden/paper_constants.json)."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
     p = lib.params()
-    assert list(p.i0) == [255.0, 255.0, 255.0]        # 8-bit maximum intensity (Eq. 1)
-    assert p.white_sum == 660                          # mean intensity 220 (Sec. 3.1 item 2)
-    assert p.percentile == 99.0                        # Eq. 3
+    assert list(p.i0) == [float(g["eq1_max_intensity_8bit"]["value"])] * 3
+    assert p.white_sum == 3 * g["white_intensity_threshold"]["value"]      # mean of the three channels
+    assert p.percentile == float(g["normalisation_percentile"]["value"])
+    assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, g["i0_max_samples"]["value"]) > 0   # the paper's cap fits
+    import inspect
+    sig = inspect.signature(lib.spcn_estimate_i0).parameters
+    assert sig["n_samples"].default == g["i0_max_samples"]["value"]
+    assert sig["percentile"].default == float(g["i0_percentile"]["value"])
+    assert sig["white_sum"].default == 3 * g["background_intensity_threshold"]["value"]
     q = lib.spcn_params()
     lib._L.spcn_default_params(C.byref(q))
     assert list(q.hist_hi) == [4.0, 4.0]
