@@ -88,7 +88,7 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_SAMPLE_PERCENTILE 8   /* n_samples */
 #define SPCN_OP_BAND_PERCENTILES  9   /* n_items = number of bands */
 #define SPCN_OP_STREAM_NORMALIZE 10   /* n_px = image width, n_items = chunk_rows */
-#define SPCN_OP_EXACT_PERCENTILE 11   /* no size arguments: a fixed 2^28 + 37120 bytes */
+#define SPCN_OP_EXACT_PERCENTILE 11   /* no size arguments: a fixed 2^28 + 2^26 + 37120 bytes */
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
@@ -198,7 +198,7 @@ spcn_status spcn_sample_percentile(const uint8_t* img, int64_t height, int64_t w
  * the value.
  *   p99_out   device [2]: the selected FP64 density rounded to FP32 (0 without tissue)
  *   flags_out device [2] or NULL: SPCN_FLAG_NO_TISSUE, SPCN_FLAG_BASIS
- *   ws        spcn_workspace_size(SPCN_OP_EXACT_PERCENTILE, 0, 0, 0) bytes (about 256 MiB, whatever the
+ *   ws        spcn_workspace_size(SPCN_OP_EXACT_PERCENTILE, 0, 0, 0) bytes (about 320 MiB, whatever the
  *             image size); calls that share a workspace must not overlap */
 spcn_status spcn_exact_percentile(const uint8_t* img, int64_t height, int64_t width, const float* w,
                                   const spcn_params* p, float* p99_out, int32_t* flags_out, void* ws,
