@@ -143,9 +143,10 @@ hipError_t launch_band_percentiles(const uint8_t* img, int64_t height, int64_t w
     hipLaunchKernelGGL(k_band_zero, dim3((unsigned)hmin((nh + 255) / 256, (int64_t)1024)), dim3(256), 0, s, hist, nh);
     BandArgs a{};
     a.img = img; a.height = height; a.width = width; a.band_rows = band_rows; a.n_bands = n_bands;
-    // about one workgroup per CU in total, at least one per band, parts of at least 64k units
+    // about four workgroups per CU in total (they run one per CU at a time, so the hardware balances
+    // bands of unequal tissue content), at least one per band, parts of at least 64k units
     const int64_t band_units = band_rows * width / 4;
-    int64_t parts = (dev.cus + n_bands - 1) / n_bands;
+    int64_t parts = (4 * (int64_t)dev.cus + n_bands - 1) / n_bands;
     parts = hmin(parts, hmax((int64_t)1, band_units / 65536));
     parts = hmax(parts, (band_units + (1 << 26) - 1) >> 26);   // a part's bytes stay below 2^32
     a.parts = (int32_t)hmax((int64_t)1, parts);
