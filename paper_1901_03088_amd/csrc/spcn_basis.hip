@@ -849,31 +849,109 @@ __global__ __launch_bounds__(256) void k_sample_dens(const uint8_t* img, const i
     }
 }
 
-// Nearest-rank percentile of each stain's sampled densities (one workgroup).
-__global__ __launch_bounds__(1024) void k_sample_pctl(const BasisWork* bw, const double* H, double q, float* p99_out,
-                                                      int32_t* flags_out) {
-    __shared__ uint32_t s_hist[16 * 256];
-    __shared__ int s_misc[2];
-    const int64_t n = bw->n_acc, ns = bw->n_s;
-    for (int j = 0; j < 2; ++j) {
-        double P = 0.0;
-        if (n > 0) {
-            int64_t k = (int64_t)ceil(q * (double)n);
-            k = k < 1 ? 1 : (k > n ? n : k);
-            const double* Hj = H + j * ns;
-            P = block_select(n, k, [&](int64_t i) { return Hj[i]; }, s_hist, s_misc);
+// Nearest-rank percentile of each stain's sampled densities: a radix selection over the FP64 bit
+// patterns (non-negative doubles order like them) spread over many workgroups.  Six digit passes of
+// 11, 11, 11, 11, 11 and 8 bits (bit 63 is 0): k_sel_digits builds the digit histogram of the values
+// that share the bits fixed so far, k_sel_pick fixes the next digit.
+constexpr int SEL_BINS = 2048;
+constexpr int SEL_PASSES = 6;
+__host__ __device__ constexpr int sel_shift(int pass) { return pass < 5 ? 52 - 11 * pass : 0; }
+__host__ __device__ constexpr int sel_width(int pass) { return pass < 5 ? 11 : 8; }
+
+struct SelState {
+    unsigned long long prefix[2];   // key bits fixed so far
+    long long r[2];                 // 1-based rank still to find among the values sharing the prefix
+    long long n;                    // values (kept samples)
+};
+
+__global__ __launch_bounds__(64) void k_sel_init(const BasisWork* bw, double q, SelState* st, uint32_t* dhist) {
+    const long long n = bw->n_acc;
+    long long k = n > 0 ? (long long)ceil(q * (double)n) : 0;
+    k = n > 0 ? (k < 1 ? 1 : (k > n ? n : k)) : 0;
+    if (threadIdx.x < 2) { st->prefix[threadIdx.x] = 0ull; st->r[threadIdx.x] = k; }
+    if (threadIdx.x == 0) st->n = n;
+    for (int i = threadIdx.x; i < 2 * SEL_BINS; i += blockDim.x) dhist[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_sel_digits(const double* H, int64_t ns, const SelState* st, uint32_t* dhist,
+                                                    int pass) {
+    __shared__ uint32_t s_h[SEL_BINS];
+    const int j = blockIdx.y;
+    const long long n = st->n;
+    if (n == 0) return;                                  // uniform
+    for (int i = threadIdx.x; i < SEL_BINS; i += blockDim.x) s_h[i] = 0u;
+    __syncthreads();
+    const int shift = sel_shift(pass), hi = shift + sel_width(pass);
+    const unsigned long long prefix = st->prefix[j], dmask = (1ull << sel_width(pass)) - 1;
+    const double* Hj = H + j * ns;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double v = Hj[i];
+        const unsigned long long u = v > 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
+        if (((u ^ prefix) >> hi) == 0ull) atomicAdd(&s_h[(u >> shift) & dmask], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < SEL_BINS; i += blockDim.x)
+        if (s_h[i]) atomicAdd(dhist + j * SEL_BINS + i, s_h[i]);
+}
+
+// One workgroup of 256 threads per stain: the digit holding the remaining rank (parallel prefix sums),
+// the digit histogram cleared for the next pass; after the last pass the value and the flags.
+__global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* dhist, int pass, int64_t ns,
+                                                  float* p99_out, int32_t* flags_out) {
+    __shared__ uint32_t s_wsum[4];
+    __shared__ int s_g;
+    __shared__ uint32_t s_below;
+    const int j = blockIdx.x, t = threadIdx.x, lane = t & 63;
+    const long long n = st->n;
+    constexpr int per = SEL_BINS / 256;
+    uint32_t* dh = dhist + j * SEL_BINS;
+    if (n > 0) {
+        const uint32_t r = (uint32_t)st->r[j];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < per; ++i) sum += dh[t * per + i];
+        uint32_t incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t up = __shfl_up(incl, o);
+            if (lane >= o) incl += up;
         }
-        if (threadIdx.x == 0) {
-            p99_out[j] = (float)P;
-            if (flags_out) flags_out[j] = (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
+        if (lane == 63) s_wsum[t >> 6] = incl;
+        __syncthreads();
+        for (int w = 0; w < (t >> 6); ++w) incl += s_wsum[w];
+        if (t == 255) { s_g = 255; s_below = incl - sum; }   // default if the counts fall short of r
+        __syncthreads();
+        if (incl - sum < r && r <= incl) { s_g = t; s_below = incl - sum; }   // at most one thread
+        __syncthreads();
+        if (t < 64) {
+            const int g = s_g;
+            const uint32_t c = t < per ? dh[g * per + t] : 0u;
+            uint32_t in = c;
+            for (int o = 1; o < per; o <<= 1) {
+                const uint32_t up = __shfl_up(in, o);
+                if (t >= o) in += up;
+            }
+            const uint32_t rr = r - s_below;
+            const uint64_t m = __ballot(t < per && in - c < rr && rr <= in);
+            const int who = m ? __ffsll((unsigned long long)m) - 1 : per - 1;
+            const uint32_t before = __shfl(in - c, who);
+            if (t == 0) {
+                st->r[j] = (long long)(rr - before);
+                st->prefix[j] |= (unsigned long long)(g * per + who) << sel_shift(pass);
+            }
         }
         __syncthreads();
+        for (int i = t; i < SEL_BINS; i += blockDim.x) dh[i] = 0u;
+    }
+    if (pass == SEL_PASSES - 1 && t == 0) {
+        p99_out[j] = n > 0 ? (float)__longlong_as_double((long long)st->prefix[j]) : 0.0f;
+        if (flags_out) flags_out[j] = (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
     }
 }
 
 size_t sample_pctl_workspace_bytes(int64_t n_s) {
     if (n_s <= 0) return 0;
-    return i0_workspace_bytes(n_s) + align256((size_t)2 * n_s * sizeof(double));
+    return i0_workspace_bytes(n_s) + align256((size_t)2 * n_s * sizeof(double)) + align256(sizeof(SelState)) +
+           align256((size_t)2 * SEL_BINS * sizeof(uint32_t));
 }
 
 hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, int64_t n_s,
@@ -885,7 +963,9 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
     int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
-    double* H = reinterpret_cast<double*>(p);
+    double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
+    SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
+    uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
     const int64_t max_cand = 64 * n_s;
     hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr);
     int64_t t0 = 0;
@@ -898,8 +978,14 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     }
     hipLaunchKernelGGL(k_sample_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
                        img, (const int64_t*)idx, (const BasisWork*)bw, w, pk.lambda, pk.i0[0], pk.i0[1], pk.i0[2], H);
-    hipLaunchKernelGGL(k_sample_pctl, dim3(1), dim3(1024), 0, s, (const BasisWork*)bw, (const double*)H, pk.q64,
-                       p99_out, flags_out);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, s, (const BasisWork*)bw, pk.q64, sel, dhist);
+    const int64_t sel_want = hmin((n_s + 1023) / 1024, (int64_t)dev.cus);
+    const unsigned sel_grid = (unsigned)(sel_want > 0 ? sel_want : 1);
+    for (int pass = 0; pass < SEL_PASSES; ++pass) {
+        hipLaunchKernelGGL(k_sel_digits, dim3(sel_grid, 2), dim3(256), 0, s, (const double*)H, n_s,
+                           (const SelState*)sel, dhist, pass);
+        hipLaunchKernelGGL(k_sel_pick, dim3(2), dim3(256), 0, s, sel, dhist, pass, n_s, p99_out, flags_out);
+    }
     return hipGetLastError();
 }
 
