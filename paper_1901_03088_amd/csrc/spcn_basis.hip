@@ -138,24 +138,65 @@ __device__ inline void nmf_basis(const double* W, double lambda, NmfBasis& B) {
 // Exact non-negative lasso of one sample (Eq. 2 with W fixed): h_j = max(0, min(p_j, f_j)) with
 // f = G^-1 b, p_j = b_j / g_jj (valid because g01 >= 0 for a non-negative W).  Columns of zero
 // norm give zero densities.
-__device__ inline void nmf_solve(const NmfBasis& B, double v0, double v1, double v2, double& h0, double& h1) {
+__device__ __forceinline__ void nmf_rhs(const NmfBasis& B, double v0, double v1, double v2, double& b0, double& b1) {
     const double* W = B.w;
-    double b0 = W[0] * v0; b0 = b0 + W[1] * v1; b0 = b0 + W[2] * v2; b0 = b0 - B.half_lambda;
-    double b1 = W[3] * v0; b1 = b1 + W[4] * v1; b1 = b1 + W[5] * v2; b1 = b1 - B.half_lambda;
+    b0 = W[0] * v0; b0 = b0 + W[1] * v1; b0 = b0 + W[2] * v2; b0 = b0 - B.half_lambda;
+    b1 = W[3] * v0; b1 = b1 + W[4] * v1; b1 = b1 + W[5] * v2; b1 = b1 - B.half_lambda;
+}
+
+// The regular case (B.ok): branch-free.
+__device__ __forceinline__ void nmf_solve_regular(const NmfBasis& B, double v0, double v1, double v2, double& h0,
+                                                  double& h1) {
+    double b0, b1;
+    nmf_rhs(B, v0, v1, v2, b0, b1);
+    double f0 = (B.g11 * b0 - B.g01 * b1) * B.r_det;
+    double f1 = (B.g00 * b1 - B.g01 * b0) * B.r_det;
+    double p0 = b0 * B.r00, p1 = b1 * B.r11;
+    double t0 = p0 < f0 ? p0 : f0, t1 = p1 < f1 ? p1 : f1;
+    h0 = t0 > 0.0 ? t0 : 0.0;
+    h1 = t1 > 0.0 ? t1 : 0.0;
+}
+
+__device__ inline void nmf_solve(const NmfBasis& B, double v0, double v1, double v2, double& h0, double& h1) {
     if (B.ok) {
-        double f0 = (B.g11 * b0 - B.g01 * b1) * B.r_det;
-        double f1 = (B.g00 * b1 - B.g01 * b0) * B.r_det;
-        double p0 = b0 * B.r00, p1 = b1 * B.r11;
-        double t0 = p0 < f0 ? p0 : f0, t1 = p1 < f1 ? p1 : f1;
-        h0 = t0 > 0.0 ? t0 : 0.0;
-        h1 = t1 > 0.0 ? t1 : 0.0;
+        nmf_solve_regular(B, v0, v1, v2, h0, h1);
     } else {
+        double b0, b1;
+        nmf_rhs(B, v0, v1, v2, b0, b1);
         double p0 = B.g00 > 0.0 ? b0 / B.g00 : 0.0, p1 = B.g11 > 0.0 ? b1 / B.g11 : 0.0;
         // one live column (or none): the problem is a scalar lasso in the better one
         double o0 = -p0 * b0, o1 = -p1 * b1;   // objective drop of each single-column candidate
         h0 = 0.0; h1 = 0.0;
         if (p0 > 0.0 && (o0 <= o1 || !(p1 > 0.0))) h0 = p0;
         else if (p1 > 0.0) h1 = p1;
+    }
+}
+
+// The W-step's sums over one thread's samples (densities by the H-step above, then the products).
+// Slots past the last sample hold v = 0, whose densities are exactly 0 (b = -lambda/2 <= 0 gives
+// p <= 0), so they add exact zeros and need no test; with a regular basis (uniform over the
+// workgroup) the loop is branch-free.
+template <int K>
+__device__ __forceinline__ void nmf_sums(const NmfBasis& B, const double (&v)[K][3], double (&acc)[9]) {
+    auto add = [&](const double* x, double h0, double h1) {
+        acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
+        acc[3] += x[0] * h0; acc[4] += x[0] * h1;
+        acc[5] += x[1] * h0; acc[6] += x[1] * h1;
+        acc[7] += x[2] * h0; acc[8] += x[2] * h1;
+    };
+    if (__builtin_amdgcn_readfirstlane(B.ok)) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double h0, h1;
+            nmf_solve_regular(B, v[k][0], v[k][1], v[k][2], h0, h1);
+            add(v[k], h0, h1);
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            double h0, h1;
+            nmf_solve(B, v[k][0], v[k][1], v[k][2], h0, h1);
+            add(v[k], h0, h1);
+        }
     }
 }
 
@@ -210,58 +251,35 @@ __device__ inline void initial_basis(const float* w_init, double* W) {
     }
 }
 
-// Exact k-th smallest (1-based) of n non-negative doubles produced by `val(i)`, by a most-
-// significant-digit radix select over their bit patterns (monotone for x >= 0), block-wide.
-template <class F>
-__device__ double block_select(int64_t n, int64_t k, F val, uint32_t* s_hist, int* s_misc) {
-    // s_hist: [16][256], one digit histogram per wavefront (values that share their leading
-    // digits all hit one bin: per-wavefront copies keep the atomics of different waves apart)
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint64_t prefix = 0, pmask = 0;
-    int64_t kk = k;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int b = threadIdx.x; b < nw * 256; b += blockDim.x) s_hist[b] = 0;
-        __syncthreads();
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            uint64_t u = (uint64_t)__double_as_longlong(val(i));
-            if ((u & pmask) == prefix) atomicAdd(&s_hist[wave * 256 + ((u >> shift) & 255)], 1u);
-        }
-        __syncthreads();
-        if (threadIdx.x < 256) {
-            uint32_t t = 0;
-            for (int w = 0; w < nw; ++w) t += s_hist[w * 256 + threadIdx.x];
-            s_hist[threadIdx.x] = t;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t acc = 0;
-            int d = 0;
-            for (; d < 256; ++d) {
-                if (acc + (int64_t)s_hist[d] >= kk) break;
-                acc += s_hist[d];
-            }
-            s_misc[0] = d;
-            s_misc[1] = (int)(kk - acc);
-        }
-        __syncthreads();
-        prefix |= (uint64_t)s_misc[0] << shift;
-        pmask |= (uint64_t)255 << shift;
-        kk = s_misc[1];
-        __syncthreads();
-    }
-    return __longlong_as_double((long long)prefix);
-}
-
 // ------------------------------------------------------------------ one image, many samples
 
 struct BasisWork {          // layout of the caller's workspace (single image)
     int64_t n_s, max_cand;
     int32_t n_acc;          // samples kept so far
-    uint32_t arrive;        // NMF: workgroup arrivals, summed over rounds
     int32_t base;           // sampling: samples kept before the current round
     int32_t flags;          // SPCN_FLAG_TIMEOUT if a wait between workgroups expired
     double W[6];
 };
+
+constexpr int FIT_THREADS = 512;
+constexpr int FIT_SPT = 8;
+constexpr int FIT_PER_BLOCK = FIT_THREADS * FIT_SPT;
+constexpr int FIT_MAX_BLOCKS = 64;               // kMaxBasisSamples / FIT_PER_BLOCK (one wavefront)
+constexpr uint32_t FIT_SPIN_LIMIT = 1u << 20;
+static_assert(FIT_MAX_BLOCKS * FIT_PER_BLOCK >= kMaxBasisSamples, "fit grid must cover every sample");
+static_assert(FIT_MAX_BLOCKS <= 64, "one partial row per lane of the reducing wavefront");
+// Exchange slot of one workgroup and round parity: one 128-byte line with the 9 sums and, after
+// them, the sequence word (measured faster than sequence words packed side by side, which every
+// workgroup then writes into the same two lines).
+constexpr int FIT_SLOT = 16;                     // doubles per slot: 9 sums, the sequence word, padding
+constexpr size_t FIT_XCHG_BYTES = (size_t)2 * FIT_MAX_BLOCKS * FIT_SLOT * sizeof(double);
+
+__device__ __forceinline__ double* fit_slot(double* xchg, int parity, int b) {
+    return xchg + ((size_t)parity * FIT_MAX_BLOCKS + b) * FIT_SLOT;
+}
+__device__ __forceinline__ uint32_t* fit_seq(double* xchg, int parity, int b) {
+    return reinterpret_cast<uint32_t*>(fit_slot(xchg, parity, b) + 9);
+}
 
 struct SampleArgs {
     const uint8_t* img; int64_t n_px; int32_t white_sum; uint64_t seed;
@@ -302,7 +320,6 @@ __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_round(SampleArgs a) {
 // Exclusive scan of the round's per-workgroup counts (one workgroup), in place: counts[b] becomes
 // the rank of workgroup b's first kept candidate within the round and counts[nb] the round's total.
 // Records the samples kept before the round and the new total (capped at n_s).
-constexpr int MERGE_MAX_BLOCKS = 12288;   // rounds of at most 48 * 262144 candidates
 __global__ __launch_bounds__(1024) void k_sample_scan(SampleArgs a) {
     __shared__ int s_part[1024];
     BasisWork* bw = a.bw;
@@ -366,11 +383,14 @@ static void launch_round(const SampleArgs& a, const DevInfo& dev, hipStream_t s)
     hipLaunchKernelGGL(k_sample_copy, dim3(grid), dim3(SAMPLE_BLOCK), 0, s, a);
 }
 
-__global__ void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init) {
+__global__ void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init, double* xchg) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->arrive = 0; bw->base = 0; bw->flags = 0;
+        bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->base = 0; bw->flags = 0;
         initial_basis(w_init, bw->W);
     }
+    if (xchg)   // the fit's sequence words start below every round number
+        for (int i = threadIdx.x; i < 2 * FIT_MAX_BLOCKS; i += blockDim.x)
+            *fit_seq(xchg, i / FIT_MAX_BLOCKS, i % FIT_MAX_BLOCKS) = 0u;
 }
 
 // FP64 optical densities of the kept samples, planar [3][n_s].
@@ -389,461 +409,116 @@ __global__ __launch_bounds__(256) void k_od_gather(const uint8_t* img, const int
 }
 
 // The whole fit in one launch: every workgroup holds up to FIT_PER_BLOCK samples in registers for
-// all rounds.  Per round each workgroup publishes its FP64 partial sums (double-buffered by round
-// parity), arrives on a counter and waits for all others; then every workgroup reduces the same
-// partials in the same fixed order and performs the same W-step, so all hold bit-identical W.
-// The grid (at most 64 workgroups) is far below what the chip keeps resident at once, so all
-// workgroups run concurrently; the wait is bounded nonetheless and reports SPCN_FLAG_TIMEOUT.
-constexpr int FIT_THREADS = 512;
-constexpr int FIT_SPT = 8;
-constexpr int FIT_PER_BLOCK = FIT_THREADS * FIT_SPT;
-constexpr int FIT_MAX_BLOCKS = 64;               // kMaxBasisSamples / FIT_PER_BLOCK (one wavefront)
-constexpr uint32_t FIT_SPIN_LIMIT = 1u << 20;
-static_assert(FIT_MAX_BLOCKS * FIT_PER_BLOCK >= kMaxBasisSamples, "fit grid must cover every sample");
-static_assert(FIT_MAX_BLOCKS <= 64, "one partial row per lane of the reducing wavefront");
-
+// all rounds.  Per round each workgroup publishes its FP64 partial sums in its own slot (double-
+// buffered by round parity), then the round number as its sequence word (a release store, no
+// read-modify-write); one wavefront polls every workgroup's word (a lane each) until all show the
+// round.  Then every workgroup reduces the same partials in the same fixed order and performs the
+// same W-step, so all hold bit-identical W.  The grid (at most 64 workgroups) is far below what
+// the chip keeps resident at once, so all workgroups run concurrently; the wait is bounded
+// nonetheless and reports SPCN_FLAG_TIMEOUT.
 struct FitArgs {
     BasisWork* bw;
     const double* V;        // [3][n_s]
-    double* partial;        // [2][gridDim][9]
+    double* xchg;           // [2][FIT_MAX_BLOCKS][FIT_SLOT] slots (+ sequence words), FIT_XCHG_BYTES
     double lambda;
     int32_t n_iter;
 };
 
 __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
     __shared__ double s_red[9 * 16];
-    __shared__ double s_sum[9];
-    __shared__ double s_W[6];        // W, updated by thread 0 (one W-step per workgroup, not per thread)
-    __shared__ NmfBasis s_B;         // the H-step constants of s_W
+    __shared__ NmfBasis s_B;         // the H-step constants of the current W
     __shared__ int s_abort;
     BasisWork* bw = a.bw;
     const int64_t n = bw->n_acc, ns = bw->n_s;
     const unsigned nblk = gridDim.x;
-    double v[FIT_SPT][3];
-    bool live[FIT_SPT];
+    double v[FIT_SPT][3];            // slots past the last sample hold zeros (they add nothing)
 #pragma unroll
     for (int k = 0; k < FIT_SPT; ++k) {
         const int64_t i = (int64_t)blockIdx.x * FIT_PER_BLOCK + k * FIT_THREADS + threadIdx.x;
-        live[k] = i < n;
-        for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? a.V[c * ns + i] : 0.0;
+        for (int c = 0; c < 3; ++c) v[k][c] = i < n ? a.V[c * ns + i] : 0.0;
     }
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 6; ++i) s_W[i] = bw->W[i];
-        nmf_basis(s_W, a.lambda, s_B);
-    }
+    double W[6];                     // W in the registers of lane 0 (one W-step per workgroup and round)
+    for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
+    if (threadIdx.x == 0) nmf_basis(W, a.lambda, s_B);
     __syncthreads();
     for (int it = 0; it < a.n_iter; ++it) {
         const NmfBasis B = s_B;
         double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < FIT_SPT; ++k) {
-            if (!live[k]) continue;
-            double h0, h1;
-            nmf_solve(B, v[k][0], v[k][1], v[k][2], h0, h1);
-            acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
-            acc[3] += v[k][0] * h0; acc[4] += v[k][0] * h1;
-            acc[5] += v[k][1] * h0; acc[6] += v[k][1] * h1;
-            acc[7] += v[k][2] * h0; acc[8] += v[k][2] * h1;
-        }
-        block_sums(acc, s_red, s_sum);
-        double* part = a.partial + (size_t)(it & 1) * nblk * 9;
-        if (threadIdx.x < 9) part[blockIdx.x * 9 + threadIdx.x] = s_sum[threadIdx.x];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            // one release per workgroup and round publishes its partials; the wait polls with
-            // relaxed loads and a single acquire follows (no cache maintenance inside the loop)
-            __hip_atomic_fetch_add(&bw->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t target = (uint32_t)(it + 1) * nblk;
+        nmf_sums(B, v, acc);
+        const int par = it & 1;
+        block_sums(acc, s_red, fit_slot(a.xchg, par, blockIdx.x));   // the totals go straight into the slot
+        const uint32_t want = (uint32_t)(it + 1);
+        if (threadIdx.x == 0)   // the release orders the workgroup's slot stores (after the barrier) before it
+            __hip_atomic_store(fit_seq(a.xchg, par, blockIdx.x), want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x < 64) {  // one wavefront: lane b waits for workgroup b, then reads its sums
+            const int lane = threadIdx.x;
+            bool ready = lane >= (int)nblk;
             uint32_t spins = 0;
             int abort = 0;
-            while (__hip_atomic_load(&bw->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > FIT_SPIN_LIMIT ||
-                    __hip_atomic_load(&bw->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    atomicOr(&bw->flags, SPCN_FLAG_TIMEOUT);
+            for (;;) {   // the sequence words and the abort flag are read together: one round trip per poll
+                const uint32_t sq =
+                    ready ? want : __hip_atomic_load(fit_seq(a.xchg, par, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int stop = __hip_atomic_load(&bw->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                ready = sq >= want;
+                if (__ballot(!ready) == 0ull) break;
+                if (++spins > FIT_SPIN_LIMIT || __builtin_amdgcn_readfirstlane(stop)) {
+                    if (lane == 0) atomicOr(&bw->flags, SPCN_FLAG_TIMEOUT);
                     abort = 1;
                     break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            s_abort = abort;
+            double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (!abort && lane < (int)nblk) {
+                const double* src = fit_slot(a.xchg, par, lane);
+                for (int q = 0; q < 9; ++q) tot[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (int q = 0; q < 9; ++q) tot[q] = wave_sum_d(tot[q]);
+            if (lane == 0) {       // every workgroup: the same update on the same sums
+                s_abort = abort;
+                if (!abort) {
+                    w_step(W, tot);
+                    nmf_basis(W, a.lambda, s_B);
+                }
+            }
         }
         __syncthreads();
         if (s_abort) return;
-        if (threadIdx.x < 64) {   // one wavefront reduces the (at most 64) partial rows
-            double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            if (threadIdx.x < nblk)
-                for (int q = 0; q < 9; ++q)
-                    tot[q] = __hip_atomic_load(part + threadIdx.x * 9 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int q = 0; q < 9; ++q) tot[q] = wave_sum_d(tot[q]);
-            if (threadIdx.x == 0)
-                for (int q = 0; q < 9; ++q) s_sum[q] = tot[q];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {    // every workgroup: the same update on the same sums
-            w_step(s_W, s_sum);
-            nmf_basis(s_W, a.lambda, s_B);
-        }
-        __syncthreads();
     }
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int i = 0; i < 6; ++i) bw->W[i] = s_W[i];
+        for (int i = 0; i < 6; ++i) bw->W[i] = W[i];
 }
 
-// Unit columns, stain order, outputs; optionally the nearest-rank percentile of the fitted
-// densities of the samples (one workgroup).
-__global__ __launch_bounds__(1024) void k_nmf_finish(BasisWork* bw, const double* V, double lambda, double q,
-                                                     float* w_out, float* sample_p99, int32_t* flags_out) {
-    __shared__ uint32_t s_hist[16 * 256];
-    __shared__ int s_misc[2];
-    __shared__ double s_W[6];
+// Unit columns, stain order, outputs and flags (one thread); the finished FP64 basis is kept in the
+// workspace for the densities of the samples.
+__global__ void k_nmf_finish(BasisWork* bw, float* w_out, int32_t* flags_out) {
+    if (threadIdx.x != 0) return;
+    double W[6];
+    for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
+    finish_basis(W);
+    for (int i = 0; i < 6; ++i) { bw->W[i] = W[i]; w_out[i] = (float)W[i]; }
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    if (flags_out)
+        for (int j = 0; j < 2; ++j)
+            flags_out[j] = (n < ns ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | bw->flags;
+}
+
+// Fitted densities of the kept samples under the finished basis (the H-step of the fit, FP64),
+// planar [2][n_s], for the sample percentile.
+__global__ __launch_bounds__(256) void k_nmf_dens(const BasisWork* bw, const double* V, double lambda, double* H) {
+    __shared__ NmfBasis s_B;
     if (threadIdx.x == 0) {
         double W[6];
         for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
-        finish_basis(W);
-        for (int i = 0; i < 6; ++i) { s_W[i] = W[i]; w_out[i] = (float)W[i]; }
+        nmf_basis(W, lambda, s_B);
     }
     __syncthreads();
-    const int64_t n = bw->n_acc, ns = bw->n_s;
-    if (flags_out && threadIdx.x < 2)
-        flags_out[threadIdx.x] = (n < ns ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | bw->flags;
-    if (!sample_p99) return;
-    NmfBasis B;
-    nmf_basis(s_W, lambda, B);
-    for (int j = 0; j < 2; ++j) {
-        double P = 0.0;
-        if (n > 0) {
-            int64_t k = (int64_t)ceil(q * (double)n);
-            k = k < 1 ? 1 : (k > n ? n : k);
-            P = block_select(n, k, [&](int64_t i) {
-                double h0, h1;
-                nmf_solve(B, V[i], V[ns + i], V[2 * ns + i], h0, h1);
-                return j == 0 ? h0 : h1;
-            }, s_hist, s_misc);
-        }
-        if (threadIdx.x == 0) sample_p99[j] = (float)P;
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ a batch of tiles
-
-struct TileArgs {
-    const spcn_tile* tiles;
-    int32_t n_tiles;
-    float i0[3];
-    int32_t white_sum;
-    double lambda;
-    double q;
-    int64_t n_s;
-    uint64_t seed;
-    int32_t n_iter;
-    const float* w_init;
-    float* w_out;
-    float* sample_p99;
-    int32_t* flags_out;
-};
-
-__global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
-    __shared__ int64_t s_idx[TILE_THREADS * TILE_SPT];
-    __shared__ double s_od[3 * kHistBins];
-    __shared__ int s_wave[TILE_THREADS / 64];
-    __shared__ double s_red[9 * 16];
-    __shared__ double s_sum[9];
-    __shared__ double s_W[6];
-    __shared__ NmfBasis s_B;
-    __shared__ uint32_t s_hist[256];
-    __shared__ int s_misc[2];
-    __shared__ int s_count;
-    const int tile = blockIdx.x;
-    const spcn_tile T = a.tiles[tile];
-    const int64_t n_px = T.height * T.width;
-    const uint64_t seed = a.seed + (uint64_t)tile;
-    const int64_t n_s = a.n_s, max_cand = 64 * a.n_s;
-
-    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
-        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)a.i0[c], k);
-    if (threadIdx.x == 0) { s_count = 0; initial_basis(a.w_init, s_W); }
-    __syncthreads();
-
-    // sampling, in draw order, one candidate per thread per step
-    for (int64_t t0 = 0; t0 < max_cand; t0 += blockDim.x) {
-        const int base = s_count;
-        if (base >= n_s) break;
-        const int64_t t = t0 + threadIdx.x;
-        bool keep = false;
-        int64_t pix = 0;
-        if (t < max_cand) {
-            pix = candidate_pixel(seed, (uint64_t)t, n_px);
-            keep = non_white(T.src, pix, a.white_sum);
-        }
-        int total;
-        const int r = block_rank(keep, s_wave, &total);
-        if (keep && base + r < n_s) s_idx[base + r] = pix;
-        if (threadIdx.x == 0) s_count = (int)min((int64_t)base + total, n_s);
-        __syncthreads();
-    }
-    const int n = s_count;
-
-    // samples in registers: sample s lives in thread s % TILE_THREADS, slot s / TILE_THREADS
-    double v[TILE_SPT][3];
-    bool live[TILE_SPT];
-#pragma unroll
-    for (int k = 0; k < TILE_SPT; ++k) {
-        const int s = k * TILE_THREADS + threadIdx.x;
-        live[k] = s < n;
-        const uint8_t* p = T.src + 3 * (live[k] ? s_idx[s] : 0);
-        for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? s_od[c * kHistBins + p[c]] : 0.0;
-    }
-
-    if (threadIdx.x == 0) nmf_basis(s_W, a.lambda, s_B);
-    __syncthreads();
-    for (int it = 0; it < a.n_iter; ++it) {
-        const NmfBasis B = s_B;
-        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < TILE_SPT; ++k) {
-            if (!live[k]) continue;
-            double h0, h1;
-            nmf_solve(B, v[k][0], v[k][1], v[k][2], h0, h1);
-            acc[0] += h0 * h0; acc[1] += h0 * h1; acc[2] += h1 * h1;
-            acc[3] += v[k][0] * h0; acc[4] += v[k][0] * h1;
-            acc[5] += v[k][1] * h0; acc[6] += v[k][1] * h1;
-            acc[7] += v[k][2] * h0; acc[8] += v[k][2] * h1;
-        }
-        block_sums(acc, s_red, s_sum);
-        if (threadIdx.x == 0) {    // one W-step for the workgroup
-            w_step(s_W, s_sum);
-            nmf_basis(s_W, a.lambda, s_B);
-        }
-        __syncthreads();
-    }
-    double W[6];
-    for (int i = 0; i < 6; ++i) W[i] = s_W[i];
-    finish_basis(W);
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 6; ++i) a.w_out[6 * tile + i] = (float)W[i];
-        if (a.flags_out)
-            for (int j = 0; j < 2; ++j)
-                a.flags_out[2 * tile + j] = (n < n_s ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0);
-    }
-    if (!a.sample_p99) return;
-    NmfBasis B;
-    nmf_basis(W, a.lambda, B);
-    double hv[TILE_SPT][2];
-#pragma unroll
-    for (int k = 0; k < TILE_SPT; ++k) nmf_solve(B, v[k][0], v[k][1], v[k][2], hv[k][0], hv[k][1]);
-    for (int j = 0; j < 2; ++j) {
-        double P = 0.0;
-        if (n > 0) {
-            int64_t kth = (int64_t)ceil(a.q * (double)n);
-            kth = kth < 1 ? 1 : (kth > n ? n : kth);
-            // radix select over the register-resident values: thread-owned slots are visited by
-            // index i = slot * TILE_THREADS + thread, so val() is only called with this thread's indices
-            uint64_t prefix = 0, pmask = 0;
-            int64_t kk = kth;
-            for (int shift = 56; shift >= 0; shift -= 8) {
-                for (int b = threadIdx.x; b < 256; b += blockDim.x) s_hist[b] = 0;
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < TILE_SPT; ++k) {
-                    if (!live[k]) continue;
-                    uint64_t u = (uint64_t)__double_as_longlong(hv[k][j]);
-                    if ((u & pmask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255], 1u);
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    int64_t acc = 0;
-                    int d = 0;
-                    for (; d < 256; ++d) {
-                        if (acc + (int64_t)s_hist[d] >= kk) break;
-                        acc += s_hist[d];
-                    }
-                    s_misc[0] = d;
-                    s_misc[1] = (int)(kk - acc);
-                }
-                __syncthreads();
-                prefix |= (uint64_t)s_misc[0] << shift;
-                pmask |= (uint64_t)255 << shift;
-                kk = s_misc[1];
-                __syncthreads();
-            }
-            P = __longlong_as_double((long long)prefix);
-        }
-        if (threadIdx.x == 0) a.sample_p99[2 * tile + j] = (float)P;
-    }
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------ launchers
-
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-static int64_t hmin(int64_t a, int64_t b) { return a < b ? a : b; }
-
-static int64_t round_candidates(int64_t n_s, int r) {
-    const int64_t mult[MAX_ROUNDS] = {4, 12, 48};
-    return mult[r] * n_s;
-}
-
-static int64_t max_round_blocks(int64_t n_s) {
-    return (round_candidates(n_s, MAX_ROUNDS - 1) + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK;
-}
-
-size_t basis_workspace_bytes(int64_t n_s) {
-    if (n_s <= 0) return 0;
-    const int64_t nb = max_round_blocks(n_s);
-    size_t b = align256(sizeof(BasisWork));
-    b += align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t));   // staging
-    b += align256((size_t)(nb + 1) * sizeof(int32_t));            // counts / offsets
-    b += align256((size_t)n_s * sizeof(int64_t));                 // idx
-    b += align256((size_t)3 * n_s * sizeof(double));              // V
-    b += align256((size_t)2 * FIT_MAX_BLOCKS * 9 * sizeof(double));  // partial sums
-    return b;
-}
-
-hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK& pk, float lambda_nmf,
-                                 int64_t n_s, uint64_t seed, int32_t n_iter, const float* w_init,
-                                 float* w_out, float* sample_p99, int32_t* flags_out, void* ws,
-                                 const DevInfo& dev, hipStream_t s) {
-    uint8_t* p = static_cast<uint8_t*>(ws);
-    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
-    const int64_t nbmax = max_round_blocks(n_s);
-    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
-    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
-    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
-    double* V = reinterpret_cast<double*>(p); p += align256((size_t)3 * n_s * sizeof(double));
-    double* partial = reinterpret_cast<double*>(p);
-
-    const int64_t max_cand = 64 * n_s;
-    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, w_init);
-    int64_t t0 = 0;
-    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
-        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
-        SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
-                     counts, idx};
-        launch_round(a, dev, s);
-        t0 += rc;
-    }
-    hipLaunchKernelGGL(k_od_gather, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s, img, idx,
-                       bw, pk.i0[0], pk.i0[1], pk.i0[2], V);
-    const int nblk = (int)((n_s + FIT_PER_BLOCK - 1) / FIT_PER_BLOCK);
-    if (nblk > FIT_MAX_BLOCKS) return hipErrorInvalidValue;
-    FitArgs fa{bw, V, partial, (double)lambda_nmf, n_iter};
-    if (n_iter > 0) hipLaunchKernelGGL(k_nmf_fit, dim3(nblk), dim3(FIT_THREADS), 0, s, fa);
-    hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(1024), 0, s, bw, (const double*)V, (double)lambda_nmf, pk.q64,
-                       w_out, sample_p99, flags_out);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------- channel-wise background intensity
-
-// Per-channel histogram of the sampled background pixels: workgroups take strided samples, count
-// into per-wavefront LDS copies (background values crowd into a few bins) and add to the global
-// [3][256] counts.
-__global__ __launch_bounds__(1024) void k_i0_hist(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
-                                                  uint32_t* ghist) {
-    __shared__ uint32_t s_hist[16][3 * kHistBins];
-    const int t = threadIdx.x, wave = t >> 6;
-    for (int i = t; i < 16 * 3 * kHistBins; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
-    __syncthreads();
-    const int64_t n = bw->n_acc;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + t; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t* p = img + 3 * idx[i];
-        atomicAdd(&s_hist[wave][p[0]], 1u);
-        atomicAdd(&s_hist[wave][kHistBins + p[1]], 1u);
-        atomicAdd(&s_hist[wave][2 * kHistBins + p[2]], 1u);
-    }
-    __syncthreads();
-    for (int b = t; b < 3 * kHistBins; b += blockDim.x) {
-        uint32_t sum = 0;
-        for (int w = 0; w < 16; ++w) sum += s_hist[w][b];
-        if (sum) atomicAdd(ghist + b, sum);
-    }
-}
-
-__global__ void k_i0_clear(uint32_t* ghist) {
-    for (int i = threadIdx.x; i < 3 * kHistBins; i += blockDim.x) ghist[i] = 0u;
-}
-
-// Nearest-rank percentile of each channel (one workgroup): k = max(1, ceil(q n)) in FP64, the
-// smallest value whose cumulative count reaches k.
-__global__ __launch_bounds__(256) void k_i0_select(const uint32_t* ghist, const BasisWork* bw, double q,
-                                                   float* i0_out, int32_t* flags_out) {
-    __shared__ uint32_t s_cum[3][kHistBins];
-    const int t = threadIdx.x;
-    if (t < 3) {   // 3 x 256 serial prefix sums
-        uint32_t run = 0;
-        for (int k = 0; k < kHistBins; ++k) { run += ghist[t * kHistBins + k]; s_cum[t][k] = run; }
-    }
-    __syncthreads();
-    const int64_t n = bw->n_acc, ns = bw->n_s;
-    if (n > 0) {
-        int64_t k = (int64_t)ceil(q * (double)n);
-        k = k < 1 ? 1 : (k > n ? n : k);
-        for (int c = 0; c < 3; ++c)
-            if ((int64_t)s_cum[c][t] >= k && (t == 0 || (int64_t)s_cum[c][t - 1] < k)) i0_out[c] = (float)t;
-    } else if (t < 3) {
-        i0_out[t] = 255.0f;
-    }
-    if (flags_out && t == 0)
-        flags_out[0] = (n == 0 ? SPCN_FLAG_NO_BACKGROUND : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
-}
-
-size_t i0_workspace_bytes(int64_t n_s) {
-    if (n_s <= 0) return 0;
-    const int64_t nb = max_round_blocks(n_s);
-    return align256(sizeof(BasisWork)) + align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t)) +
-           align256((size_t)(nb + 1) * sizeof(int32_t)) + align256((size_t)n_s * sizeof(int64_t)) +
-           align256((size_t)3 * kHistBins * sizeof(uint32_t));
-}
-
-hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
-                              double q, float* i0_out, int32_t* flags_out, void* ws, const DevInfo& dev,
-                              hipStream_t s) {
-    uint8_t* p = static_cast<uint8_t*>(ws);
-    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
-    const int64_t nbmax = max_round_blocks(n_s);
-    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
-    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
-    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
-    uint32_t* ghist = reinterpret_cast<uint32_t*>(p);
-    const int64_t max_cand = 64 * n_s;
-    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr);
-    hipLaunchKernelGGL(k_i0_clear, dim3(1), dim3(256), 0, s, ghist);
-    int64_t t0 = 0;
-    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
-        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
-        SampleArgs a{img, n_px, white_sum, seed, 1, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
-                     counts, idx};
-        launch_round(a, dev, s);
-        t0 += rc;
-    }
-    hipLaunchKernelGGL(k_i0_hist, dim3((unsigned)hmin((n_s + 1023) / 1024, 128)), dim3(1024), 0, s, img,
-                       (const int64_t*)idx, (const BasisWork*)bw, ghist);
-    hipLaunchKernelGGL(k_i0_select, dim3(1), dim3(256), 0, s, (const uint32_t*)ghist, (const BasisWork*)bw, q,
-                       i0_out, flags_out);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------- percentile of the sub-sampled pixels
-
-// FP64 densities (Eq. 2, W fixed, the density lambda) of the sampled pixels, planar [2][n_s].
-__global__ __launch_bounds__(256) void k_sample_dens(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
-                                                     const float* w, float lambda, float i00, float i01, float i02,
-                                                     double* H) {
-    __shared__ double s_od[3 * kHistBins];
-    __shared__ Basis64 B;
-    const float i0[3] = {i00, i01, i02};
-    if (threadIdx.x == 0) derive_basis(w, lambda, B);
-    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
-        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)i0[c], k);
-    __syncthreads();
+    const NmfBasis B = s_B;
     const int64_t n = bw->n_acc, ns = bw->n_s;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t* p = img + 3 * idx[i];
-        double h0 = 0.0, h1 = 0.0;
-        if (B.ok) solve64(B, s_od[p[0]], s_od[kHistBins + p[1]], s_od[2 * kHistBins + p[2]], h0, h1);
+        double h0, h1;
+        nmf_solve(B, V[i], V[ns + i], V[2 * ns + i], h0, h1);
         H[i] = h0;
         H[ns + i] = h1;
     }
@@ -948,6 +623,343 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* dhist,
     }
 }
 
+// ------------------------------------------------------------------ a batch of tiles
+
+struct TileArgs {
+    const spcn_tile* tiles;
+    int32_t n_tiles;
+    float i0[3];
+    int32_t white_sum;
+    double lambda;
+    double q;
+    int64_t n_s;
+    uint64_t seed;
+    int32_t n_iter;
+    const float* w_init;
+    float* w_out;
+    float* sample_p99;
+    int32_t* flags_out;
+};
+
+__global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
+    __shared__ int64_t s_idx[TILE_THREADS * TILE_SPT];
+    __shared__ double s_od[3 * kHistBins];
+    __shared__ int s_wave[TILE_THREADS / 64];
+    __shared__ double s_red[9 * 16];
+    __shared__ double s_sum[9];
+    __shared__ double s_W[6];
+    __shared__ NmfBasis s_B;
+    __shared__ uint32_t s_hist[256];
+    __shared__ int s_misc[2];
+    __shared__ int s_count;
+    const int tile = blockIdx.x;
+    const spcn_tile T = a.tiles[tile];
+    const int64_t n_px = T.height * T.width;
+    const uint64_t seed = a.seed + (uint64_t)tile;
+    const int64_t n_s = a.n_s, max_cand = 64 * a.n_s;
+
+    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
+        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)a.i0[c], k);
+    if (threadIdx.x == 0) { s_count = 0; initial_basis(a.w_init, s_W); }
+    __syncthreads();
+
+    // sampling, in draw order, one candidate per thread per step
+    for (int64_t t0 = 0; t0 < max_cand; t0 += blockDim.x) {
+        const int base = s_count;
+        if (base >= n_s) break;
+        const int64_t t = t0 + threadIdx.x;
+        bool keep = false;
+        int64_t pix = 0;
+        if (t < max_cand) {
+            pix = candidate_pixel(seed, (uint64_t)t, n_px);
+            keep = non_white(T.src, pix, a.white_sum);
+        }
+        int total;
+        const int r = block_rank(keep, s_wave, &total);
+        if (keep && base + r < n_s) s_idx[base + r] = pix;
+        if (threadIdx.x == 0) s_count = (int)min((int64_t)base + total, n_s);
+        __syncthreads();
+    }
+    const int n = s_count;
+
+    // samples in registers: sample s lives in thread s % TILE_THREADS, slot s / TILE_THREADS
+    double v[TILE_SPT][3];
+    bool live[TILE_SPT];
+#pragma unroll
+    for (int k = 0; k < TILE_SPT; ++k) {
+        const int s = k * TILE_THREADS + threadIdx.x;
+        live[k] = s < n;
+        const uint8_t* p = T.src + 3 * (live[k] ? s_idx[s] : 0);
+        for (int c = 0; c < 3; ++c) v[k][c] = live[k] ? s_od[c * kHistBins + p[c]] : 0.0;
+    }
+
+    if (threadIdx.x == 0) nmf_basis(s_W, a.lambda, s_B);
+    __syncthreads();
+    for (int it = 0; it < a.n_iter; ++it) {
+        const NmfBasis B = s_B;
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        nmf_sums(B, v, acc);
+        block_sums(acc, s_red, s_sum);
+        if (threadIdx.x == 0) {    // one W-step for the workgroup
+            w_step(s_W, s_sum);
+            nmf_basis(s_W, a.lambda, s_B);
+        }
+        __syncthreads();
+    }
+    double W[6];
+    for (int i = 0; i < 6; ++i) W[i] = s_W[i];
+    finish_basis(W);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 6; ++i) a.w_out[6 * tile + i] = (float)W[i];
+        if (a.flags_out)
+            for (int j = 0; j < 2; ++j)
+                a.flags_out[2 * tile + j] = (n < n_s ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0);
+    }
+    if (!a.sample_p99) return;
+    NmfBasis B;
+    nmf_basis(W, a.lambda, B);
+    double hv[TILE_SPT][2];
+#pragma unroll
+    for (int k = 0; k < TILE_SPT; ++k) nmf_solve(B, v[k][0], v[k][1], v[k][2], hv[k][0], hv[k][1]);
+    for (int j = 0; j < 2; ++j) {
+        double P = 0.0;
+        if (n > 0) {
+            int64_t kth = (int64_t)ceil(a.q * (double)n);
+            kth = kth < 1 ? 1 : (kth > n ? n : kth);
+            // radix select over the register-resident values: thread-owned slots are visited by
+            // index i = slot * TILE_THREADS + thread, so val() is only called with this thread's indices
+            uint64_t prefix = 0, pmask = 0;
+            int64_t kk = kth;
+            for (int shift = 56; shift >= 0; shift -= 8) {
+                for (int b = threadIdx.x; b < 256; b += blockDim.x) s_hist[b] = 0;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < TILE_SPT; ++k) {
+                    if (!live[k]) continue;
+                    uint64_t u = (uint64_t)__double_as_longlong(hv[k][j]);
+                    if ((u & pmask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255], 1u);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int64_t acc = 0;
+                    int d = 0;
+                    for (; d < 256; ++d) {
+                        if (acc + (int64_t)s_hist[d] >= kk) break;
+                        acc += s_hist[d];
+                    }
+                    s_misc[0] = d;
+                    s_misc[1] = (int)(kk - acc);
+                }
+                __syncthreads();
+                prefix |= (uint64_t)s_misc[0] << shift;
+                pmask |= (uint64_t)255 << shift;
+                kk = s_misc[1];
+                __syncthreads();
+            }
+            P = __longlong_as_double((long long)prefix);
+        }
+        if (threadIdx.x == 0) a.sample_p99[2 * tile + j] = (float)P;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int64_t hmin(int64_t a, int64_t b) { return a < b ? a : b; }
+
+static int64_t round_candidates(int64_t n_s, int r) {
+    const int64_t mult[MAX_ROUNDS] = {4, 12, 48};
+    return mult[r] * n_s;
+}
+
+static int64_t max_round_blocks(int64_t n_s) {
+    return (round_candidates(n_s, MAX_ROUNDS - 1) + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK;
+}
+
+size_t basis_workspace_bytes(int64_t n_s) {
+    if (n_s <= 0) return 0;
+    const int64_t nb = max_round_blocks(n_s);
+    size_t b = align256(sizeof(BasisWork));
+    b += align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t));   // staging
+    b += align256((size_t)(nb + 1) * sizeof(int32_t));            // counts / offsets
+    b += align256((size_t)n_s * sizeof(int64_t));                 // idx
+    b += align256((size_t)3 * n_s * sizeof(double));              // V
+    b += align256(FIT_XCHG_BYTES);                                // the fit's exchange slots
+    b += align256((size_t)2 * n_s * sizeof(double));              // fitted densities of the samples
+    b += align256(sizeof(SelState)) + align256((size_t)2 * SEL_BINS * sizeof(uint32_t));   // their percentile
+    return b;
+}
+
+// Nearest-rank percentile of both stains of H [2][n_s] (the first bw->n_acc values of each row):
+// the selection state, then six digit passes.
+static void launch_select(const BasisWork* bw, const double* H, int64_t n_s, double q, SelState* sel, uint32_t* dhist,
+                          float* p99_out, int32_t* flags_out, const DevInfo& dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, s, bw, q, sel, dhist);
+    const int64_t sel_want = hmin((n_s + 1023) / 1024, (int64_t)dev.cus);
+    const unsigned sel_grid = (unsigned)(sel_want > 0 ? sel_want : 1);
+    for (int pass = 0; pass < SEL_PASSES; ++pass) {
+        hipLaunchKernelGGL(k_sel_digits, dim3(sel_grid, 2), dim3(256), 0, s, H, n_s, (const SelState*)sel, dhist, pass);
+        hipLaunchKernelGGL(k_sel_pick, dim3(2), dim3(256), 0, s, sel, dhist, pass, n_s, p99_out, flags_out);
+    }
+}
+
+hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK& pk, float lambda_nmf,
+                                 int64_t n_s, uint64_t seed, int32_t n_iter, const float* w_init,
+                                 float* w_out, float* sample_p99, int32_t* flags_out, void* ws,
+                                 const DevInfo& dev, hipStream_t s) {
+    uint8_t* p = static_cast<uint8_t*>(ws);
+    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
+    const int64_t nbmax = max_round_blocks(n_s);
+    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
+    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
+    double* V = reinterpret_cast<double*>(p); p += align256((size_t)3 * n_s * sizeof(double));
+    double* xchg = reinterpret_cast<double*>(p); p += align256(FIT_XCHG_BYTES);
+    double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
+    SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
+    uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
+
+    const int64_t max_cand = 64 * n_s;
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, w_init, xchg);
+    int64_t t0 = 0;
+    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
+        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
+        SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
+                     counts, idx};
+        launch_round(a, dev, s);
+        t0 += rc;
+    }
+    hipLaunchKernelGGL(k_od_gather, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s, img, idx,
+                       bw, pk.i0[0], pk.i0[1], pk.i0[2], V);
+    const int nblk = (int)((n_s + FIT_PER_BLOCK - 1) / FIT_PER_BLOCK);
+    if (nblk > FIT_MAX_BLOCKS) return hipErrorInvalidValue;
+    FitArgs fa{bw, V, xchg, (double)lambda_nmf, n_iter};
+    if (n_iter > 0) hipLaunchKernelGGL(k_nmf_fit, dim3(nblk), dim3(FIT_THREADS), 0, s, fa);
+    hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(64), 0, s, bw, w_out, flags_out);
+    if (sample_p99) {
+        hipLaunchKernelGGL(k_nmf_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
+                           (const BasisWork*)bw, (const double*)V, (double)lambda_nmf, H);
+        launch_select(bw, H, n_s, pk.q64, sel, dhist, sample_p99, nullptr, dev, s);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- channel-wise background intensity
+
+// Per-channel histogram of the sampled background pixels: workgroups take strided samples, count
+// into per-wavefront LDS copies (background values crowd into a few bins) and add to the global
+// [3][256] counts.
+__global__ __launch_bounds__(1024) void k_i0_hist(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
+                                                  uint32_t* ghist) {
+    __shared__ uint32_t s_hist[16][3 * kHistBins];
+    const int t = threadIdx.x, wave = t >> 6;
+    for (int i = t; i < 16 * 3 * kHistBins; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
+    __syncthreads();
+    const int64_t n = bw->n_acc;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + t; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t* p = img + 3 * idx[i];
+        atomicAdd(&s_hist[wave][p[0]], 1u);
+        atomicAdd(&s_hist[wave][kHistBins + p[1]], 1u);
+        atomicAdd(&s_hist[wave][2 * kHistBins + p[2]], 1u);
+    }
+    __syncthreads();
+    for (int b = t; b < 3 * kHistBins; b += blockDim.x) {
+        uint32_t sum = 0;
+        for (int w = 0; w < 16; ++w) sum += s_hist[w][b];
+        if (sum) atomicAdd(ghist + b, sum);
+    }
+}
+
+__global__ void k_i0_clear(uint32_t* ghist) {
+    for (int i = threadIdx.x; i < 3 * kHistBins; i += blockDim.x) ghist[i] = 0u;
+}
+
+// Nearest-rank percentile of each channel (one workgroup): k = max(1, ceil(q n)) in FP64, the
+// smallest value whose cumulative count reaches k.
+__global__ __launch_bounds__(256) void k_i0_select(const uint32_t* ghist, const BasisWork* bw, double q,
+                                                   float* i0_out, int32_t* flags_out) {
+    __shared__ uint32_t s_cum[3][kHistBins];
+    const int t = threadIdx.x;
+    if (t < 3) {   // 3 x 256 serial prefix sums
+        uint32_t run = 0;
+        for (int k = 0; k < kHistBins; ++k) { run += ghist[t * kHistBins + k]; s_cum[t][k] = run; }
+    }
+    __syncthreads();
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    if (n > 0) {
+        int64_t k = (int64_t)ceil(q * (double)n);
+        k = k < 1 ? 1 : (k > n ? n : k);
+        for (int c = 0; c < 3; ++c)
+            if ((int64_t)s_cum[c][t] >= k && (t == 0 || (int64_t)s_cum[c][t - 1] < k)) i0_out[c] = (float)t;
+    } else if (t < 3) {
+        i0_out[t] = 255.0f;
+    }
+    if (flags_out && t == 0)
+        flags_out[0] = (n == 0 ? SPCN_FLAG_NO_BACKGROUND : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
+}
+
+size_t i0_workspace_bytes(int64_t n_s) {
+    if (n_s <= 0) return 0;
+    const int64_t nb = max_round_blocks(n_s);
+    return align256(sizeof(BasisWork)) + align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t)) +
+           align256((size_t)(nb + 1) * sizeof(int32_t)) + align256((size_t)n_s * sizeof(int64_t)) +
+           align256((size_t)3 * kHistBins * sizeof(uint32_t));
+}
+
+hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_sum, int64_t n_s, uint64_t seed,
+                              double q, float* i0_out, int32_t* flags_out, void* ws, const DevInfo& dev,
+                              hipStream_t s) {
+    uint8_t* p = static_cast<uint8_t*>(ws);
+    BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
+    const int64_t nbmax = max_round_blocks(n_s);
+    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
+    int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
+    uint32_t* ghist = reinterpret_cast<uint32_t*>(p);
+    const int64_t max_cand = 64 * n_s;
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr,
+                       (double*)nullptr);
+    hipLaunchKernelGGL(k_i0_clear, dim3(1), dim3(256), 0, s, ghist);
+    int64_t t0 = 0;
+    for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
+        const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
+        SampleArgs a{img, n_px, white_sum, seed, 1, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
+                     counts, idx};
+        launch_round(a, dev, s);
+        t0 += rc;
+    }
+    hipLaunchKernelGGL(k_i0_hist, dim3((unsigned)hmin((n_s + 1023) / 1024, 128)), dim3(1024), 0, s, img,
+                       (const int64_t*)idx, (const BasisWork*)bw, ghist);
+    hipLaunchKernelGGL(k_i0_select, dim3(1), dim3(256), 0, s, (const uint32_t*)ghist, (const BasisWork*)bw, q,
+                       i0_out, flags_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- percentile of the sub-sampled pixels
+
+// FP64 densities (Eq. 2, W fixed, the density lambda) of the sampled pixels, planar [2][n_s].
+__global__ __launch_bounds__(256) void k_sample_dens(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
+                                                     const float* w, float lambda, float i00, float i01, float i02,
+                                                     double* H) {
+    __shared__ double s_od[3 * kHistBins];
+    __shared__ Basis64 B;
+    const float i0[3] = {i00, i01, i02};
+    if (threadIdx.x == 0) derive_basis(w, lambda, B);
+    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
+        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)i0[c], k);
+    __syncthreads();
+    const int64_t n = bw->n_acc, ns = bw->n_s;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t* p = img + 3 * idx[i];
+        double h0 = 0.0, h1 = 0.0;
+        if (B.ok) solve64(B, s_od[p[0]], s_od[kHistBins + p[1]], s_od[2 * kHistBins + p[2]], h0, h1);
+        H[i] = h0;
+        H[ns + i] = h1;
+    }
+}
+
 size_t sample_pctl_workspace_bytes(int64_t n_s) {
     if (n_s <= 0) return 0;
     return i0_workspace_bytes(n_s) + align256((size_t)2 * n_s * sizeof(double)) + align256(sizeof(SelState)) +
@@ -967,7 +979,8 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
     uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
     const int64_t max_cand = 64 * n_s;
-    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr);
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr,
+                       (double*)nullptr);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
@@ -978,14 +991,7 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     }
     hipLaunchKernelGGL(k_sample_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
                        img, (const int64_t*)idx, (const BasisWork*)bw, w, pk.lambda, pk.i0[0], pk.i0[1], pk.i0[2], H);
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, s, (const BasisWork*)bw, pk.q64, sel, dhist);
-    const int64_t sel_want = hmin((n_s + 1023) / 1024, (int64_t)dev.cus);
-    const unsigned sel_grid = (unsigned)(sel_want > 0 ? sel_want : 1);
-    for (int pass = 0; pass < SEL_PASSES; ++pass) {
-        hipLaunchKernelGGL(k_sel_digits, dim3(sel_grid, 2), dim3(256), 0, s, (const double*)H, n_s,
-                           (const SelState*)sel, dhist, pass);
-        hipLaunchKernelGGL(k_sel_pick, dim3(2), dim3(256), 0, s, sel, dhist, pass, n_s, p99_out, flags_out);
-    }
+    launch_select(bw, H, n_s, pk.q64, sel, dhist, p99_out, flags_out, dev, s);
     return hipGetLastError();
 }
 
