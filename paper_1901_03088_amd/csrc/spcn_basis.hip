@@ -14,9 +14,9 @@
 //
 // Two layouts:
 //   * one image with many samples: one launch for all rounds, up to 64 workgroups holding 4096
-//     samples each in registers; per round FP64 partial sums per workgroup, an arrival counter, and
-//     the same fixed-order reduction and W-step in every workgroup;
-//   * a batch of tiles: one 1024-thread workgroup per tile, samples held in registers, every round
+//     samples each in registers; per round FP64 partial sums per workgroup published with a
+//     sequence word, and the same fixed-order reduction and W-step in every workgroup;
+//   * a batch of tiles: one 256-thread workgroup per tile, samples held in registers, every round
 //     inside the workgroup.
 #include "spcn_internal.h"
 #include "spcn_device.hpp"
