@@ -285,40 +285,45 @@ struct SampleArgs {
     const uint8_t* img; int64_t n_px; int32_t white_sum; uint64_t seed;
     int32_t background;     // keep pixels with R + G + B > white_sum instead of non-white ones
     int64_t t0, t_end;      // candidates [t0, t_end) form this round
-    int64_t nb;             // workgroups in this round
+    int64_t nb;             // candidate groups in this round
     BasisWork* bw;
-    int64_t* staging;       // [nb][SAMPLE_BLOCK]
-    int32_t* counts;        // [nb] kept candidates per workgroup; the scan turns them into offsets
+    uint64_t* staging;      // [nb][SAMPLE_BLOCK] kept candidates: pixel index | R << 40 | G << 48 | B << 56
+    int32_t* counts;        // [nb + 1] kept candidates per group; the round's scan turns them into offsets
     int64_t* idx;           // [n_s] kept pixel indices
+    const double* od;       // [3][256] optical densities (Eq. 1) when V is set
+    double* V;              // [3][n_s] optical densities of the kept samples, or null
 };
 
-// Grid-stride over the round's candidate groups (SAMPLE_BLOCK candidates each), so that a round
-// made unnecessary by earlier ones costs one small launch.
+constexpr int STAGE_PIX_BITS = 40;   // pixel indices stay below 2^36 (the entry points' limit)
+
+// Draws the round's candidate groups (SAMPLE_BLOCK candidates each, grid-stride, so that a round
+// made unnecessary by earlier ones costs one small launch) and keeps each group's non-white
+// candidates in draw order, with their bytes.
 __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_round(SampleArgs a) {
     __shared__ int s_wave[SAMPLE_BLOCK / 64];
     if (a.bw->n_acc >= a.bw->n_s) return;                  // earlier rounds found enough
     for (int64_t b = blockIdx.x; b < a.nb; b += gridDim.x) {
         const int64_t t = a.t0 + b * SAMPLE_BLOCK + threadIdx.x;
         bool keep = false;
-        int64_t pix = 0;
+        uint64_t packed = 0;
         if (t < a.t_end) {
-            pix = candidate_pixel(a.seed, (uint64_t)t, a.n_px);
-            if (a.background) {
-                const uint8_t* q = a.img + 3 * pix;
-                keep = (int32_t)q[0] + (int32_t)q[1] + (int32_t)q[2] > a.white_sum;
-            } else {
-                keep = non_white(a.img, pix, a.white_sum);
-            }
+            const int64_t pix = candidate_pixel(a.seed, (uint64_t)t, a.n_px);
+            const uint8_t* q = a.img + 3 * pix;
+            const uint32_t R = q[0], G = q[1], B = q[2];
+            const int32_t sum = (int32_t)(R + G + B);
+            keep = a.background ? sum > a.white_sum : (a.white_sum <= 0 || sum < a.white_sum);
+            packed = (uint64_t)pix | ((uint64_t)R << STAGE_PIX_BITS) | ((uint64_t)G << (STAGE_PIX_BITS + 8)) |
+                     ((uint64_t)B << (STAGE_PIX_BITS + 16));
         }
         int total;
         const int r = block_rank(keep, s_wave, &total);
-        if (keep) a.staging[b * SAMPLE_BLOCK + r] = pix;
+        if (keep) a.staging[b * SAMPLE_BLOCK + r] = packed;
         if (threadIdx.x == 0) a.counts[b] = total;
     }
 }
 
-// Exclusive scan of the round's per-workgroup counts (one workgroup), in place: counts[b] becomes
-// the rank of workgroup b's first kept candidate within the round and counts[nb] the round's total.
+// Exclusive scan of the round's per-group counts (one workgroup), in place: counts[b] becomes the
+// rank of group b's first kept candidate within the round and counts[nb] the round's total.
 // Records the samples kept before the round and the new total (capped at n_s).
 __global__ __launch_bounds__(1024) void k_sample_scan(SampleArgs a) {
     __shared__ int s_part[1024];
@@ -370,7 +375,16 @@ __global__ __launch_bounds__(SAMPLE_BLOCK) void k_sample_copy(SampleArgs a) {
         const int64_t off = a.counts[b];
         const int64_t c = a.counts[b + 1] - off;   // kept in this candidate group
         const int i = threadIdx.x;
-        if (i < c && off + i < room) a.idx[base + off + i] = a.staging[b * SAMPLE_BLOCK + i];
+        if (i < c && off + i < room) {
+            const uint64_t packed = a.staging[b * SAMPLE_BLOCK + i];
+            const int64_t k = base + off + i;
+            a.idx[k] = (int64_t)(packed & ((1ull << STAGE_PIX_BITS) - 1));
+            if (a.V) {
+                const int64_t ns = bw->n_s;
+                for (int ch = 0; ch < 3; ++ch)
+                    a.V[ch * ns + k] = a.od[ch * kHistBins + (int)((packed >> (STAGE_PIX_BITS + 8 * ch)) & 255u)];
+            }
+        }
     }
 }
 
@@ -383,28 +397,22 @@ static void launch_round(const SampleArgs& a, const DevInfo& dev, hipStream_t s)
     hipLaunchKernelGGL(k_sample_copy, dim3(grid), dim3(SAMPLE_BLOCK), 0, s, a);
 }
 
-__global__ void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init, double* xchg) {
+// Workspace state of a sampling run (one workgroup of 256 threads).  With od set, also the FP64
+// optical densities od[c][k] of Eq. 1 for the given i0, which the copy stores per kept sample; with
+// xchg set, the fit's sequence words start below every round number.
+__global__ __launch_bounds__(256) void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init,
+                                                    double* xchg, double* od, float i00, float i01, float i02) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->base = 0; bw->flags = 0;
         initial_basis(w_init, bw->W);
     }
-    if (xchg)   // the fit's sequence words start below every round number
+    if (xchg)
         for (int i = threadIdx.x; i < 2 * FIT_MAX_BLOCKS; i += blockDim.x)
             *fit_seq(xchg, i / FIT_MAX_BLOCKS, i % FIT_MAX_BLOCKS) = 0u;
-}
-
-// FP64 optical densities of the kept samples, planar [3][n_s].
-__global__ __launch_bounds__(256) void k_od_gather(const uint8_t* img, const int64_t* idx, const BasisWork* bw,
-                                                   float i00, float i01, float i02, double* V) {
-    __shared__ double s_od[3 * kHistBins];
-    const float i0[3] = {i00, i01, i02};
-    for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
-        for (int c = 0; c < 3; ++c) s_od[c * kHistBins + k] = od_u8((double)i0[c], k);
-    __syncthreads();
-    const int64_t n = bw->n_acc, ns = bw->n_s;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t* p = img + 3 * idx[i];
-        for (int c = 0; c < 3; ++c) V[c * ns + i] = s_od[c * kHistBins + p[c]];
+    if (od) {
+        const float i0[3] = {i00, i01, i02};
+        for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
+            for (int c = 0; c < 3; ++c) od[c * kHistBins + k] = od_u8((double)i0[c], k);
     }
 }
 
@@ -782,10 +790,11 @@ size_t basis_workspace_bytes(int64_t n_s) {
     if (n_s <= 0) return 0;
     const int64_t nb = max_round_blocks(n_s);
     size_t b = align256(sizeof(BasisWork));
-    b += align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t));   // staging
+    b += align256((size_t)nb * SAMPLE_BLOCK * sizeof(uint64_t));  // staging
     b += align256((size_t)(nb + 1) * sizeof(int32_t));            // counts / offsets
     b += align256((size_t)n_s * sizeof(int64_t));                 // idx
     b += align256((size_t)3 * n_s * sizeof(double));              // V
+    b += align256((size_t)3 * kHistBins * sizeof(double));        // optical-density table
     b += align256(FIT_XCHG_BYTES);                                // the fit's exchange slots
     b += align256((size_t)2 * n_s * sizeof(double));              // fitted densities of the samples
     b += align256(sizeof(SelState)) + align256((size_t)2 * SEL_BINS * sizeof(uint32_t));   // their percentile
@@ -809,32 +818,32 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
                                  int64_t n_s, uint64_t seed, int32_t n_iter, const float* w_init,
                                  float* w_out, float* sample_p99, int32_t* flags_out, void* ws,
                                  const DevInfo& dev, hipStream_t s) {
+    const int nblk = (int)((n_s + FIT_PER_BLOCK - 1) / FIT_PER_BLOCK);
+    if (nblk > FIT_MAX_BLOCKS) return hipErrorInvalidValue;
     uint8_t* p = static_cast<uint8_t*>(ws);
     BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
     const int64_t nbmax = max_round_blocks(n_s);
-    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    uint64_t* staging = reinterpret_cast<uint64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(uint64_t));
     int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
     double* V = reinterpret_cast<double*>(p); p += align256((size_t)3 * n_s * sizeof(double));
+    double* od = reinterpret_cast<double*>(p); p += align256((size_t)3 * kHistBins * sizeof(double));
     double* xchg = reinterpret_cast<double*>(p); p += align256(FIT_XCHG_BYTES);
     double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
     SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
     uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
 
     const int64_t max_cand = 64 * n_s;
-    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, w_init, xchg);
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, w_init, xchg, od, pk.i0[0], pk.i0[1],
+                       pk.i0[2]);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
         SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
-                     counts, idx};
+                     counts, idx, od, V};
         launch_round(a, dev, s);
         t0 += rc;
     }
-    hipLaunchKernelGGL(k_od_gather, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s, img, idx,
-                       bw, pk.i0[0], pk.i0[1], pk.i0[2], V);
-    const int nblk = (int)((n_s + FIT_PER_BLOCK - 1) / FIT_PER_BLOCK);
-    if (nblk > FIT_MAX_BLOCKS) return hipErrorInvalidValue;
     FitArgs fa{bw, V, xchg, (double)lambda_nmf, n_iter};
     if (n_iter > 0) hipLaunchKernelGGL(k_nmf_fit, dim3(nblk), dim3(FIT_THREADS), 0, s, fa);
     hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(64), 0, s, bw, w_out, flags_out);
@@ -903,7 +912,7 @@ __global__ __launch_bounds__(256) void k_i0_select(const uint32_t* ghist, const 
 size_t i0_workspace_bytes(int64_t n_s) {
     if (n_s <= 0) return 0;
     const int64_t nb = max_round_blocks(n_s);
-    return align256(sizeof(BasisWork)) + align256((size_t)nb * SAMPLE_BLOCK * sizeof(int64_t)) +
+    return align256(sizeof(BasisWork)) + align256((size_t)nb * SAMPLE_BLOCK * sizeof(uint64_t)) +
            align256((size_t)(nb + 1) * sizeof(int32_t)) + align256((size_t)n_s * sizeof(int64_t)) +
            align256((size_t)3 * kHistBins * sizeof(uint32_t));
 }
@@ -914,19 +923,19 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
     uint8_t* p = static_cast<uint8_t*>(ws);
     BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
     const int64_t nbmax = max_round_blocks(n_s);
-    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    uint64_t* staging = reinterpret_cast<uint64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(uint64_t));
     int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
     uint32_t* ghist = reinterpret_cast<uint32_t*>(p);
     const int64_t max_cand = 64 * n_s;
-    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr,
-                       (double*)nullptr);
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, (const float*)nullptr,
+                       (double*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
     hipLaunchKernelGGL(k_i0_clear, dim3(1), dim3(256), 0, s, ghist);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
         SampleArgs a{img, n_px, white_sum, seed, 1, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
-                     counts, idx};
+                     counts, idx, nullptr, nullptr};
         launch_round(a, dev, s);
         t0 += rc;
     }
@@ -972,20 +981,20 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     uint8_t* p = static_cast<uint8_t*>(ws);
     BasisWork* bw = reinterpret_cast<BasisWork*>(p); p += align256(sizeof(BasisWork));
     const int64_t nbmax = max_round_blocks(n_s);
-    int64_t* staging = reinterpret_cast<int64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(int64_t));
+    uint64_t* staging = reinterpret_cast<uint64_t*>(p); p += align256((size_t)nbmax * SAMPLE_BLOCK * sizeof(uint64_t));
     int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
     double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
     SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
     uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
     const int64_t max_cand = 64 * n_s;
-    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(64), 0, s, bw, n_s, max_cand, (const float*)nullptr,
-                       (double*)nullptr);
+    hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, (const float*)nullptr,
+                       (double*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
         SampleArgs a{img, n_px, pk.white_sum, seed, 0, t0, t0 + rc, (rc + SAMPLE_BLOCK - 1) / SAMPLE_BLOCK, bw, staging,
-                     counts, idx};
+                     counts, idx, nullptr, nullptr};
         launch_round(a, dev, s);
         t0 += rc;
     }
