@@ -324,7 +324,7 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
  *                              4 = (1, 512), 5 = (16, 1024) (default 3)
  *   SPCN_OPT_P2_BLOCKS_PER_CU  pass-2 workgroups per compute unit, 1..16 (default 8)
  *   SPCN_OPT_BATCH_CHUNK       batched normalisation: log2 of the 4-pixel units in one work item,
- *                              12..16 (default 15 = 131072 pixels)
+ *                              12..18 (default 15 = 131072 pixels)
  * spcn_set_option returns SPCN_E_ARG for an unknown option or a value out of range. */
 #define SPCN_OPT_P1_VARIANT       0
 #define SPCN_OPT_P2_VARIANT       1

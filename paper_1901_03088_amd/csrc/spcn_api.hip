@@ -16,7 +16,7 @@ static thread_local char g_err[512];
 constexpr int N_OPT = 4;
 static std::atomic<int> g_opt[N_OPT] = {{6}, {3}, {8}, {15}};   // fastest measured on a 2-gigapixel slide
 static const int g_opt_lo[N_OPT] = {0, 0, 1, 12};
-static const int g_opt_hi[N_OPT] = {9, 5, 16, 16};
+static const int g_opt_hi[N_OPT] = {9, 5, 16, 18};
 
 int option(int id) { return (id >= 0 && id < N_OPT) ? g_opt[id].load(std::memory_order_relaxed) : 0; }
 

@@ -251,6 +251,33 @@ __device__ inline void initial_basis(const float* w_init, double* W) {
     }
 }
 
+// The bin holding the kk-th smallest (1-based) value of a 256-bin digit histogram and kk's rank
+// within that bin (s_misc[0], s_misc[1]), by a parallel inclusive scan: threads 0..255 one bin each
+// (wavefront shuffles, then the four wavefront totals).  blockDim.x >= 256; ends with a barrier.
+__device__ void pick_digit256(const uint32_t* s_hist, int64_t kk, uint32_t* s_wsum, int* s_misc) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t c = 0, incl = 0;
+    if (t < 256) {                      // whole wavefronts
+        c = s_hist[t];
+        incl = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t up = __shfl_up(incl, o);
+            if (lane >= o) incl += up;
+        }
+        if (lane == 63) s_wsum[w] = incl;
+    }
+    if (t == 0) { s_misc[0] = 255; s_misc[1] = 1; }   // only if the counts fall short of kk
+    __syncthreads();
+    if (t < 256) {
+        for (int i = 0; i < w; ++i) incl += s_wsum[i];
+        if ((int64_t)(incl - c) < kk && kk <= (int64_t)incl) {   // exactly one bin
+            s_misc[0] = t;
+            s_misc[1] = (int)(kk - (int64_t)(incl - c));
+        }
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------------------------ one image, many samples
 
 struct BasisWork {          // layout of the caller's workspace (single image)
@@ -658,6 +685,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
     __shared__ double s_W[6];
     __shared__ NmfBasis s_B;
     __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_wsum[4];
     __shared__ int s_misc[2];
     __shared__ int s_count;
     const int tile = blockIdx.x;
@@ -671,7 +699,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
     if (threadIdx.x == 0) { s_count = 0; initial_basis(a.w_init, s_W); }
     __syncthreads();
 
-    // sampling, in draw order, one candidate per thread per step
+    // sampling, in draw order, one candidate per thread per step (four per thread and step, their
+    // pixel reads in flight together, measured slower)
     for (int64_t t0 = 0; t0 < max_cand; t0 += blockDim.x) {
         const int base = s_count;
         if (base >= n_s) break;
@@ -734,8 +763,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
         if (n > 0) {
             int64_t kth = (int64_t)ceil(a.q * (double)n);
             kth = kth < 1 ? 1 : (kth > n ? n : kth);
-            // radix select over the register-resident values: thread-owned slots are visited by
-            // index i = slot * TILE_THREADS + thread, so val() is only called with this thread's indices
+            // radix select over the register-resident values: 8-bit digits of the FP64 bit patterns
+            // (monotone for values >= 0) from the top, each digit picked by a parallel scan
             uint64_t prefix = 0, pmask = 0;
             int64_t kk = kth;
             for (int shift = 56; shift >= 0; shift -= 8) {
@@ -748,17 +777,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
                     if ((u & pmask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255], 1u);
                 }
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    int64_t acc = 0;
-                    int d = 0;
-                    for (; d < 256; ++d) {
-                        if (acc + (int64_t)s_hist[d] >= kk) break;
-                        acc += s_hist[d];
-                    }
-                    s_misc[0] = d;
-                    s_misc[1] = (int)(kk - acc);
-                }
-                __syncthreads();
+                pick_digit256(s_hist, kk, s_wsum, s_misc);
                 prefix |= (uint64_t)s_misc[0] << shift;
                 pmask |= (uint64_t)255 << shift;
                 kk = s_misc[1];

@@ -121,7 +121,7 @@ def test_options_ranges(lib):
     assert saved == [6, 3, 8, 15]
     try:
         for opt, lo, hi in ((lib.OPT_P1_VARIANT, 0, 9), (lib.OPT_P2_VARIANT, 0, 5),
-                            (lib.OPT_P2_BLOCKS_PER_CU, 1, 16), (lib.OPT_BATCH_CHUNK, 12, 16)):
+                            (lib.OPT_P2_BLOCKS_PER_CU, 1, 16), (lib.OPT_BATCH_CHUNK, 12, 18)):
             for v in (lo, hi):
                 lib.set_option(opt, v)
                 assert lib.get_option(opt) == v

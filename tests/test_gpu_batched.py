@@ -73,7 +73,7 @@ def test_batched_chunk_sizes_identical(S):
     saved = S.get_option(S.OPT_BATCH_CHUNK)
     ref = None
     try:
-        for c in (12, 13, 14, 15, 16):
+        for c in (12, 13, 14, 15, 16, 17, 18):
             S.set_option(S.OPT_BATCH_CHUNK, c)
             for o in outs:
                 o.zero_()
