@@ -256,7 +256,9 @@ typedef struct {
 
 /* Basis estimation for every tile of a batch (same algorithm as spcn_estimate_basis, one
  * workgroup per tile).  tiles: device array of n_tiles descriptors; w_out [n_tiles][6];
- * sample_p99 [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.  Tile t uses seed + t. */
+ * sample_p99 [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.  Tile t uses seed + t.  A
+ * descriptor with a NULL source or no pixels is not read: its basis is the initial one, its
+ * percentiles 0 and its flags SPCN_FLAG_SHORT | SPCN_FLAG_NO_TISSUE. */
 spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t max_tile_px,
                                         const spcn_params* p, float lambda_nmf, int64_t n_samples,
                                         uint64_t seed, int32_t n_iter, const float* w_init,

@@ -96,3 +96,27 @@ def test_estimate_basis_batched_tiles(S, orc):
         ang = col_angles(w[t], Wo)
         assert ang.max() < 1e-6, (t, ang)
         assert np.allclose(sp[t], spo, rtol=1e-6)
+
+
+def test_estimate_basis_batched_empty_descriptors(S, orc):
+    """Descriptors without pixels (NULL source, zero height or width) are not read: initial basis,
+    zero percentiles, SHORT | NO_TISSUE; the real tile beside them is unaffected."""
+    d = synth.make_tile(3, 256, 192, device=DEV)
+    img = d["img"]
+    rows = [[0, 0, 0, 0], [img.data_ptr(), 0, 0, 192], [img.data_ptr(), 0, 256, 0],
+            [img.data_ptr(), 0, 256, 192]]
+    table = torch.tensor(rows, dtype=torch.int64).to(DEV)
+    p = S.params()
+    w, sp, flags = S.spcn_estimate_basis_batched(table, 4, 1024, seed=70, p=p, lambda_nmf=0.1, n_iter=20)
+    torch.cuda.synchronize()
+    w = w.cpu().numpy(); sp = sp.cpu().numpy(); flags = flags.cpu().numpy()
+    H0 = np.array([0.65, 0.70, 0.29]); E0 = np.array([0.07, 0.99, 0.11])
+    ref = orc.f32(np.concatenate([H0 / np.linalg.norm(H0), E0 / np.linalg.norm(E0)]))   # column-major [6]
+    for t in range(3):
+        assert col_angles(w[t], ref).max() < 1e-6, t
+        assert (sp[t] == 0).all()
+        assert (flags[t] == (S.FLAG_SHORT | S.FLAG_NO_TISSUE)).all(), flags[t]
+    Wo, spo, _ = oracle_fit(orc, img.cpu().numpy(), 1024, 70 + 3, orc.f32(0.1), 20, p)
+    assert col_angles(w[3], Wo).max() < 1e-6
+    assert np.allclose(sp[3], spo, rtol=1e-6)
+    assert (flags[3] == 0).all()
