@@ -189,3 +189,24 @@ def test_exact_percentile_on_config1(S, orc):
     print(f"\n[exact] config1: gpu {g} oracle {o_P} histogram {st['p99_src'].cpu().numpy()}")
     assert _close32(g, o_P)
     assert np.all(np.abs(g - st["p99_src"].cpu().numpy()) <= 4.0 / 256)
+
+
+def test_exact_percentile_list_overflow(S, orc):
+    """All 2^24 colours once each with a histogram range of 256 (bins one density unit wide): the
+    crossing bins hold more colours than the (key, count) list takes (2^21), so the digit passes scan
+    the colour table instead.  At the median both stains overflow (5.9M and 13.8M colours in the
+    bin); at q = 90 stain 0 overflows (2.27M) and stain 1 does not (1.64M)."""
+    idx = torch.arange(1 << 24, dtype=torch.int64, device=DEV)
+    cube = torch.stack([idx & 255, (idx >> 8) & 255, idx >> 16], dim=1).to(torch.uint8).view(4096, 4096, 3)
+    W = S.as_basis(synth.reference_basis(), DEV)
+    Wn = orc.f32(orc.basis(synth.reference_basis()))
+    host = cube.cpu().numpy()
+    ws = S.workspace(S.workspace_size(S.OP_EXACT_PERCENTILE, 0, 0, 0), DEV)
+    for q in (50.0, 90.0):
+        p = S.params(percentile=q, hist_hi=(256.0, 256.0))
+        P, fl = S.spcn_exact_percentile(cube, W, p, ws=ws)
+        torch.cuda.synchronize()
+        o_P, n, o_f = orc.exact_percentile(host, Wn, lam=orc.f32(p.lambda_), percentile=q)
+        print(f"[exact overflow q={q}] gpu {P.cpu().numpy()} oracle {o_P} (n = {n})", flush=True)
+        assert _close32(P.cpu().numpy(), o_P)
+        assert int(fl.cpu().numpy().max()) == 0
