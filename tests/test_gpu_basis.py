@@ -68,6 +68,8 @@ def test_estimate_basis_short_and_white(S, orc):
     torch.cuda.synchronize()
     f = flags.cpu().numpy()
     assert (f & S.FLAG_NO_TISSUE).all() and (f & S.FLAG_SHORT).all()
+    assert (sp.cpu().numpy() == 0).all()          # no samples: the percentile of nothing is 0
+    assert np.isfinite(w.cpu().numpy()).all()
 
 
 def test_estimate_basis_large_sample(S, orc):
