@@ -23,8 +23,8 @@ from . import (OPT_BATCH_CHUNK, OPT_P1_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_P2_VAR
                OP_NORMALIZE_BATCHED)
 
 P1_CANDIDATES = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9)
-P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 1), (3, 1), (3, 2), (3, 4), (3, 8), (4, 1), (4, 2),
-                 (4, 4), (5, 1))
+P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 1), (3, 1), (3, 2), (3, 4), (3, 6), (3, 8), (4, 1),
+                 (4, 2), (4, 3), (4, 4), (5, 1))
 CHUNK_CANDIDATES = (12, 13, 14, 15, 16, 17, 18)
 
 
@@ -43,12 +43,14 @@ def _median_ms(fn: Callable[[], None], reps: int) -> float:
 
 
 def _sweep(cands: Iterable, apply: Callable, run: Callable[[], None], result: Callable[[], List[torch.Tensor]],
-           reps: int) -> Tuple[object, List[dict]]:
+           reps: int, finalists: int = 3, rounds: int = 3) -> Tuple[object, List[dict]]:
     """Times every candidate; a candidate whose results differ from the first one's is rejected
-    (raises: variants are required to be identical)."""
+    (raises: variants are required to be identical).  The fastest few are then timed again in
+    interleaved rounds and the lowest median over those rounds wins, so that a single noisy
+    measurement (the first candidate timed while the device warms up, a neighbour's burst) does not
+    decide."""
     ref = None
     rows = []
-    best, best_ms = None, math.inf
     for c in cands:
         apply(c)
         ms = _median_ms(run, reps)
@@ -58,9 +60,19 @@ def _sweep(cands: Iterable, apply: Callable, run: Callable[[], None], result: Ca
         elif not all(torch.equal(a, b) for a, b in zip(ref, cur)):
             raise RuntimeError(f"autotune: variant {c} changed the results")
         rows.append({"candidate": c, "ms": round(ms, 4)})
-        if ms < best_ms:
-            best, best_ms = c, ms
-    return best, rows
+    top = [r["candidate"] for r in sorted(rows, key=lambda r: r["ms"])[:finalists]]
+    again = {i: [] for i in range(len(top))}
+    for _ in range(rounds):
+        for i, c in enumerate(top):
+            apply(c)
+            again[i].append(_median_ms(run, reps))
+    final = {i: sorted(v)[len(v) // 2] for i, v in again.items()}
+    best_i = min(final, key=final.get)
+    for r in rows:
+        for i, c in enumerate(top):
+            if r["candidate"] == c:
+                r["final_ms"] = round(final[i], 4)
+    return top[best_i], rows
 
 
 def size_class(n_px: int) -> int:
@@ -128,7 +140,7 @@ def tune_image(img: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scal
     best2, rows2 = _sweep(P2_CANDIDATES, p2_set, p2_run, lambda: [out], reps)
     p2_set(best2)
     res = {"options": {"p1_variant": best1, "p2_variant": best2[0], "p2_blocks_per_cu": best2[1]},
-           "pass1": rows1, "pass2": [{"candidate": list(r["candidate"]), "ms": r["ms"]} for r in rows2],
+           "pass1": rows1, "pass2": [dict(r, candidate=list(r["candidate"])) for r in rows2],
            "key": key, "cached": False}
     if cache_path:
         cache[key] = {k: v for k, v in res.items() if k != "cached"}

@@ -266,3 +266,28 @@ def test_option_validation(S):
     assert S._L.spcn_set_option(0, 10) == S.SPCN_E_ARG
     assert S._L.spcn_set_option(7, 0) == S.SPCN_E_ARG
     assert S.get_option(7) == -1
+
+
+def test_autotune_image_sets_a_measured_choice(S, orc):
+    """The tuner times every pass-1 and pass-2 variant on a 1024^2 image (identical bytes required,
+    else it raises), re-times its finalists, leaves the winner set and reports every timing; the
+    normalisation under the chosen options still matches the oracle."""
+    from paper_1901_03088_amd import autotune
+    src = synth.make_image(0, 1024, 1024, device=DEV)
+    tgt = synth.make_image(1, 1024, 1024, device=DEV)
+    p = S.params()
+    ws, wt = S.as_basis(src["W"], DEV), S.as_basis(tgt["W"], DEV)
+    _, _, sc, _ = S.spcn_densities(tgt["img"], wt, p, want_h=False)
+    saved = autotune.current()
+    try:
+        res = autotune.tune_image(src["img"], ws, wt, sc, p, reps=3)
+        cur = autotune.current()
+        for k in ("p1_variant", "p2_variant", "p2_blocks_per_cu"):
+            assert cur[k] == res["options"][k], k
+        assert len(res["pass1"]) == len(autotune.P1_CANDIDATES) and len(res["pass2"]) == len(autotune.P2_CANDIDATES)
+        assert sum("final_ms" in r for r in res["pass1"]) == 3 and sum("final_ms" in r for r in res["pass2"]) == 3
+        out, st, sc2 = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], p)
+        o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc2, p)
+        check_normalize("autotuned", out, st, o_out, o_st, o_hist)
+    finally:
+        autotune.apply(saved)
