@@ -120,10 +120,10 @@ def timed(fn, steps, warmup, stream):
     return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
 
 
-def bench_batched(dev, S, synth, steps, warmup, n_tiles=512):
+def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True):
     """512 uneven tiles (sides 256..2048 step 64), per-tile basis fit (4096 samples, 50 rounds,
     lambda 0.1) and normalisation to one target, captured in one hipGraph and replayed; against a
-    per-tile loop of the plain single-image path (same work, same results)."""
+    per-tile loop of the plain single-image path (same work, same results) unless loop is False."""
     import torch
     shapes = synth.tile_shapes(n_tiles)
     srcs = [synth.make_tile(t, h, w, device=dev)["img"] for t, (h, w) in enumerate(shapes)]
@@ -156,19 +156,22 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512):
         run()
     stream = torch.cuda.current_stream()
     ms_graph = timed(g.replay, steps, warmup, stream)
+    res = {"tiles": n_tiles, "pixels": total, "autotune": tuned["options"], "graph_ms": round(ms_graph, 3),
+           "graph_Mpx_s": round(total / ms_graph / 1e3, 1)}
+    if not loop:
+        return res
     ws1 = S.workspace(S.workspace_size(S.OP_ESTIMATE_BASIS, 0, 1, 4096), dev)
     wsn1 = S.workspace(S.workspace_size(S.OP_NORMALIZE, 0, 1, 0), dev)
     w1 = torch.empty((n_tiles, 6), dtype=torch.float32, device=dev)
 
-    def loop():
+    def per_tile():
         for t in range(n_tiles):
             S.spcn_estimate_basis(srcs[t], 4096, seed=30000 + t, p=p, lambda_nmf=0.1, n_iter=50, want_p99=False,
                                   w_out=w1[t], ws=ws1)
             S.spcn_normalize(srcs[t], w1[t], wt, sc, p, out=outs[t], stats=False, ws=wsn1)
-    ms_loop = timed(loop, max(1, steps // 4), 1, stream)
-    return {"tiles": n_tiles, "pixels": total, "autotune": tuned["options"], "graph_ms": round(ms_graph, 3),
-            "graph_Mpx_s": round(total / ms_graph / 1e3, 1), "per_tile_loop_ms": round(ms_loop, 3),
-            "per_tile_loop_Mpx_s": round(total / ms_loop / 1e3, 1), "speedup": round(ms_loop / ms_graph, 2)}
+    ms_loop = timed(per_tile, max(1, steps // 4), 1, stream)
+    return dict(res, per_tile_loop_ms=round(ms_loop, 3), per_tile_loop_Mpx_s=round(total / ms_loop / 1e3, 1),
+                speedup=round(ms_loop / ms_graph, 2))
 
 
 def bench_fwdbwd(dev, S, synth, steps, warmup, n=64, size=512):
@@ -210,6 +213,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="skip the batched and forward+backward measurements")
+    ap.add_argument("--only", choices=["batched", "fwdbwd"], default=None,
+                    help="run one extension workload alone (the batched graph without the per-tile loop, or the "
+                         "differentiable batch), for profiling; no slide step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg on float32), "
                          "whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM byte counters")
@@ -226,6 +232,14 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        if args.only == "batched":
+            r = bench_batched(dev, S, synth, args.steps, args.warmup, loop=False)
+        else:
+            r = bench_fwdbwd(dev, S, synth, args.steps, args.warmup)
+        log(f"[bench] {args.only} {r}")
+        print(json.dumps(dict(only=args.only, steps=args.steps, warmup=args.warmup, **r)))
+        return 0
     t0 = time.time()
     img, W_src, desc = build_slide(args.workload, dev)
     Hh, Ww = int(img.shape[0]), int(img.shape[1])
