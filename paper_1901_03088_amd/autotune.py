@@ -23,8 +23,8 @@ from . import (OPT_BATCH_CHUNK, OPT_P1_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_P2_VAR
                OP_NORMALIZE_BATCHED)
 
 P1_CANDIDATES = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9)
-P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 1), (3, 1), (3, 2), (3, 4), (3, 6), (3, 8), (4, 1),
-                 (4, 2), (4, 3), (4, 4), (5, 1))
+P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 1), (3, 1), (3, 2), (3, 3), (3, 4), (3, 6), (3, 8),
+                 (4, 1), (4, 2), (4, 3), (4, 4), (5, 1))
 CHUNK_CANDIDATES = (12, 13, 14, 15, 16, 17, 18)
 
 
