@@ -43,17 +43,19 @@ def _median_ms(fn: Callable[[], None], reps: int) -> float:
 
 
 def _sweep(cands: Iterable, apply: Callable, run: Callable[[], None], result: Callable[[], List[torch.Tensor]],
-           reps: int, finalists: int = 3, rounds: int = 3) -> Tuple[object, List[dict]]:
+           reps: int, finalists: int = 3, rounds: int = 3,
+           timer: Callable[[Callable[[], None], int], float] = None) -> Tuple[object, List[dict]]:
     """Times every candidate; a candidate whose results differ from the first one's is rejected
     (raises: variants are required to be identical).  The fastest few are then timed again in
     interleaved rounds and the lowest median over those rounds wins, so that a single noisy
     measurement (the first candidate timed while the device warms up, a neighbour's burst) does not
     decide."""
+    timer = timer or _median_ms
     ref = None
     rows = []
     for c in cands:
         apply(c)
-        ms = _median_ms(run, reps)
+        ms = timer(run, reps)
         cur = [r.clone() for r in result()]
         if ref is None:
             ref = cur
@@ -65,7 +67,7 @@ def _sweep(cands: Iterable, apply: Callable, run: Callable[[], None], result: Ca
     for _ in range(rounds):
         for i, c in enumerate(top):
             apply(c)
-            again[i].append(_median_ms(run, reps))
+            again[i].append(timer(run, reps))
     final = {i: sorted(v)[len(v) // 2] for i, v in again.items()}
     best_i = min(final, key=final.get)
     for r in rows:
