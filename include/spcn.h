@@ -141,16 +141,21 @@ spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, cons
 /* Out-of-core spcn_normalize for a slide in host memory (the paper's divide and conquer of WSIs,
  * Sec. 3.2 item 3, here for slides larger than, or arriving outside, device memory).  The slide is
  * processed in chunks of chunk_rows rows: pass 1 copies each chunk to the device and adds it to one
- * exact non-white histogram, pass 2 copies it again, recolours it and copies the result back.
- * Copies run on copy_in / copy_out and overlap the kernels on `compute`; all work is enqueued
- * without host synchronisation and `compute` completes after the last copy.  The result equals
- * spcn_normalize of the whole slide byte for byte.
+ * exact non-white histogram, pass 2 recolours it and copies the result back.  The first R chunks
+ * stay resident in the workspace between the passes (R = spcn_stream_resident_chunks: as many as
+ * the bytes beyond the minimum workspace hold); every other chunk is copied to the device again in
+ * pass 2.  Copies run on copy_in / copy_out and overlap the kernels on `compute`; they start only
+ * after the work queued on `compute` before the call; all work is enqueued without host
+ * synchronisation and `compute` completes after the last copy.  The result equals spcn_normalize
+ * of the whole slide byte for byte.
  *   host_src, host_out  uint8 HWC, 3*height*width bytes of pinned host memory (hipHostMalloc or
  *                       equivalent; pageable memory serialises the copies); they must not overlap
  *   chunk_rows          rows per chunk, at most 2^30 pixels per chunk
  *   st                  optional device statistics (hist is ignored: the histogram lives in ws)
- *   ws                  device workspace of spcn_workspace_size(SPCN_OP_STREAM_NORMALIZE, width,
- *                       chunk_rows, 0) bytes: the histogram and four chunk staging buffers
+ *   ws                  device workspace of at least spcn_workspace_size(SPCN_OP_STREAM_NORMALIZE,
+ *                       width, chunk_rows, 0) bytes (the histogram and four chunk staging buffers);
+ *                       each further 3*chunk_rows*width bytes (rounded up to 256) keep one more chunk
+ *                       resident
  *   compute, copy_in, copy_out  streams; copy_in and copy_out must differ from compute (they may
  *                       be the same stream).  Overlapping calls on one device must be serialised. */
 spcn_status spcn_normalize_streamed(const uint8_t* host_src, uint8_t* host_out, int64_t height,
@@ -159,6 +164,10 @@ spcn_status spcn_normalize_streamed(const uint8_t* host_src, uint8_t* host_out, 
                                     const spcn_params* p, int64_t chunk_rows,
                                     const spcn_norm_stats* st, void* ws, size_t ws_bytes,
                                     hipStream_t compute, hipStream_t copy_in, hipStream_t copy_out);
+
+/* Number of chunks spcn_normalize_streamed keeps resident between its passes with a workspace of
+ * ws_bytes bytes (0 for invalid sizes). */
+int64_t spcn_stream_resident_chunks(int64_t height, int64_t width, int64_t chunk_rows, size_t ws_bytes);
 
 /* Paper-compatible percentiles of Eq. 3 (alternatives to the exact global histogram percentile of
  * spcn_normalize; feed any of them to spcn_recolor_p99).

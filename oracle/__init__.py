@@ -80,6 +80,8 @@ def lib():
         L.orc_backward_f32.restype = C.c_int
         L.orc_backward_f32.argtypes = [_d, C.c_int64, _d, _d, _d, _d, _d, C.c_double, C.c_int, C.c_double,
                                        _d, _i64, _d, _d, _d]
+        L.orc_active_margin_f32.restype = None
+        L.orc_active_margin_f32.argtypes = [_d, C.c_int64, _d, _d, C.c_double, _d]
         _LIB = L
     return _LIB
 
@@ -347,3 +349,12 @@ def backward_f32(x, W_src, W_tgt, scale_tgt, grad_y, i0_in=(1, 1, 1), i0_out=(1,
                                 q_of(percentile), _p(g, _d), None if ist is None else _p(ist, _i64),
                                 _p(gx, _d), _p(gW, _d), _p(gs, _d))
     return gx.reshape(x.shape), gW, gs, fl
+
+
+def active_margin_f32(x, W_src, i0_in=(1, 1, 1), lam=0.01):
+    """Per pixel (flat, n), the distance from an active-set change of Eq. (2): pixels with a tiny
+    margin may be solved on another face in FP32 than in FP64."""
+    x = np.ascontiguousarray(x, dtype=np.float64); n = x.shape[1] * x.shape[2]
+    m = np.empty(n)
+    lib().orc_active_margin_f32(_p(x, _d), n, _p(basis(W_src), _d), _p(_vec(i0_in, 3), _d), float(lam), _p(m, _d))
+    return m

@@ -501,6 +501,38 @@ int orc_forward_f32(const double* x, int64_t n_px, const double W_src[6], const 
     return flags;
 }
 
+/* Distance of each pixel of a float image from a change of its active set in Eq. (2) (W fixed):
+ * the smallest magnitude among the quantities whose signs pick the face of the quadrant that holds
+ * the minimiser -- the one-stain minimisers b_j / g_jj and, when G is regular, the two entries of
+ * G^-1 b.  A pixel whose margin is tiny may be solved on another face in FP32 than in FP64.  (The
+ * OD clamps of Eq. (1) and the non-white mask are decided on the same FP32 input on both sides and
+ * are not counted.) */
+void orc_active_margin_f32(const double* x, int64_t n_px, const double W[6], const double i0_in[3],
+                           double lambda, double* margin) {
+    double g00 = 0, g01 = 0, g11 = 0;
+    for (int c = 0; c < 3; ++c) {
+        g00 += W[c] * W[c]; g01 += W[c] * W[c + 3]; g11 += W[c + 3] * W[c + 3];
+    }
+    double det = g00 * g11 - g01 * g01;
+    for (int64_t i = 0; i < n_px; ++i) {
+        double v[3], b0 = 0.0, b1 = 0.0, m = INFINITY;
+        for (int c = 0; c < 3; ++c) {
+            v[c] = orc_od_f(i0_in[c], x[c * n_px + i]);
+            b0 += W[c] * v[c];
+            b1 += W[c + 3] * v[c];
+        }
+        b0 -= 0.5 * lambda;
+        b1 -= 0.5 * lambda;
+        if (g00 > 0.0) m = fmin(m, fabs(b0 / g00));
+        if (g11 > 0.0) m = fmin(m, fabs(b1 / g11));
+        if (det > 0.0) {
+            m = fmin(m, fabs((g11 * b0 - g01 * b1) / det));
+            m = fmin(m, fabs((g00 * b1 - g01 * b0) / det));
+        }
+        margin[i] = m;
+    }
+}
+
 /* Adjoint, derived by hand from the forward definitions above:
  *   y_c = i0_out,c exp(-u_c),  u_c = sum_j Wt[c,j] s_j h_j,  s_j = S_j / P_j,  P_j = h_j(pixel i*_j).
  *   ubar_c = -y_c gbar_c;  dWt[c,j] = sum_i ubar_ic s_j h_ij;  ds_j = sum_i sum_c ubar_ic Wt[c,j] h_ij;

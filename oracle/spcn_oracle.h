@@ -155,6 +155,11 @@ int orc_forward_f32(const double* x, int64_t n_px, const double W_src[6], const 
                     double lambda, int white_sum, double q, double* y, double* P, int64_t* istar,
                     double* H_out);
 
+/* Per pixel of a float image (CHW), the distance from a change of the Eq. (2) active set:
+ * min over |b_j / g_jj| and |(G^-1 b)_j| (if G is regular), b = W^T v - lambda/2. */
+void orc_active_margin_f32(const double* x, int64_t n_px, const double W[6], const double i0_in[3],
+                           double lambda, double* margin);
+
 /* Analytic adjoint of orc_forward_f32 w.r.t. x, W_tgt and scale_tgt (W_src held fixed; the mask
  * and the rank selection are piecewise constant).  If istar_in is non-NULL it fixes the selected
  * pixels (else they are recomputed).  grad_x is CHW like x. */

@@ -68,6 +68,7 @@ _SIGS = {
     "spcn_recolor_p99": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _vp]),
     "spcn_normalize_streamed": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _i64, _vp, _vp, _sz, _vp,
                                           _vp, _vp]),
+    "spcn_stream_resident_chunks": (_i64, [_i64, _i64, _i64, _sz]),
     "spcn_normalize_batched": (C.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_f32": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -371,6 +372,11 @@ def spcn_normalize_streamed(host_src: torch.Tensor, w_src: torch.Tensor, w_tgt: 
                                       C.byref(st), wsp, wsn, _stream(), C.c_void_p(copy_in.cuda_stream),
                                       C.c_void_p(copy_out.cuda_stream)), "spcn_normalize_streamed")
     return host_out, res
+
+
+def stream_resident_chunks(height: int, width: int, chunk_rows: int, ws_bytes: int) -> int:
+    """Chunks spcn_normalize_streamed keeps on the device between its passes with ws_bytes of workspace."""
+    return int(_L.spcn_stream_resident_chunks(height, width, chunk_rows, ws_bytes))
 
 
 def tile_table(srcs, outs=None) -> torch.Tensor:

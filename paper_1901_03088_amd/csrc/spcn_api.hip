@@ -382,11 +382,16 @@ spcn_status spcn_normalize_streamed(const uint8_t* host_src, uint8_t* host_out, 
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_stream_normalize(host_src, host_out, height, width, w_src, w_tgt, scale_tgt, io,
-                                           make_params(p), chunk_rows, ws, st ? st->p99_src : nullptr,
+                                           make_params(p), chunk_rows, ws, ws_bytes, st ? st->p99_src : nullptr,
                                            st ? st->scale : nullptr, st ? st->flags : nullptr, dev, compute, copy_in,
                                            copy_out);
     if (e != hipSuccess) return hip_fail(e, "spcn_normalize_streamed");
     return SPCN_OK;
+}
+
+int64_t spcn_stream_resident_chunks(int64_t height, int64_t width, int64_t chunk_rows, size_t ws_bytes) {
+    if (height <= 0 || width <= 0 || chunk_rows < 1 || chunk_rows > ((int64_t)1 << 30) / width) return 0;
+    return stream_resident_chunks(height, width, chunk_rows, ws_bytes);
 }
 
 spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t max_tile_px,

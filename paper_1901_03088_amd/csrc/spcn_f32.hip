@@ -80,7 +80,9 @@ __device__ __forceinline__ void solve_px(const F32Basis& F, float x0, float x1, 
         const float xc = fmaxf(xs[c], lo);
         const float v = (F.log2i0[c] - __builtin_amdgcn_logf(xc)) * 0.69314718055994531f;
         p.od[c] = fmaxf(v, 0.0f);
-        p.live[c] = xs[c] > lo && xs[c] < F.i0[c];
+        // the clamp's kink is at the real 1/255, which lies just below its FP32 rounding lo: every
+        // x >= lo is above the kink and has the derivative -1/x
+        p.live[c] = xs[c] >= lo && xs[c] < F.i0[c];
     }
     float f0 = F.fc[0], f1 = F.fc[1];
     for (int c = 0; c < 3; ++c) { f0 = fmaf(F.q[0][c], p.od[c], f0); f1 = fmaf(F.q[1][c], p.od[c], f1); }
@@ -474,7 +476,7 @@ __device__ __forceinline__ void pixel_vjp(const F32Basis& F, const Px& p, float 
     const float xs[3] = {x0, x1, x2};
     for (int c = 0; c < 3; ++c) {
         const float vbar = F.w[c] * z0 + F.w[c + 3] * z1;
-        g[c] = p.live[c] ? -vbar * __builtin_amdgcn_rcpf(xs[c]) : 0.0f;   // live: x_c > 1/255
+        g[c] = p.live[c] ? -vbar * __builtin_amdgcn_rcpf(xs[c]) : 0.0f;   // live: x_c above the real 1/255
     }
 }
 

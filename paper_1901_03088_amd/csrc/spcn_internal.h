@@ -79,10 +79,11 @@ size_t exact_workspace_bytes();
 hipError_t launch_exact_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
                                    float* p99_out, int32_t* flags_out, void* ws, const DevInfo& dev, hipStream_t s);
 size_t stream_workspace_bytes(int64_t width, int64_t chunk_rows);
+int64_t stream_resident_chunks(int64_t height, int64_t width, int64_t chunk_rows, size_t ws_bytes);
 hipError_t launch_stream_normalize(const uint8_t* host_src, uint8_t* host_out, int64_t height, int64_t width,
                                    const float* w_src, const float* w_tgt, const float* scale_tgt,
                                    const float i0_out[3], const ParamsK& pk, int64_t chunk_rows, void* ws,
-                                   float* p99_out, float* scale_out, int32_t* flags_out, const DevInfo& dev,
+                                   size_t ws_bytes, float* p99_out, float* scale_out, int32_t* flags_out, const DevInfo& dev,
                                    hipStream_t compute, hipStream_t copy_in, hipStream_t copy_out);
 size_t sample_pctl_workspace_bytes(int64_t n_samples);
 hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, int64_t n_s,

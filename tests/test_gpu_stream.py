@@ -1,7 +1,8 @@
 """GPU tests of the out-of-core normalisation of a slide in pinned host memory: the streamed result
 equals spcn_normalize of the same image on the device byte for byte (one exact histogram over all
-chunks), for several chunk sizes including single rows, ragged last chunks and one chunk; and it
-matches the FP64 oracle at the uint8 bar."""
+chunks), for several chunk sizes including single rows, ragged last chunks and one chunk, with
+none, some or all chunks kept resident between the passes; it matches the FP64 oracle at the uint8
+bar; and the copies wait for work still queued on the compute stream."""
 import numpy as np
 import pytest
 import torch
@@ -55,3 +56,39 @@ def test_streamed_repeat_and_separate_copy_streams(S):
         out, _ = S.spcn_normalize_streamed(host, ws, wt, sc, p, chunk_rows=rows, copy_in=cin, copy_out=cout)
         torch.cuda.synchronize()
         assert torch.equal(out, ref.cpu())
+
+
+@pytest.mark.parametrize("resident", [1, 3, 100])
+def test_streamed_resident_chunks(S, resident):
+    """A larger workspace keeps the first chunks on the device between the passes (recoloured in
+    place): same bytes as the in-HBM path, whatever the number kept (all of them included)."""
+    h, w, rows = 777, 501, 64
+    src, tgt, p, ws, wt, sc = setup(S, 5, h, w)
+    ref, st = S.spcn_normalize(src["img"], ws, wt, sc, p)
+    host = src["img"].cpu().pin_memory()
+    base = S.workspace_size(S.OP_STREAM_NORMALIZE, w, rows, 0)
+    chunk = (3 * rows * w + 255) // 256 * 256
+    n_chunks = (h + rows - 1) // rows
+    wsb = S.workspace(base + resident * chunk, DEV)
+    assert S.stream_resident_chunks(h, w, rows, base + resident * chunk) == min(resident, n_chunks)
+    out, rst = S.spcn_normalize_streamed(host, ws, wt, sc, p, chunk_rows=rows, ws=wsb)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref.cpu())
+    assert torch.equal(rst["p99_src"], st["p99_src"]) and torch.equal(rst["scale"], st["scale"])
+
+
+def test_streamed_waits_for_queued_compute_work(S):
+    """The host input is written by a copy still queued on the compute stream when the streamed call
+    is made (no synchronisation in between): the call's copies must wait for it."""
+    src, tgt, p, ws, wt, sc = setup(S, 6, 640, 480)
+    ref, _ = S.spcn_normalize(src["img"], ws, wt, sc, p)
+    torch.cuda.synchronize()
+    host = torch.zeros((640, 480, 3), dtype=torch.uint8).pin_memory()
+    busy = torch.empty((4096, 4096), device=DEV)
+    busy.normal_()
+    for _ in range(20):          # keep the compute stream busy for a while
+        busy = busy @ busy.T * 1e-3
+    host.copy_(src["img"], non_blocking=True)   # device -> pinned host, queued behind the products
+    out, _ = S.spcn_normalize_streamed(host, ws, wt, sc, p, chunk_rows=100)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref.cpu())

@@ -62,6 +62,30 @@ def synth_od(W, n, seed, minor=0.15, noise=0.0, pure=False):
     return np.clip(V, 0, None)
 
 
+def test_nmf_objective_pins(orc):
+    """The Eq. (2) objective ||V - W H||_F^2 + lambda sum(H) that the monotonicity pin below rests
+    on, against values the definition fixes: a hand-computed integer case, H = 0, an exact
+    factorisation V = W H (only the penalty remains), the slope in lambda, and a numpy evaluation
+    of the same definition on random data."""
+    # V columns (1,2,3) and (0,1,2); W = unit R and G axes; H columns (1,1) and (0,1):
+    # residuals (0,1,3) and (0,0,2) -> 1 + 9 + 4 = 14, plus lambda * 3
+    V = np.array([[1.0, 0.0], [2.0, 1.0], [3.0, 2.0]])
+    W = np.array([[1.0, 0.0], [0.0, 1.0], [0.0, 0.0]])
+    H = np.array([[1.0, 0.0], [1.0, 1.0]])
+    assert orc.nmf_objective(V, H, W, 0.5) == 15.5
+    assert orc.nmf_objective(V, H, W, 0.0) == 14.0
+    rng = np.random.default_rng(60)
+    Wr = synth.jitter_basis(rng, 5)
+    Hr = rng.uniform(0, 2, (2, 500))
+    Vr = rng.uniform(0, 3, (3, 500))
+    assert np.isclose(orc.nmf_objective(Vr, np.zeros((2, 500)), Wr, 0.3), (Vr ** 2).sum(), rtol=1e-13)
+    Vx = Wr @ Hr
+    assert np.isclose(orc.nmf_objective(Vx, Hr, Wr, 0.1), 0.1 * Hr.sum(), rtol=1e-12)
+    f1, f2 = orc.nmf_objective(Vr, Hr, Wr, 0.1), orc.nmf_objective(Vr, Hr, Wr, 0.7)
+    assert np.isclose(f2 - f1, 0.6 * Hr.sum(), rtol=1e-10)
+    assert np.isclose(f1, ((Vr - Wr @ Hr) ** 2).sum() + 0.1 * Hr.sum(), rtol=1e-13)
+
+
 def test_nmf_objective_monotone(orc):
     W = synth.jitter_basis(np.random.default_rng(40), 5)
     V = synth_od(W, 4000, 41, noise=0.03)
@@ -122,57 +146,76 @@ def test_estimate_basis_on_image(orc):
 
 # ------------------------------------------------------------------ adjoint of the float path
 
-def _loss(orc, x, Ws, Wt, S, wts, lam, white_sum=660):
-    y, P, ist, H, fl = orc.forward_f32(x, Ws, Wt, S, lam=lam, white_sum=white_sum)
-    return float((wts * y).sum()), y, P, ist, H
+def _fwd(orc, x, Ws, Wt, S, lam, white_sum=660):
+    return orc.forward_f32(x, Ws, Wt, S, lam=lam, white_sum=white_sum)
+
+
+def _dloss(wts, yp, ym):
+    """L(+) - L(-) for L = sum(w * y^2), summed from per-element differences (exact where an
+    element does not change), so that the difference quotient is not lost in the rounding of two
+    large sums."""
+    return float((wts * (yp - ym) * (yp + ym)).sum())
+
+
+def _crop32(seed):
+    """A 32 x 32 crop of the float workload's generator (the benchmark's 512 x 512 images are made
+    of the same field), as FP32 values in [0, 1] widened to float64."""
+    d = synth.make_image(seed, 96, 96)
+    x = d["img"][40:72, 24:56].numpy().transpose(2, 0, 1).astype(np.float32) / np.float32(255.0)
+    return np.ascontiguousarray(x.astype(np.float64)), d["W"]
 
 
 @pytest.mark.parametrize("lam", [0.0, 0.01])
 def test_backward_matches_finite_differences(orc, lam):
-    """FP64 central differences of the oracle's own forward, eps = 1e-6, at pixels away from
-    active-set switches and rank swaps; L = sum(w * y)."""
-    d = synth.make_image(50, 16, 16)
-    x = d["img"].numpy().transpose(2, 0, 1).astype(np.float32).astype(np.float64) / 255.0
-    x = np.ascontiguousarray(x)
-    Ws = d["W"]
+    """FP64 central differences of the oracle's own forward, eps = 1e-6, on a 32 x 32 crop, at
+    pixels away from active-set switches and rank swaps; L = sum(w * y^2), so dL/dy = 2 w y."""
+    x, Ws = _crop32(50)
     Wt = synth.target_bases(1, 51, 10.0)[0]
     S = np.array([0.9, 1.1])
     wts = np.random.default_rng(52).uniform(0, 1, x.shape)
-    L0, y, P, ist, H = _loss(orc, x, Ws, Wt, S, wts, lam)
-    gy = wts * 1.0
-    gx, gW, gs, fl = orc.backward_f32(x, Ws, Wt, S, gy, lam=lam)
+    y, P, ist, H, fl = _fwd(orc, x, Ws, Wt, S, lam)
+    gx, gW, gs, fl = orc.backward_f32(x, Ws, Wt, S, 2.0 * wts * y, lam=lam)
     eps = 1e-6
     n = x.shape[1] * x.shape[2]
-    # sorted densities: keep pixels whose value is not within 1e-4 of a rank neighbour
+    margin = orc.active_margin_f32(x, Ws, lam=lam)
     checked = 0
-    for i in list(range(0, n, 7)) + list(ist):
-        a0 = H[:, i]
-        if np.any((a0 > 0) & (a0 < 1e-4)):
-            continue
+    for i in list(range(0, n, 5)) + list(ist):
+        if margin[i] < 1e-4:
+            continue           # an active-set switch within reach of the perturbation
         for c in range(3):
             xc = x.reshape(3, -1)[c, i]
             if xc >= 1.0 - 1e-4 or xc <= 1.0 / 255 + 1e-4:
                 continue       # the OD clamp's kinks (x = 1 and x = 1/255): one-sided derivatives
             xp = x.copy(); xm = x.copy()
             xp.reshape(3, -1)[c, i] += eps; xm.reshape(3, -1)[c, i] -= eps
-            Lp = _loss(orc, xp, Ws, Wt, S, wts, lam)
-            Lm = _loss(orc, xm, Ws, Wt, S, wts, lam)
-            if not (np.array_equal(Lp[3], ist) and np.array_equal(Lm[3], ist)):
+            rp, rm = _fwd(orc, xp, Ws, Wt, S, lam), _fwd(orc, xm, Ws, Wt, S, lam)
+            if not (np.array_equal(rp[2], ist) and np.array_equal(rm[2], ist)):
                 continue       # the selected order statistic changed pixel: not differentiable here
-            fd = (Lp[0] - Lm[0]) / (2 * eps)
+            fd = _dloss(wts, rp[0], rm[0]) / (2 * eps)
             an = gx.reshape(3, -1)[c, i]
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (i, c, fd, an)
             checked += 1
-    assert checked > 40
+    assert checked > 300
+    # the selected pixels themselves carry the order-statistic term
+    for j in range(2):
+        k = int(ist[j])
+        if margin[k] >= 1e-4:
+            for c in range(3):
+                xp = x.copy(); xm = x.copy()
+                xp.reshape(3, -1)[c, k] += eps; xm.reshape(3, -1)[c, k] -= eps
+                rp, rm = _fwd(orc, xp, Ws, Wt, S, lam), _fwd(orc, xm, Ws, Wt, S, lam)
+                if np.array_equal(rp[2], ist) and np.array_equal(rm[2], ist):
+                    fd = _dloss(wts, rp[0], rm[0]) / (2 * eps)
+                    assert abs(fd - gx.reshape(3, -1)[c, k]) <= 1e-6 * max(1.0, abs(fd)), (j, c)
     Wb = orc.basis(Wt)
     for k in range(6):
         Wp = Wb.copy(); Wm = Wb.copy(); Wp[k] += eps; Wm[k] -= eps
-        fd = (_loss(orc, x, Ws, Wp, S, wts, lam)[0] - _loss(orc, x, Ws, Wm, S, wts, lam)[0]) / (2 * eps)
-        assert abs(fd - gW[k]) <= 1e-6 * max(1.0, abs(gW[k]))
+        fd = _dloss(wts, _fwd(orc, x, Ws, Wp, S, lam)[0], _fwd(orc, x, Ws, Wm, S, lam)[0]) / (2 * eps)
+        assert abs(fd - gW[k]) <= 1e-6 * max(1.0, abs(gW[k])), (k, fd, gW[k])
     for j in range(2):
         Sp = S.copy(); Sm = S.copy(); Sp[j] += eps; Sm[j] -= eps
-        fd = (_loss(orc, x, Ws, Wt, Sp, wts, lam)[0] - _loss(orc, x, Ws, Wt, Sm, wts, lam)[0]) / (2 * eps)
-        assert abs(fd - gs[j]) <= 1e-6 * max(1.0, abs(gs[j]))
+        fd = _dloss(wts, _fwd(orc, x, Ws, Wt, Sp, lam)[0], _fwd(orc, x, Ws, Wt, Sm, lam)[0]) / (2 * eps)
+        assert abs(fd - gs[j]) <= 1e-6 * max(1.0, abs(gs[j])), (j, fd, gs[j])
 
 
 def test_backward_selected_pixel_carries_percentile_term(orc):
