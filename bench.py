@@ -3,7 +3,9 @@
 ~60% background, normalised to one target.
 
 One step = the whole path for the slide: basis estimation from 200k sampled tissue pixels (sparse
-NMF, 50 rounds) + pass 1 (densities + exact histogram) + pass 2 (percentile, recolour, uint8 write).
+NMF, 50 rounds, the samples' percentile and the histogram range derived from it) + pass 1 (densities
++ exact histogram, with the device-side range check and its gated repeat) + pass 2 (percentile,
+recolour, uint8 write).  The flags of the timed step are checked: no overflow, timeout or skip.
 Inputs are resident in HBM before the timed region.  Extras (same JSON line): the batched workload
 (512 tiles in one graph) against a per-tile loop, and forward+backward of the float path against
 forward only.  Prints ONE JSON line.
@@ -136,14 +138,17 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True):
     _, _, sc, _ = S.spcn_densities(tgt["img"], wt, p, want_h=False)
     ws_b = S.workspace(S.workspace_size(S.OP_ESTIMATE_BATCHED, 0, n_tiles, 4096), dev)
     ws_n = S.workspace(S.workspace_size(S.OP_NORMALIZE_BATCHED, total, n_tiles), dev)
+    hh_t = torch.empty((n_tiles, 2), dtype=torch.float32, device=dev)   # per-tile ranges from the fits
+    p_t = S.params(hist_hi_dev=hh_t)
 
     def run():
-        W, _, _ = S.spcn_estimate_basis_batched(table, n_tiles, 4096, seed=30000, p=p, want_p99=False, ws=ws_b)
-        S.spcn_normalize_batched(table, n_tiles, total, W, wt, sc, p, ws=ws_n, stats=False)
+        W, _, _ = S.spcn_estimate_basis_batched(table, n_tiles, 4096, seed=30000, p=p, want_p99=False, ws=ws_b,
+                                                hist_hi_out=hh_t)
+        S.spcn_normalize_batched(table, n_tiles, total, W, wt, sc, p_t, ws=ws_n, stats=False)
         return W
     from paper_1901_03088_amd import autotune
     W_fit = run()
-    tuned = autotune.tune_batched(table, n_tiles, total, W_fit, wt, sc, outs, p)
+    tuned = autotune.tune_batched(table, n_tiles, total, W_fit, wt, sc, outs, p_t)
     run()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -160,23 +165,42 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True):
            "graph_Mpx_s": round(total / ms_graph / 1e3, 1)}
     if not loop:
         return res
+    # the same work tile by tile through the single-image entry points (same fits, same ranges, no
+    # automatic retry, so the same bytes), eagerly and captured into one graph
     ws1 = S.workspace(S.workspace_size(S.OP_ESTIMATE_BASIS, 0, 1, 4096), dev)
-    wsn1 = S.workspace(S.workspace_size(S.OP_NORMALIZE, 0, 1, 0), dev)
+    wsn1 = S.workspace(S.workspace_size(S.OP_NORMALIZE), dev)
     w1 = torch.empty((n_tiles, 6), dtype=torch.float32, device=dev)
+    hh1 = torch.empty((n_tiles, 2), dtype=torch.float32, device=dev)
+    p1 = [S.params(hist_hi_dev=hh1[t], auto_range=False) for t in range(n_tiles)]
 
     def per_tile():
         for t in range(n_tiles):
             S.spcn_estimate_basis(srcs[t], 4096, seed=30000 + t, p=p, lambda_nmf=0.1, n_iter=50, want_p99=False,
-                                  w_out=w1[t], ws=ws1)
-            S.spcn_normalize(srcs[t], w1[t], wt, sc, p, out=outs[t], stats=False, ws=wsn1)
+                                  w_out=w1[t], ws=ws1, hist_hi_out=hh1[t])
+            S.spcn_normalize(srcs[t], w1[t], wt, sc, p1[t], out=outs[t], stats=False, ws=wsn1)
     ms_loop = timed(per_tile, max(1, steps // 4), 1, stream)
+    per_tile()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        per_tile()
+    torch.cuda.current_stream().wait_stream(side)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        per_tile()
+    ms_loop_graph = timed(g2.replay, max(2, steps // 2), 1, stream)
+    del g2
     return dict(res, per_tile_loop_ms=round(ms_loop, 3), per_tile_loop_Mpx_s=round(total / ms_loop / 1e3, 1),
-                speedup=round(ms_loop / ms_graph, 2))
+                per_tile_graph_ms=round(ms_loop_graph, 3),
+                per_tile_graph_Mpx_s=round(total / ms_loop_graph / 1e3, 1),
+                speedup_vs_eager_loop=round(ms_loop / ms_graph, 2),
+                speedup_vs_graph_loop=round(ms_loop_graph / ms_graph, 2))
 
 
 def bench_fwdbwd(dev, S, synth, steps, warmup, n=64, size=512):
     """Differentiable path: 64 x 3 x 512 x 512 float images, per-sample target bases, forward +
-    backward of L = sum(w * y), against forward only."""
+    backward of L = sum(w * y^2) (fixed random weights w, so dL/dy = 2 w y, one elementwise product
+    timed with the step), against forward only."""
     import torch
     x, Ws, Wt, wts = synth.float_batch(n, size, device=dev)
     p = S.float_params()
@@ -186,6 +210,8 @@ def bench_fwdbwd(dev, S, synth, steps, warmup, n=64, size=512):
     fws = S.workspace(S.workspace_size(S.OP_FORWARD_F32, size * size, n), dev)
     bws = S.workspace(S.workspace_size(S.OP_BACKWARD_F32, size * size, n), dev)
     y = torch.empty_like(x)
+    gy = torch.empty_like(x)
+    w2 = 2.0 * wts
     stream = torch.cuda.current_stream()
     state = {}
 
@@ -194,12 +220,15 @@ def bench_fwdbwd(dev, S, synth, steps, warmup, n=64, size=512):
 
     def fwd_bwd():
         fwd()
-        S.spcn_normalize_backward(x, ws, wt, sc, state["saved"], wts, p, ws=bws)
+        torch.mul(w2, y, out=gy)                    # dL/dy of L = sum(w * y^2)
+        S.spcn_normalize_backward(x, ws, wt, sc, state["saved"], gy, p, ws=bws)
     ms_f = timed(fwd, steps, warmup, stream)
     ms_fb = timed(fwd_bwd, steps, warmup, stream)
+    ms_loss = timed(lambda: torch.mul(w2, y, out=gy), steps, warmup, stream)
     px = n * size * size
-    return {"batch": [n, 3, size, size], "forward_ms": round(ms_f, 3), "forward_Mpx_s": round(px / ms_f / 1e3, 1),
-            "fwd_bwd_ms": round(ms_fb, 3), "fwd_bwd_Mpx_s": round(px / ms_fb / 1e3, 1),
+    return {"batch": [n, 3, size, size], "loss": "sum(w * y^2)", "forward_ms": round(ms_f, 3),
+            "forward_Mpx_s": round(px / ms_f / 1e3, 1), "fwd_bwd_ms": round(ms_fb, 3),
+            "fwd_bwd_Mpx_s": round(px / ms_fb / 1e3, 1), "loss_grad_ms": round(ms_loss, 3),
             "forward_bytes_per_px": 48, "backward_bytes_per_px": 36}
 
 
@@ -253,30 +282,41 @@ def main() -> int:
     out = torch.empty_like(img)
     hist = torch.empty((2, 256), dtype=torch.uint64, device=dev)
     w_fit = torch.empty(6, dtype=torch.float32, device=dev)
+    hh_fit = torch.empty(2, dtype=torch.float32, device=dev)     # range from the basis sample
+    hh_used = torch.empty(2, dtype=torch.float32, device=dev)    # range the histogram was built over
+    p_fit = S.params(hist_hi_dev=hh_fit)
+    p_used = S.params(hist_hi_dev=hh_used)
     n_samples = 200000
     ws_fit = S.workspace(S.workspace_size(S.OP_ESTIMATE_BASIS, n_px, 1, n_samples), dev)
+    ws_d = S.workspace(S.workspace_size(S.OP_DENSITIES), dev)
+    st = {"p99_src": torch.empty(2, dtype=torch.float32, device=dev),
+          "scale": torch.empty(2, dtype=torch.float32, device=dev),
+          "flags": torch.empty(2, dtype=torch.int32, device=dev),
+          "hist_hi": torch.empty(2, dtype=torch.float32, device=dev)}
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
     from paper_1901_03088_amd import autotune
     # tune on the basis the step fits (the bin distribution, hence LDS contention, depends on it)
     S.spcn_estimate_basis(img, n_samples, seed=2024, p=S.params(), lambda_nmf=0.1, n_iter=50, want_p99=False,
-                          w_out=w_fit, ws=ws_fit)
-    tuned = autotune.tune_image(img, w_fit, w_tgt, scale_tgt, p)
+                          w_out=w_fit, ws=ws_fit, hist_hi_out=hh_fit)
+    tuned = autotune.tune_image(img, w_fit, w_tgt, scale_tgt, p_fit)
     log(f"[bench] autotune chose {tuned['options']}")
 
     def step(ev=None):
-        # one step = the whole path for the slide: basis fit (200k samples) -> pass 1 -> pass 2
+        # one step = the whole path for the slide: basis fit (200k samples, sample percentile and
+        # range) -> pass 1 (range check, gated repeat) -> pass 2
         if ev is not None:
             ev[0].record(stream)
         S.spcn_estimate_basis(img, n_samples, seed=2024, p=S.params(), lambda_nmf=0.1, n_iter=50, want_p99=False,
-                              w_out=w_fit, ws=ws_fit)
+                              w_out=w_fit, ws=ws_fit, hist_hi_out=hh_fit)
         if ev is not None:
             ev[1].record(stream)
-        S.spcn_densities(img, w_fit, p, want_h=False, hist_out=hist, finalize=False)
+        S.spcn_densities(img, w_fit, p_fit, want_h=False, hist_out=hist, finalize=False, hist_hi_out=hh_used,
+                         ws=ws_d)
         if ev is not None:
             ev[2].record(stream)
-        S.spcn_recolor(img, w_fit, w_tgt, scale_tgt, hist, p, out=out, stats=False)
+        S.spcn_recolor(img, w_fit, w_tgt, scale_tgt, hist, p_used, out=out, stats=st)
         if ev is not None:
             ev[3].record(stream)
 
@@ -299,6 +339,11 @@ def main() -> int:
     pbm, p1m, p2m = float(np.mean(pb)), float(np.mean(p1)), float(np.mean(p2))
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}), "
         f"basis {pbm:.3f} ms, pass1 {p1m:.3f} ms, pass2 {p2m:.3f} ms")
+    step_flags = [int(v) for v in st["flags"].cpu()]
+    bad = S.FLAG_RANGE | S.FLAG_TIMEOUT | S.FLAG_BATCH | S.FLAG_NO_TISSUE | S.FLAG_BASIS
+    if any(f & bad for f in step_flags):
+        log(f"[bench] the timed step raised flags {step_flags}")
+        return 3
 
     # roofline of the dominant kernel (algorithmic bytes: 3 B/px read in pass 1; 3 read + 3 written in pass 2)
     k1 = P1_KERNELS[S.get_option(S.OPT_P1_VARIANT)]
@@ -317,7 +362,9 @@ def main() -> int:
                      "traffic": measured_traffic(k_name, desc["workload"]),
                      "algorithmic_bytes": round(k_bytes)},
         "autotune": tuned["options"],
-        "path": {"basis_fit_ms": round(pbm, 4), "pass1_ms": round(p1m, 4), "pass2_ms": round(p2m, 4),
+        "path": {"flags": step_flags, "hist_hi": [float(v) for v in st["hist_hi"].cpu()],
+                 "p99_src": [float(v) for v in st["p99_src"].cpu()],
+                 "basis_fit_ms": round(pbm, 4), "pass1_ms": round(p1m, 4), "pass2_ms": round(p2m, 4),
                  "normalize_ms": round(norm_ms, 4), "normalize_Mpx_s": round(n_px / norm_ms / 1e3, 1),
                  "normalize_GBs_9B_per_px": round(path_gbs, 1),
                  "normalize_frac_of_peak": round(path_gbs / HBM_PEAK_GBS, 4)},

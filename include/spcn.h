@@ -50,7 +50,8 @@ typedef enum {
 
 /* Device-side result flags, one int32 word per stain (bit OR). */
 #define SPCN_FLAG_NO_TISSUE 1   /* no pixel passed the non-white mask: scale kept at 1            */
-#define SPCN_FLAG_RANGE     2   /* percentile fell in the last histogram bin: raise hist_hi       */
+#define SPCN_FLAG_RANGE     2   /* percentile fell in the last histogram bin (after the automatic
+                                   retry, if any): raise hist_hi                                   */
 #define SPCN_FLAG_BIN0      4   /* percentile fell in bin 0 (stain absent): scale kept at 1       */
 #define SPCN_FLAG_BASIS     8   /* the basis has a singular Gram matrix: densities set to 0       */
 #define SPCN_FLAG_SHORT    16   /* basis estimation drew fewer tissue samples than requested      */
@@ -59,6 +60,8 @@ typedef enum {
 #define SPCN_FLAG_TIMEOUT  64   /* a bounded device-side wait between workgroups expired: the
                                    results of this call are invalid                                 */
 #define SPCN_FLAG_NO_BACKGROUND 128 /* spcn_estimate_i0 found no background pixel: i0 set to 255    */
+#define SPCN_FLAG_RANGE_RETRY 256   /* the percentile fell in the last bin at the range given; the
+                                       histogram was rebuilt at twice this stain's range (auto_range) */
 
 #define SPCN_HIST_BINS 256
 
@@ -70,15 +73,24 @@ typedef struct {
     float percentile;   /* Eq. (3) percentile, in (0, 100]                                         */
     float hist_hi[2];   /* per-stain density histogram range [0, hist_hi): power of two in
                            [2^-8, 2^8]; 256 bins; values beyond land in the last bin               */
+    const float* hist_hi_dev; /* device range that replaces hist_hi when non-NULL: [2] per image
+                           ([n_tiles][2] for spcn_normalize_batched), e.g. the hist_hi_out of basis
+                           estimation.  A value is rounded up to a power of two and clamped to
+                           [2^-8, 2^8]; one that is not finite and positive falls back to hist_hi.
+                           The histogram range is not part of the paper (Eq. 3 takes an order
+                           statistic); it only places the bins.                                    */
+    int32_t auto_range; /* 1: when a stain's percentile falls in the last bin, spcn_densities and
+                           spcn_normalize rebuild the histogram once at twice that stain's range,
+                           on the device (SPCN_FLAG_RANGE_RETRY); 0: only SPCN_FLAG_RANGE is set   */
 } spcn_params;
 
 /* Fills the paper's defaults: i0 = 255, lambda = 0.01, white_sum = 660 (mean intensity 220),
- * percentile 99, hist_hi = 4. */
+ * percentile 99, hist_hi = 4, no device range, auto_range = 1. */
 void spcn_default_params(spcn_params* p);
 
 /* Operation codes for spcn_workspace_size. */
-#define SPCN_OP_DENSITIES         0
-#define SPCN_OP_NORMALIZE         1
+#define SPCN_OP_DENSITIES         0   /* no size arguments */
+#define SPCN_OP_NORMALIZE         1   /* no size arguments */
 #define SPCN_OP_ESTIMATE_BASIS    2
 #define SPCN_OP_NORMALIZE_BATCHED 3
 #define SPCN_OP_ESTIMATE_BATCHED  4
@@ -99,14 +111,17 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
  * percentile (Eq. 3 numerator when applied to a target image).
  *   img       uint8 HWC, height*width pixels
  *   w         [6] basis
- *   h_out     [2][n_px] FP32 densities, or NULL (histogram only)
+ *   h_out     [2][n_px] FP32 densities, 16-byte aligned, or NULL (histogram only)
  *   hist_out  [2][256] uint64 counts over non-white pixels (overwritten)
  *   p99_out   [2] histogram percentile per stain (interpolated in the crossing bin), or NULL
  *   flags_out [2] SPCN_FLAG_* per stain, or NULL
+ *   hist_hi_out [2] the range hist_out was built over (after an automatic retry), or NULL
+ *   ws        spcn_workspace_size(SPCN_OP_DENSITIES, 0, 0, 0) bytes (range and retry words)
  * Histogram counts are exact: bin decisions agree with FP64 arithmetic on every pixel. */
 spcn_status spcn_densities(const uint8_t* img, int64_t height, int64_t width, const float* w,
                            const spcn_params* p, float* h_out, uint64_t* hist_out, float* p99_out,
-                           int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream);
+                           int32_t* flags_out, float* hist_hi_out, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
 
 /* Optional device outputs of spcn_normalize (any member may be NULL). */
 typedef struct {
@@ -114,6 +129,7 @@ typedef struct {
     float* p99_src;     /* [2] source percentile P99(H_src)             */
     float* scale;       /* [2] applied scale P99(H_tgt) / P99(H_src)    */
     int32_t* flags;     /* [2] SPCN_FLAG_* per stain                    */
+    float* hist_hi;     /* [2] histogram range used (after an automatic retry) */
 } spcn_norm_stats;
 
 /* Fused normalisation of one uint8 image (Eqs. 1-4): pass 1 solves every pixel and builds the
@@ -123,7 +139,12 @@ typedef struct {
  *   w_src      [6] source basis;  w_tgt [6] target basis
  *   scale_tgt  [2] target percentiles P99(H_tgt) (e.g. p99_out of spcn_densities on the target)
  *   i0_out     host [3] intensity of Eq. (4), or NULL for p->i0
- *   st         host struct of optional device outputs, or NULL */
+ *   st         host struct of optional device outputs, or NULL
+ *   ws         spcn_workspace_size(SPCN_OP_NORMALIZE, 0, 0, 0) bytes: histogram, range and retry
+ *              words (the histogram goes to st->hist instead when that is given)
+ * With p->auto_range, pass 1 is launched a second time; that launch ends at once unless a stain's
+ * percentile fell in the last bin, in which case it rebuilds the histogram at twice that stain's
+ * range (one retry, decided on the device, so the call stays free of host synchronisation). */
 spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
                            const float* w_tgt, const float* scale_tgt, const float* i0_out,
                            const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
@@ -132,7 +153,9 @@ spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, co
 /* Pass 2 of spcn_normalize on its own: percentile of Eq. 3 from a given non-white histogram (from
  * spcn_densities on this image, or the element-wise sum of the histograms of its shards), scaling,
  * recolouring and Eq. 4.  Arguments as for spcn_normalize; hist is an input here and st->hist is
- * ignored.  spcn_densities followed by spcn_recolor equals spcn_normalize. */
+ * ignored.  The histogram's range is p->hist_hi_dev or p->hist_hi (no retry: the histogram is
+ * given); st->hist_hi receives it.  spcn_densities followed by spcn_recolor (with hist_hi_dev =
+ * the hist_hi_out of spcn_densities) equals spcn_normalize. */
 spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
                          const float* w_tgt, const float* scale_tgt, const float* i0_out,
                          const spcn_params* p, const uint64_t* hist, uint8_t* out,
@@ -232,12 +255,16 @@ spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, 
  *   w_init       [6] initial basis, or NULL for the unit reference H&E vectors
  *                [0.65, 0.70, 0.29] and [0.07, 0.99, 0.11]
  *   w_out        [6] fitted basis;  sample_p99 [2] nearest-rank percentile (p->percentile) of the
- *                fitted densities of the samples, or NULL;  flags_out [2] or NULL */
+ *                fitted densities of the samples, or NULL;  flags_out [2] or NULL
+ *   hist_hi_out  [2] histogram range for the passes, or NULL: per stain the power of two
+ *                2^ceil(log2(2 * sample_p99_j)), clamped to [2^-4, 2^6] (feed it to
+ *                spcn_params.hist_hi_dev: the image percentile then lands in the middle of the bins
+ *                unless it is more than twice the sample's) */
 spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t width,
                                 const spcn_params* p, float lambda_nmf, int64_t n_samples,
                                 uint64_t seed, int32_t n_iter, const float* w_init, float* w_out,
-                                float* sample_p99, int32_t* flags_out, void* ws, size_t ws_bytes,
-                                hipStream_t stream);
+                                float* sample_p99, float* hist_hi_out, int32_t* flags_out, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
 
 /* Channel-wise background intensity i0 (Sec. 3.1 item 1: the fixed maximum intensity of Eqs. 1
  * and 4 replaced by a per-image, per-channel estimate).  Draws pixels with the same counter-based
@@ -265,14 +292,17 @@ typedef struct {
 
 /* Basis estimation for every tile of a batch (same algorithm as spcn_estimate_basis, one
  * workgroup per tile).  tiles: device array of n_tiles descriptors; w_out [n_tiles][6];
- * sample_p99 [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.  Tile t uses seed + t.  A
+ * sample_p99 [n_tiles][2] or NULL; hist_hi_out [n_tiles][2] or NULL (as in spcn_estimate_basis,
+ * per tile: feed it to spcn_params.hist_hi_dev of spcn_normalize_batched); flags_out [n_tiles][2]
+ * or NULL.  Tile t uses seed + t.  A
  * descriptor with a NULL source or no pixels is not read: its basis is the initial one, its
  * percentiles 0 and its flags SPCN_FLAG_SHORT | SPCN_FLAG_NO_TISSUE. */
 spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t max_tile_px,
                                         const spcn_params* p, float lambda_nmf, int64_t n_samples,
                                         uint64_t seed, int32_t n_iter, const float* w_init,
-                                        float* w_out, float* sample_p99, int32_t* flags_out,
-                                        void* ws, size_t ws_bytes, hipStream_t stream);
+                                        float* w_out, float* sample_p99, float* hist_hi_out,
+                                        int32_t* flags_out, void* ws, size_t ws_bytes,
+                                        hipStream_t stream);
 
 /* Normalises every tile of a batch to one target (Eqs. 1-4, each tile with its own basis
  * w_src[t] and its own percentile) in ONE persistent kernel launch: a global work queue hands out
@@ -283,7 +313,9 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
  *            more, nothing is processed and every tile's flags get SPCN_FLAG_BATCH)
  *   w_src [n_tiles][6]; w_tgt [6]; scale_tgt [2]; i0_out host [3] or NULL;
  *   p99_out, scale_out [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.
- * Results are identical to calling spcn_normalize on each tile. */
+ * Tile t's histogram range is p->hist_hi_dev[2t .. 2t+1] when given, else p->hist_hi; there is no
+ * automatic retry (a percentile in the last bin sets SPCN_FLAG_RANGE for that tile).
+ * Results are identical to calling spcn_normalize on each tile with that range and auto_range 0. */
 spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px,
                                    const float* w_src, const float* w_tgt, const float* scale_tgt,
                                    const float* i0_out, const spcn_params* p, float* p99_out,

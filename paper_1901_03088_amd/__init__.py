@@ -24,8 +24,8 @@ _L = C.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ ABI mirror
 
 SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
-FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT, FLAG_NO_BACKGROUND = \
-    1, 2, 4, 8, 16, 32, 64, 128
+FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT, FLAG_NO_BACKGROUND, \
+    FLAG_RANGE_RETRY = 1, 2, 4, 8, 16, 32, 64, 128, 256
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
     OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES, \
     OP_STREAM_NORMALIZE, OP_EXACT_PERCENTILE = range(12)
@@ -35,11 +35,13 @@ OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
 class spcn_params(C.Structure):
     _fields_ = [("i0", C.c_float * 3), ("lambda_", C.c_float), ("white_sum", C.c_int32),
-                ("percentile", C.c_float), ("hist_hi", C.c_float * 2)]
+                ("percentile", C.c_float), ("hist_hi", C.c_float * 2), ("hist_hi_dev", C.c_void_p),
+                ("auto_range", C.c_int32)]
 
 
 class spcn_norm_stats(C.Structure):
-    _fields_ = [("hist", C.c_void_p), ("p99_src", C.c_void_p), ("scale", C.c_void_p), ("flags", C.c_void_p)]
+    _fields_ = [("hist", C.c_void_p), ("p99_src", C.c_void_p), ("scale", C.c_void_p), ("flags", C.c_void_p),
+                ("hist_hi", C.c_void_p)]
 
 
 class spcn_tile(C.Structure):
@@ -52,15 +54,15 @@ _P = C.POINTER(spcn_params)
 _SIGS = {
     "spcn_default_params": (None, [_P]),
     "spcn_workspace_size": (_sz, [C.c_int, _i64, _i64, _i64]),
-    "spcn_densities": (C.c_int, [_vp, _i64, _i64, _vp, _P, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_densities": (C.c_int, [_vp, _i64, _i64, _vp, _P, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, C.POINTER(spcn_norm_stats), _vp,
                                  _sz, _vp]),
     "spcn_recolor": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, C.POINTER(spcn_norm_stats),
                                _vp]),
-    "spcn_estimate_basis": (C.c_int, [_vp, _i64, _i64, _P, _f, _i64, _u64, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
-                                      _vp]),
+    "spcn_estimate_basis": (C.c_int, [_vp, _i64, _i64, _P, _f, _i64, _u64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _sz, _vp]),
     "spcn_estimate_basis_batched": (C.c_int, [_vp, _i32, _i64, _P, _f, _i64, _u64, _i32, _vp, _vp, _vp, _vp,
-                                              _vp, _sz, _vp]),
+                                              _vp, _vp, _sz, _vp]),
     "spcn_estimate_i0": (C.c_int, [_vp, _i64, _i64, _i64, _u64, _i32, _f, _vp, _vp, _vp, _sz, _vp]),
     "spcn_band_percentiles": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_sample_percentile": (C.c_int, [_vp, _i64, _i64, _vp, _P, _i64, _u64, _vp, _vp, _vp, _sz, _vp]),
@@ -101,7 +103,10 @@ def _check(status: int, where: str):
         raise SPCNError(status, where)
 
 
-def params(i0=(255.0, 255.0, 255.0), lam=0.01, white_sum=660, percentile=99.0, hist_hi=(4.0, 4.0)) -> spcn_params:
+def params(i0=(255.0, 255.0, 255.0), lam=0.01, white_sum=660, percentile=99.0, hist_hi=(4.0, 4.0),
+           hist_hi_dev: torch.Tensor | None = None, auto_range: bool = True) -> spcn_params:
+    """Parameters; hist_hi_dev is a device float32 tensor of ranges ([2], or [n_tiles, 2] for the
+    batched normalisation) that replaces hist_hi (the struct keeps a reference to it)."""
     p = spcn_params()
     _L.spcn_default_params(C.byref(p))
     p.i0[:] = [float(v) for v in (i0 if hasattr(i0, "__len__") else (i0, i0, i0))]
@@ -109,7 +114,25 @@ def params(i0=(255.0, 255.0, 255.0), lam=0.01, white_sum=660, percentile=99.0, h
     p.white_sum = int(white_sum)
     p.percentile = float(percentile)
     p.hist_hi[:] = [float(v) for v in (hist_hi if hasattr(hist_hi, "__len__") else (hist_hi, hist_hi))]
+    if hist_hi_dev is not None:
+        _dev(hist_hi_dev, torch.float32, "hist_hi_dev")
+        p.hist_hi_dev = hist_hi_dev.data_ptr()
+        p._hist_hi_ref = hist_hi_dev
+    p.auto_range = 1 if auto_range else 0
     return p
+
+
+def copy_params(p: spcn_params, hist_hi_dev: torch.Tensor | None = None) -> spcn_params:
+    """A copy of p; with hist_hi_dev, reading its range from that device tensor."""
+    q = spcn_params()
+    C.pointer(q)[0] = p
+    if getattr(p, "_hist_hi_ref", None) is not None:
+        q._hist_hi_ref = p._hist_hi_ref
+    if hist_hi_dev is not None:
+        _dev(hist_hi_dev, torch.float32, "hist_hi_dev")
+        q.hist_hi_dev = hist_hi_dev.data_ptr()
+        q._hist_hi_ref = hist_hi_dev
+    return q
 
 
 def workspace_size(op: int, n_px: int = 0, n_items: int = 0, n_samples: int = 0) -> int:
@@ -160,10 +183,11 @@ def as_basis(W, device) -> torch.Tensor:
 # ------------------------------------------------------------------ entry points
 
 def spcn_densities(img: torch.Tensor, w: torch.Tensor, p: spcn_params | None = None, want_h: bool = True,
-                   h_out=None, hist_out=None, p99_out=None, flags_out=None, finalize: bool = True):
+                   h_out=None, hist_out=None, p99_out=None, flags_out=None, finalize: bool = True,
+                   hist_hi_out=None, ws=None):
     """img (H, W, 3) uint8 on the GPU; w float32 [6].  Returns (h [2, H*W] or None, hist [2, 256]
     uint64, p99 [2] float32, flags [2] int32); with finalize=False no percentile is taken and
-    p99 / flags are None."""
+    p99 / flags are None.  hist_hi_out (device float32 [2]) receives the histogram's range."""
     _dev(img, torch.uint8, "img")
     _dev(w, torch.float32, "w")
     p = p or params()
@@ -178,14 +202,18 @@ def spcn_densities(img: torch.Tensor, w: torch.Tensor, p: spcn_params | None = N
         flags_out = flags_out if flags_out is not None else torch.empty(2, dtype=torch.int32, device=dev)
     else:
         p99_out = flags_out = None
+    if ws is None:
+        ws = workspace(workspace_size(OP_DENSITIES), dev)
+    wsp, wsn = _ws_ptr(ws)
     _check(_L.spcn_densities(_ptr(img), H, W_, _ptr(w), C.byref(p), _ptr(h_out if want_h else None),
-                             _ptr(hist_out), _ptr(p99_out), _ptr(flags_out), None, 0, _stream()), "spcn_densities")
+                             _ptr(hist_out), _ptr(p99_out), _ptr(flags_out), _ptr(hist_hi_out), wsp, wsn, _stream()),
+           "spcn_densities")
     return (h_out if want_h else None), hist_out, p99_out, flags_out
 
 
 def spcn_normalize(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
                    p: spcn_params | None = None, i0_out=None, out=None, stats: bool = True, ws=None):
-    """src (H, W, 3) uint8 on the GPU.  Returns (out, dict(hist, p99_src, scale, flags))."""
+    """src (H, W, 3) uint8 on the GPU.  Returns (out, dict(hist, p99_src, scale, flags, hist_hi))."""
     _dev(src, torch.uint8, "src")
     for t, nm in ((w_src, "w_src"), (w_tgt, "w_tgt"), (scale_tgt, "scale_tgt")):
         _dev(t, torch.float32, nm)
@@ -199,11 +227,12 @@ def spcn_normalize(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, 
         res = {"hist": torch.empty((2, HIST_BINS), dtype=torch.uint64, device=dev),
                "p99_src": torch.empty(2, dtype=torch.float32, device=dev),
                "scale": torch.empty(2, dtype=torch.float32, device=dev),
-               "flags": torch.empty(2, dtype=torch.int32, device=dev)}
+               "flags": torch.empty(2, dtype=torch.int32, device=dev),
+               "hist_hi": torch.empty(2, dtype=torch.float32, device=dev)}
         st = spcn_norm_stats(res["hist"].data_ptr(), res["p99_src"].data_ptr(), res["scale"].data_ptr(),
-                             res["flags"].data_ptr())
-    if ws is None and not stats:
-        ws = workspace(workspace_size(OP_NORMALIZE, H * W_), dev)
+                             res["flags"].data_ptr(), res["hist_hi"].data_ptr())
+    if ws is None:
+        ws = workspace(workspace_size(OP_NORMALIZE), dev)
     wsp, wsn = _ws_ptr(ws)
     io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
     _check(_L.spcn_normalize(_ptr(src), H, W_, _ptr(w_src), _ptr(w_tgt), _ptr(scale_tgt), io, C.byref(p),
@@ -213,8 +242,9 @@ def spcn_normalize(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, 
 
 
 def spcn_recolor(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
-                 hist: torch.Tensor, p: spcn_params | None = None, i0_out=None, out=None, stats: bool = True):
-    """Pass 2 alone, from a given [2, 256] uint64 histogram.  Returns (out, dict(p99_src, scale, flags))."""
+                 hist: torch.Tensor, p: spcn_params | None = None, i0_out=None, out=None, stats=True):
+    """Pass 2 alone, from a given [2, 256] uint64 histogram.  Returns (out, dict(p99_src, scale, flags,
+    hist_hi)); stats may be a dict of such preallocated device tensors to write into."""
     _dev(src, torch.uint8, "src")
     _dev(hist, torch.uint64, "hist")
     p = p or params()
@@ -223,11 +253,17 @@ def spcn_recolor(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, sc
     out = out if out is not None else torch.empty_like(src)
     res = {}
     st = None
-    if stats:
+    if isinstance(stats, dict):
+        res = stats
+        st = spcn_norm_stats(None, res["p99_src"].data_ptr(), res["scale"].data_ptr(), res["flags"].data_ptr(),
+                             res["hist_hi"].data_ptr())
+    elif stats:
         res = {"p99_src": torch.empty(2, dtype=torch.float32, device=dev),
                "scale": torch.empty(2, dtype=torch.float32, device=dev),
-               "flags": torch.empty(2, dtype=torch.int32, device=dev)}
-        st = spcn_norm_stats(None, res["p99_src"].data_ptr(), res["scale"].data_ptr(), res["flags"].data_ptr())
+               "flags": torch.empty(2, dtype=torch.int32, device=dev),
+               "hist_hi": torch.empty(2, dtype=torch.float32, device=dev)}
+        st = spcn_norm_stats(None, res["p99_src"].data_ptr(), res["scale"].data_ptr(), res["flags"].data_ptr(),
+                             res["hist_hi"].data_ptr())
     io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
     _check(_L.spcn_recolor(_ptr(src), H, W_, _ptr(w_src), _ptr(w_tgt), _ptr(scale_tgt), io, C.byref(p),
                            _ptr(hist), _ptr(out), C.byref(st) if st is not None else None, _stream()),
@@ -237,9 +273,10 @@ def spcn_recolor(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, sc
 
 def spcn_estimate_basis(img: torch.Tensor, n_samples: int, seed: int, p: spcn_params | None = None,
                         lambda_nmf: float = 0.1, n_iter: int = 50, w_init=None, want_p99: bool = True,
-                        w_out=None, ws=None):
+                        w_out=None, ws=None, hist_hi_out=None):
     """Sparse-NMF stain basis of a uint8 (H, W, 3) image.  Returns (w [6] float32, sample_p99 [2]
-    or None, flags [2] int32)."""
+    or None, flags [2] int32).  hist_hi_out (device float32 [2]) receives the histogram range derived
+    from the sample percentile (feed it to params(hist_hi_dev=...))."""
     _dev(img, torch.uint8, "img")
     p = p or params()
     H, W_ = int(img.shape[0]), int(img.shape[1])
@@ -252,7 +289,7 @@ def spcn_estimate_basis(img: torch.Tensor, n_samples: int, seed: int, p: spcn_pa
     wsp, wsn = _ws_ptr(ws)
     _check(_L.spcn_estimate_basis(_ptr(img), H, W_, C.byref(p), float(lambda_nmf), int(n_samples),
                                   int(seed) & (2 ** 64 - 1), int(n_iter), _ptr(w_init), _ptr(w_out), _ptr(sp),
-                                  _ptr(flags), wsp, wsn, _stream()), "spcn_estimate_basis")
+                                  _ptr(hist_hi_out), _ptr(flags), wsp, wsn, _stream()), "spcn_estimate_basis")
     return w_out, sp, flags
 
 
@@ -392,9 +429,9 @@ def tile_table(srcs, outs=None) -> torch.Tensor:
 
 def spcn_estimate_basis_batched(tiles: torch.Tensor, n_tiles: int, n_samples: int, seed: int,
                                 p: spcn_params | None = None, lambda_nmf: float = 0.1, n_iter: int = 50,
-                                w_init=None, want_p99: bool = True, ws=None):
+                                w_init=None, want_p99: bool = True, ws=None, hist_hi_out=None):
     """Per-tile bases for a device tile table (see tile_table).  Returns (w [n, 6], p99 [n, 2] or None,
-    flags [n, 2])."""
+    flags [n, 2]).  hist_hi_out (device float32 [n, 2]) receives each tile's histogram range."""
     p = p or params()
     dev = tiles.device
     w_out = torch.empty((n_tiles, 6), dtype=torch.float32, device=dev)
@@ -406,7 +443,7 @@ def spcn_estimate_basis_batched(tiles: torch.Tensor, n_tiles: int, n_samples: in
     wsp, wsn = _ws_ptr(ws)
     _check(_L.spcn_estimate_basis_batched(_ptr(tiles), int(n_tiles), 0, C.byref(p), float(lambda_nmf),
                                           int(n_samples), int(seed) & (2 ** 64 - 1), int(n_iter), _ptr(w_init),
-                                          _ptr(w_out), _ptr(sp), _ptr(flags), wsp, wsn, _stream()),
+                                          _ptr(w_out), _ptr(sp), _ptr(hist_hi_out), _ptr(flags), wsp, wsn, _stream()),
            "spcn_estimate_basis_batched")
     return w_out, sp, flags
 

@@ -18,9 +18,9 @@ from typing import Callable, Dict, Iterable, List, Optional, Tuple
 
 import torch
 
-from . import (OPT_BATCH_CHUNK, OPT_P1_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_P2_VARIANT, get_option, params,
-               set_option, spcn_densities, spcn_normalize_batched, spcn_recolor, workspace, workspace_size,
-               OP_NORMALIZE_BATCHED)
+from . import (OPT_BATCH_CHUNK, OPT_P1_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_P2_VARIANT, copy_params, get_option,
+               params, set_option, spcn_densities, spcn_normalize_batched, spcn_recolor, workspace, workspace_size,
+               OP_DENSITIES, OP_NORMALIZE_BATCHED)
 
 P1_CANDIDATES = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9)
 P2_CANDIDATES = ((0, 1), (0, 2), (0, 3), (0, 4), (1, 2), (2, 1), (3, 1), (3, 2), (3, 3), (3, 4), (3, 6), (3, 8),
@@ -125,10 +125,12 @@ def tune_image(img: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scal
         apply(cache[key]["options"])
         return dict(cache[key], cached=True)
     hist = torch.empty((2, 256), dtype=torch.uint64, device=img.device)
+    hh = torch.empty(2, dtype=torch.float32, device=img.device)
+    ws = workspace(workspace_size(OP_DENSITIES), img.device)
     out = torch.empty_like(img)
 
     def p1_run():
-        spcn_densities(img, w_src, p, want_h=False, hist_out=hist, finalize=False)
+        spcn_densities(img, w_src, p, want_h=False, hist_out=hist, finalize=False, hist_hi_out=hh, ws=ws)
     best1, rows1 = _sweep(P1_CANDIDATES, lambda v: set_option(OPT_P1_VARIANT, v), p1_run, lambda: [hist], reps)
     set_option(OPT_P1_VARIANT, best1)
     p1_run()
@@ -137,8 +139,10 @@ def tune_image(img: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scal
         set_option(OPT_P2_VARIANT, c[0])
         set_option(OPT_P2_BLOCKS_PER_CU, c[1])
 
+    p2 = copy_params(p, hist_hi_dev=hh)     # the range the histogram was built over
+
     def p2_run():
-        spcn_recolor(img, w_src, w_tgt, scale_tgt, hist, p, out=out, stats=False)
+        spcn_recolor(img, w_src, w_tgt, scale_tgt, hist, p2, out=out, stats=False)
     best2, rows2 = _sweep(P2_CANDIDATES, p2_set, p2_run, lambda: [out], reps)
     p2_set(best2)
     res = {"options": {"p1_variant": best1, "p2_variant": best2[0], "p2_blocks_per_cu": best2[1]},

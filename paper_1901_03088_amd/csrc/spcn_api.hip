@@ -61,6 +61,8 @@ ParamsK make_params(const spcn_params* p) {
     k.q64 = (double)p->percentile / 100.0;
     k.hist_hi[0] = p->hist_hi[0];
     k.hist_hi[1] = p->hist_hi[1];
+    k.hist_hi_dev = p->hist_hi_dev;
+    k.auto_range = p->auto_range;
     return k;
 }
 
@@ -89,6 +91,9 @@ static spcn_status check_params(const spcn_params* p, bool u8_input) {
             return fail(SPCN_E_ARG, "hist_hi[%d] = %g must be a power of two in [2^-8, 2^8]", j,
                         (double)p->hist_hi[j]);
     }
+    if (p->auto_range != 0 && p->auto_range != 1) return fail(SPCN_E_ARG, "auto_range = %d must be 0 or 1",
+                                                              (int)p->auto_range);
+    if (((uintptr_t)p->hist_hi_dev) & 3) return fail(SPCN_E_ARG, "hist_hi_dev must be 4-byte aligned");
     return SPCN_OK;
 }
 
@@ -129,6 +134,8 @@ void spcn_default_params(spcn_params* p) {
     p->percentile = 99.0f;
     p->hist_hi[0] = 4.0f;
     p->hist_hi[1] = 4.0f;
+    p->hist_hi_dev = nullptr;
+    p->auto_range = 1;
 }
 
 size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samples) {
@@ -164,25 +171,29 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
 
 spcn_status spcn_densities(const uint8_t* img, int64_t height, int64_t width, const float* w,
                            const spcn_params* p, float* h_out, uint64_t* hist_out, float* p99_out,
-                           int32_t* flags_out, void* ws, size_t ws_bytes, hipStream_t stream) {
-    (void)ws; (void)ws_bytes;
+                           int32_t* flags_out, float* hist_hi_out, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
     SPCN_CHECK(check_image(img, height, width, "img"));
     SPCN_CHECK(check_params(p, true));
     if (!w) return fail(SPCN_E_ARG, "w is NULL");
     if (!hist_out) return fail(SPCN_E_ARG, "hist_out is NULL");
     if (h_out && (((uintptr_t)h_out) & 15)) return fail(SPCN_E_ARG, "h_out must be 16-byte aligned");
+    SPCN_CHECK(check_ws(ws, ws_bytes, u8_workspace_bytes()));
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_densities(img, height * width, w, make_params(p), h_out, hist_out, p99_out, flags_out,
-                                    dev, stream);
+                                    hist_hi_out, ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_densities launch");
     return SPCN_OK;
 }
 
-spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
-                           const float* w_tgt, const float* scale_tgt, const float* i0_out,
-                           const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
-                           void* ws, size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+// spcn_normalize's checks and launches, with the workspace the caller or the library provides.
+static spcn_status normalize_into(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                                  const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                                  const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                                  void* ws, size_t ws_bytes, hipStream_t stream) {
     SPCN_CHECK(check_image(src, height, width, "src"));
     SPCN_CHECK(check_image(out, height, width, "out"));
     SPCN_CHECK(check_params(p, true));
@@ -194,18 +205,24 @@ spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, co
     for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
     for (int c = 0; c < 3; ++c)
         if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
-    uint64_t* hist = st && st->hist ? st->hist : nullptr;
-    if (!hist) {
-        SPCN_CHECK(check_ws(ws, ws_bytes, u8_workspace_bytes()));
-        hist = static_cast<uint64_t*>(ws);
-    }
+    SPCN_CHECK(check_ws(ws, ws_bytes, u8_workspace_bytes()));
+    uint64_t* hist = st && st->hist ? st->hist : static_cast<uint64_t*>(ws);
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
-    hipError_t e = launch_normalize(src, n, w_src, w_tgt, scale_tgt, io, make_params(p), out, hist,
+    hipError_t e = launch_normalize(src, n, w_src, w_tgt, scale_tgt, io, make_params(p), out, hist, ws,
                                     st ? st->p99_src : nullptr, st ? st->scale : nullptr,
-                                    st ? st->flags : nullptr, dev, stream);
+                                    st ? st->flags : nullptr, st ? st->hist_hi : nullptr, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_normalize launch");
     return SPCN_OK;
+}
+
+extern "C" {
+
+spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                           const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                           const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+    return normalize_into(src, height, width, w_src, w_tgt, scale_tgt, i0_out, p, out, st, ws, ws_bytes, stream);
 }
 
 spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
@@ -228,7 +245,7 @@ spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, cons
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_recolor(src, n, w_src, w_tgt, scale_tgt, io, make_params(p), out, hist,
                                   st ? st->p99_src : nullptr, st ? st->scale : nullptr, st ? st->flags : nullptr,
-                                  dev, stream);
+                                  st ? st->hist_hi : nullptr, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_recolor launch");
     return SPCN_OK;
 }
@@ -244,7 +261,8 @@ static spcn_status check_fit(float lambda_nmf, int64_t n_samples, int32_t n_iter
 
 spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t width, const spcn_params* p,
                                 float lambda_nmf, int64_t n_samples, uint64_t seed, int32_t n_iter,
-                                const float* w_init, float* w_out, float* sample_p99, int32_t* flags_out,
+                                const float* w_init, float* w_out, float* sample_p99, float* hist_hi_out,
+                                int32_t* flags_out,
                                 void* ws, size_t ws_bytes, hipStream_t stream) {
     SPCN_CHECK(check_image(img, height, width, "img"));
     SPCN_CHECK(check_params(p, true));
@@ -254,7 +272,7 @@ spcn_status spcn_estimate_basis(const uint8_t* img, int64_t height, int64_t widt
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_estimate_basis(img, height * width, make_params(p), lambda_nmf, n_samples, seed, n_iter,
-                                         w_init, w_out, sample_p99, flags_out, ws, dev, stream);
+                                         w_init, w_out, sample_p99, hist_hi_out, flags_out, ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_estimate_basis launch");
     return SPCN_OK;
 }
@@ -397,7 +415,8 @@ int64_t spcn_stream_resident_chunks(int64_t height, int64_t width, int64_t chunk
 spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t max_tile_px,
                                         const spcn_params* p, float lambda_nmf, int64_t n_samples,
                                         uint64_t seed, int32_t n_iter, const float* w_init, float* w_out,
-                                        float* sample_p99, int32_t* flags_out, void* ws, size_t ws_bytes,
+                                        float* sample_p99, float* hist_hi_out, int32_t* flags_out, void* ws,
+                                        size_t ws_bytes,
                                         hipStream_t stream) {
     (void)max_tile_px;
     if (!tiles) return fail(SPCN_E_ARG, "tiles is NULL");
@@ -409,7 +428,8 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_estimate_basis_batched(tiles, n_tiles, make_params(p), lambda_nmf, n_samples, seed, n_iter,
-                                                 w_init, w_out, sample_p99, flags_out, ws, dev, stream);
+                                                 w_init, w_out, sample_p99, hist_hi_out, flags_out, ws, dev,
+                                                 stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_estimate_basis_batched launch");
     return SPCN_OK;
 }

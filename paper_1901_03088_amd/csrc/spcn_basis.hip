@@ -607,7 +607,7 @@ __global__ __launch_bounds__(256) void k_sel_digits(const double* H, int64_t ns,
 // One workgroup of 256 threads per stain: the digit holding the remaining rank (parallel prefix sums),
 // the digit histogram cleared for the next pass; after the last pass the value and the flags.
 __global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* dhist, int pass, int64_t ns,
-                                                  float* p99_out, int32_t* flags_out) {
+                                                  float* p99_out, int32_t* flags_out, float* range_out = nullptr) {
     __shared__ uint32_t s_wsum[4];
     __shared__ int s_g;
     __shared__ uint32_t s_below;
@@ -653,7 +653,9 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* dhist,
         for (int i = t; i < SEL_BINS; i += blockDim.x) dh[i] = 0u;
     }
     if (pass == SEL_PASSES - 1 && t == 0) {
-        p99_out[j] = n > 0 ? (float)__longlong_as_double((long long)st->prefix[j]) : 0.0f;
+        const double P = n > 0 ? __longlong_as_double((long long)st->prefix[j]) : 0.0;
+        if (p99_out) p99_out[j] = (float)P;
+        if (range_out) range_out[j] = range_for_percentile((double)(float)P);
         if (flags_out) flags_out[j] = (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
     }
 }
@@ -673,6 +675,7 @@ struct TileArgs {
     const float* w_init;
     float* w_out;
     float* sample_p99;
+    float* range_out;
     int32_t* flags_out;
 };
 
@@ -754,7 +757,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
             for (int j = 0; j < 2; ++j)
                 a.flags_out[2 * tile + j] = (n < n_s ? SPCN_FLAG_SHORT : 0) | (n == 0 ? SPCN_FLAG_NO_TISSUE : 0);
     }
-    if (!a.sample_p99) return;
+    if (!a.sample_p99 && !a.range_out) return;
     NmfBasis B;
     nmf_basis(W, a.lambda, B);
     double hv[TILE_SPT][2];
@@ -787,7 +790,10 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
             }
             P = __longlong_as_double((long long)prefix);
         }
-        if (threadIdx.x == 0) a.sample_p99[2 * tile + j] = (float)P;
+        if (threadIdx.x == 0) {
+            if (a.sample_p99) a.sample_p99[2 * tile + j] = (float)P;
+            if (a.range_out) a.range_out[2 * tile + j] = range_for_percentile((double)(float)P);
+        }
     }
 }
 
@@ -825,19 +831,20 @@ size_t basis_workspace_bytes(int64_t n_s) {
 // Nearest-rank percentile of both stains of H [2][n_s] (the first bw->n_acc values of each row):
 // the selection state, then six digit passes.
 static void launch_select(const BasisWork* bw, const double* H, int64_t n_s, double q, SelState* sel, uint32_t* dhist,
-                          float* p99_out, int32_t* flags_out, const DevInfo& dev, hipStream_t s) {
+                          float* p99_out, int32_t* flags_out, const DevInfo& dev, hipStream_t s,
+                          float* range_out = nullptr) {
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, s, bw, q, sel, dhist);
     const int64_t sel_want = hmin((n_s + 1023) / 1024, (int64_t)dev.cus);
     const unsigned sel_grid = (unsigned)(sel_want > 0 ? sel_want : 1);
     for (int pass = 0; pass < SEL_PASSES; ++pass) {
         hipLaunchKernelGGL(k_sel_digits, dim3(sel_grid, 2), dim3(256), 0, s, H, n_s, (const SelState*)sel, dhist, pass);
-        hipLaunchKernelGGL(k_sel_pick, dim3(2), dim3(256), 0, s, sel, dhist, pass, n_s, p99_out, flags_out);
+        hipLaunchKernelGGL(k_sel_pick, dim3(2), dim3(256), 0, s, sel, dhist, pass, n_s, p99_out, flags_out, range_out);
     }
 }
 
 hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK& pk, float lambda_nmf,
                                  int64_t n_s, uint64_t seed, int32_t n_iter, const float* w_init,
-                                 float* w_out, float* sample_p99, int32_t* flags_out, void* ws,
+                                 float* w_out, float* sample_p99, float* range_out, int32_t* flags_out, void* ws,
                                  const DevInfo& dev, hipStream_t s) {
     const int nblk = (int)((n_s + FIT_PER_BLOCK - 1) / FIT_PER_BLOCK);
     if (nblk > FIT_MAX_BLOCKS) return hipErrorInvalidValue;
@@ -868,10 +875,10 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     FitArgs fa{bw, V, xchg, (double)lambda_nmf, n_iter};
     if (n_iter > 0) hipLaunchKernelGGL(k_nmf_fit, dim3(nblk), dim3(FIT_THREADS), 0, s, fa);
     hipLaunchKernelGGL(k_nmf_finish, dim3(1), dim3(64), 0, s, bw, w_out, flags_out);
-    if (sample_p99) {
+    if (sample_p99 || range_out) {
         hipLaunchKernelGGL(k_nmf_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
                            (const BasisWork*)bw, (const double*)V, (double)lambda_nmf, H);
-        launch_select(bw, H, n_s, pk.q64, sel, dhist, sample_p99, nullptr, dev, s);
+        launch_select(bw, H, n_s, pk.q64, sel, dhist, sample_p99, nullptr, dev, s, range_out);
     }
     return hipGetLastError();
 }
@@ -1029,13 +1036,14 @@ size_t basis_batched_workspace_bytes(int64_t, int64_t) { return 0; }
 
 hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, const ParamsK& pk,
                                          float lambda_nmf, int64_t n_s, uint64_t seed, int32_t n_iter,
-                                         const float* w_init, float* w_out, float* sample_p99,
+                                         const float* w_init, float* w_out, float* sample_p99, float* range_out,
                                          int32_t* flags_out, void*, const DevInfo&, hipStream_t s) {
     TileArgs a{};
     a.tiles = tiles; a.n_tiles = n_tiles;
     for (int c = 0; c < 3; ++c) a.i0[c] = pk.i0[c];
     a.white_sum = pk.white_sum; a.lambda = (double)lambda_nmf; a.q = pk.q64; a.n_s = n_s; a.seed = seed;
-    a.n_iter = n_iter; a.w_init = w_init; a.w_out = w_out; a.sample_p99 = sample_p99; a.flags_out = flags_out;
+    a.n_iter = n_iter; a.w_init = w_init; a.w_out = w_out; a.sample_p99 = sample_p99; a.range_out = range_out;
+    a.flags_out = flags_out;
     hipLaunchKernelGGL(k_nmf_tiles, dim3(n_tiles), dim3(TILE_THREADS), 0, s, a);
     return hipGetLastError();
 }

@@ -35,6 +35,7 @@ struct TileInfo {
     int32_t ok;             // basis usable
     int32_t bad;            // descriptor unusable (null or misaligned pointer, empty tile): skipped
     int32_t pad;
+    float hh[2];            // histogram range of the tile's stains
 };
 
 struct BatchHead {
@@ -93,9 +94,12 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
     __shared__ Basis64 B;
     __shared__ int s_shift;
     const int t = blockIdx.x;
+    __shared__ float s_hh[2];
     if (threadIdx.x == 0) {
         derive_basis(a.w_src + 6 * t, a.pp.lambda, B);
-        const int u = table_shift(B, a.pp.i0, a.pp.hist_hi);
+        s_hh[0] = resolve_range(a.pp.range ? a.pp.range + 2 * t : nullptr, a.pp.hist_hi[0]);
+        s_hh[1] = resolve_range(a.pp.range ? a.pp.range + 2 * t + 1 : nullptr, a.pp.hist_hi[1]);
+        const int u = table_shift(B, a.pp.i0, s_hh);
         s_shift = u < 16 ? u : 16;                 // the byte-permute layout works in <= 2^16 units
         const spcn_tile T = a.tiles[t];
         const int64_t n_px = T.height * T.width;
@@ -109,6 +113,8 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
         I.ok = B.ok;
         I.bad = !T.src || !T.out || (((uintptr_t)T.src | (uintptr_t)T.out) & 3) || T.height <= 0 || T.width <= 0;
         I.pad = 0;
+        I.hh[0] = s_hh[0];
+        I.hh[1] = s_hh[1];
         if (I.bad) { I.units = 0; I.tail = 0; I.n_chunks = 1; }
         a.w.info[t] = I;
         a.w.basis[t] = B;
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(256) void k_tiles_setup(SetupArgs a) {
     __syncthreads();
     const int k = threadIdx.x;
     const int u = s_shift;
-    const double sig0 = ldexp(256.0 / (double)a.pp.hist_hi[0], u), sig1 = ldexp(256.0 / (double)a.pp.hist_hi[1], u);
+    const double sig0 = ldexp(256.0 / (double)s_hh[0], u), sig1 = ldexp(256.0 / (double)s_hh[1], u);
     for (int c = 0; c < 3; ++c) {
         const double od = B.ok ? od_u8((double)a.pp.i0[c], k) : 0.0;
         const int g = c == 0 ? kGuardUnits - 2 * kGuardUnits : 0;   // shifted guard of the byte-permute layout
@@ -265,12 +271,16 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
                 S.p1.od[i / kHistBins][i % kHistBins] = a.w.od[i];   // computed once by k_tiles_setup
             if (tid == 0) { S.p1.B = a.w.basis[t]; S.p1.shift = I.shift; }
             __syncthreads();
+            P1Params pp = a.pp;                        // the tile's range
+            pp.hist_hi[0] = I.hh[0];
+            pp.hist_hi[1] = I.hh[1];
+            pp.range = nullptr;
             if (cnt > 0 && !I.bad) {
                 const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(T.src, u0, cnt);
-                if (I.shift == 16) p1f_run<true, RUN_P1_UNROLL, true>(S.p1, a.pp, rs, cnt, tid, RUN_THREADS);
-                else p1f_run<true, RUN_P1_UNROLL, false>(S.p1, a.pp, rs, cnt, tid, RUN_THREADS);
+                if (I.shift == 16) p1f_run<true, RUN_P1_UNROLL, true>(S.p1, pp, rs, cnt, tid, RUN_THREADS);
+                else p1f_run<true, RUN_P1_UNROLL, false>(S.p1, pp, rs, cnt, tid, RUN_THREADS);
             }
-            if (last_chunk && tid == 0 && I.tail && !I.bad) p1f_tail(S.p1, a.pp, T.src + 12 * I.units, I.tail);
+            if (last_chunk && tid == 0 && I.tail && !I.bad) p1f_tail(S.p1, pp, T.src + 12 * I.units, I.tail);
             p1f_merge(S.p1, reinterpret_cast<unsigned long long*>(a.w.hist + (int64_t)t * 2 * kHistBins));
             __syncthreads();
             if (tid == 0) {
@@ -284,7 +294,7 @@ __global__ __launch_bounds__(RUN_THREADS) void k_tiles_run(RunArgs a) {
                 uint64_t* gh = a.w.hist + (int64_t)t * 2 * kHistBins;
                 if (tid < 2 * kHistBins) S.h[tid] = __hip_atomic_load(gh + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __syncthreads();
-                block_percentiles(S.h, a.q, a.pp.hist_hi, S.F);
+                block_percentiles(S.h, a.q, I.hh, S.F);
                 if (tid == 0) {
                     double s[2];
                     int fl[2];
@@ -364,6 +374,7 @@ hipError_t launch_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int
     for (int c = 0; c < 3; ++c) sa.pp.i0[c] = pk.i0[c];
     sa.pp.lambda = pk.lambda; sa.pp.white_sum = pk.white_sum;
     sa.pp.hist_hi[0] = pk.hist_hi[0]; sa.pp.hist_hi[1] = pk.hist_hi[1];
+    sa.pp.range = pk.hist_hi_dev;    // [n_tiles][2] when given
     hipLaunchKernelGGL(k_tiles_setup, dim3(n_tiles), dim3(256), 0, s, sa);
     hipLaunchKernelGGL(k_tiles_plan, dim3(1), dim3(1024), 0, s, w, (int)n_tiles, total_px,
                        max_items_for(n_tiles, total_px), flags_out);

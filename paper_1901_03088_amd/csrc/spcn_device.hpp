@@ -98,6 +98,31 @@ __device__ inline int table_shift(const Basis64& B, const float i0[3], const flo
     return u > 20 ? 20 : (u < 0 ? 0 : u);
 }
 
+// Histogram range of one stain: a device-resident value when one is given (for example the range
+// spcn_estimate_basis derives from its sample percentile), else the host parameter.  A device value
+// is rounded up to a power of two and clamped to [2^-8, 2^8]; one that is not finite and positive
+// falls back to the host value.
+__device__ inline float resolve_range(const float* dev, float host) {
+    if (!dev) return host;
+    const float v = *dev;
+    if (!(v > 0.0f) || !(v <= 3.0e38f)) return host;
+    int e;
+    const float m = frexpf(v, &e);                   // v = m 2^e, m in [0.5, 1)
+    const float r = m == 0.5f ? v : ldexpf(1.0f, e);
+    return fminf(fmaxf(r, 0.00390625f), 256.0f);
+}
+
+// Histogram range derived from a sample percentile P: the power of two 2^ceil(log2(2 P)), clamped
+// to [2^-4, 2^6], so that a percentile of the whole image near P falls in bins 64..127.
+__device__ inline float range_for_percentile(double P) {
+    const double v = 2.0 * P;
+    if (!(v > 0.0625)) return 0.0625f;
+    if (!(v < 64.0)) return 64.0f;
+    int e;
+    const double m = frexp(v, &e);                   // v = m 2^e, m in [0.5, 1)
+    return (float)(m == 0.5 ? v : ldexp(1.0, e));
+}
+
 // Histogram percentile (Eq. 3) of one stain from inclusive cumulative counts, evaluated by the
 // thread that owns the crossing bin k* = min{k : C_k >= q n}:
 //     P = width * (k* + (q n - C_{k*-1}) / c_{k*}).

@@ -440,8 +440,10 @@ size_t exact_workspace_bytes() {
            (size_t)2 * kColours * sizeof(unsigned long long);
 }
 
-hipError_t launch_exact_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
+hipError_t launch_exact_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk_in,
                                    float* p99_out, int32_t* flags_out, void* ws, const DevInfo& dev, hipStream_t s) {
+    ParamsK pk = pk_in;
+    pk.hist_hi_dev = nullptr;   // the range only places the bins of the first read: the host value serves
     ExactWs x = carve(ws);
     hipError_t e = launch_zero_hist(x.hist, s);
     if (e != hipSuccess) return e;

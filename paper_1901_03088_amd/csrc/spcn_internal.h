@@ -38,6 +38,8 @@ struct ParamsK {
     float q;            // percentile / 100 as float (q64 below is the exact value used)
     double q64;         // (double)percentile / 100
     float hist_hi[2];
+    const float* hist_hi_dev;   // device range replacing hist_hi, or NULL
+    int32_t auto_range;         // one automatic retry at a doubled range (single-image paths)
 };
 ParamsK make_params(const spcn_params* p);
 
@@ -47,23 +49,25 @@ struct U8Work {             // device scratch carved out of the caller's workspa
 };
 size_t u8_workspace_bytes();
 
+// ctl_ws: the caller's u8 workspace (u8_workspace_bytes), whose range and retry words follow the
+// histogram slot; hist may be that slot or a caller array.
 hipError_t launch_densities(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
-                            float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out,
-                            const DevInfo& dev, hipStream_t s);
+                            float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out, float* range_out,
+                            void* ctl_ws, const DevInfo& dev, hipStream_t s);
 hipError_t launch_recolor(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
                           const float* scale_tgt, const float i0_out[3], const ParamsK& pk,
                           uint8_t* out, const uint64_t* hist, float* p99_out, float* scale_out,
-                          int32_t* flags_out, const DevInfo& dev, hipStream_t s);
+                          int32_t* flags_out, float* range_out, const DevInfo& dev, hipStream_t s);
 hipError_t launch_normalize(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
                             const float* scale_tgt, const float i0_out[3], const ParamsK& pk,
-                            uint8_t* out, uint64_t* hist, float* p99_out, float* scale_out,
-                            int32_t* flags_out, const DevInfo& dev, hipStream_t s);
+                            uint8_t* out, uint64_t* hist, void* ctl_ws, float* p99_out, float* scale_out,
+                            int32_t* flags_out, float* range_out, const DevInfo& dev, hipStream_t s);
 
 // ---- basis estimation (spcn_basis.hip)
 size_t basis_workspace_bytes(int64_t n_samples);
 hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK& pk, float lambda_nmf,
                                  int64_t n_samples, uint64_t seed, int32_t n_iter, const float* w_init,
-                                 float* w_out, float* sample_p99, int32_t* flags_out, void* ws,
+                                 float* w_out, float* sample_p99, float* range_out, int32_t* flags_out, void* ws,
                                  const DevInfo& dev, hipStream_t s);
 size_t basis_batched_workspace_bytes(int64_t n_tiles, int64_t n_samples);
 int64_t basis_tile_max_samples();
@@ -104,7 +108,7 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
 hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles, const ParamsK& pk,
                                          float lambda_nmf, int64_t n_samples, uint64_t seed,
                                          int32_t n_iter, const float* w_init, float* w_out,
-                                         float* sample_p99, int32_t* flags_out, void* ws,
+                                         float* sample_p99, float* range_out, int32_t* flags_out, void* ws,
                                          const DevInfo& dev, hipStream_t s);
 
 // ---- batched persistent normalisation (spcn_batched.hip)

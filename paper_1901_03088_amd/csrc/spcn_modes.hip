@@ -40,7 +40,8 @@ __global__ void k_band_zero(unsigned long long* h, int64_t n) {
 
 __global__ __launch_bounds__(BH_THREADS, 4) void k_band_hist(const BandArgs a) {
     __shared__ P1FLds<true> S;
-    p1f_setup(S, a.w, a.pp, true);
+    const P1Params pp = p1_resolve(a.pp);
+    p1f_setup(S, a.w, pp, true);
     const int band = blockIdx.x / a.parts, part = blockIdx.x % a.parts;
     const int64_t r0 = (int64_t)band * a.band_rows;
     const int64_t r1 = min(a.height, r0 + a.band_rows);
@@ -52,26 +53,26 @@ __global__ __launch_bounds__(BH_THREADS, 4) void k_band_hist(const BandArgs a) {
     const int cnt = (int)(min(units, u0 + per) - u0);
     const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(a.img + 3 * a0, u0, cnt);
     if (S.shift == 16)
-        p1f_run<true, BH_UNROLL, true>(S, a.pp, rs, cnt, threadIdx.x, BH_THREADS);
+        p1f_run<true, BH_UNROLL, true>(S, pp, rs, cnt, threadIdx.x, BH_THREADS);
     else
-        p1f_run<true, BH_UNROLL, false>(S, a.pp, rs, cnt, threadIdx.x, BH_THREADS);
+        p1f_run<true, BH_UNROLL, false>(S, pp, rs, cnt, threadIdx.x, BH_THREADS);
     if (part == 0 && threadIdx.x == 0) {
         if (a1 > a0) {
-            p1f_tail(S, a.pp, a.img + 3 * p0, (int)(a0 - p0));
-            p1f_tail(S, a.pp, a.img + 3 * a1, (int)(p1 - a1));
+            p1f_tail(S, pp, a.img + 3 * p0, (int)(a0 - p0));
+            p1f_tail(S, pp, a.img + 3 * a1, (int)(p1 - a1));
         } else {
-            p1f_tail(S, a.pp, a.img + 3 * p0, (int)(p1 - p0));   // a band of fewer than 8 pixels
+            p1f_tail(S, pp, a.img + 3 * p0, (int)(p1 - p0));   // a band of fewer than 8 pixels
         }
     }
     p1f_merge(S, a.hist + (int64_t)band * 2 * kHistBins);
 }
 
-__global__ __launch_bounds__(256) void k_band_final(const uint64_t* hist, double q, float hh0, float hh1,
-                                                    const float* w, float lambda, double* band_P, int32_t* band_F,
-                                                    float* band_out) {
+__global__ __launch_bounds__(256) void k_band_final(const uint64_t* hist, double q, const float* range, float hh0,
+                                                    float hh1, const float* w, float lambda, double* band_P,
+                                                    int32_t* band_F, float* band_out) {
     __shared__ FinalShared F;
     __shared__ int basis_ok;
-    const float hh[2] = {hh0, hh1};
+    const float hh[2] = {resolve_range(range, hh0), resolve_range(range ? range + 1 : nullptr, hh1)};
     const int b = blockIdx.x;
     if (threadIdx.x == 0) { Basis64 B; derive_basis(w, lambda, B); basis_ok = B.ok; }
     block_percentiles(hist + (int64_t)b * 2 * kHistBins, q, hh, F);
@@ -154,10 +155,11 @@ hipError_t launch_band_percentiles(const uint8_t* img, int64_t height, int64_t w
     for (int c = 0; c < 3; ++c) a.pp.i0[c] = pk.i0[c];
     a.pp.lambda = pk.lambda; a.pp.white_sum = pk.white_sum;
     a.pp.hist_hi[0] = pk.hist_hi[0]; a.pp.hist_hi[1] = pk.hist_hi[1];
+    a.pp.range = pk.hist_hi_dev;
     a.hist = hist;
     hipLaunchKernelGGL(k_band_hist, dim3((unsigned)(n_bands * a.parts)), dim3(BH_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_band_final, dim3((unsigned)n_bands), dim3(256), 0, s, (const uint64_t*)hist, pk.q64,
-                       pk.hist_hi[0], pk.hist_hi[1], w, pk.lambda, band_P, band_F, band_out);
+                       pk.hist_hi_dev, pk.hist_hi[0], pk.hist_hi[1], w, pk.lambda, band_P, band_F, band_out);
     hipLaunchKernelGGL(k_band_median, dim3(1), dim3(1024), 0, s, (const double*)band_P, (const int32_t*)band_F, n_bands,
                        median_out, flags_out);
     return hipGetLastError();

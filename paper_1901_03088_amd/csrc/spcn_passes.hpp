@@ -70,7 +70,17 @@ struct P1Params {
     float lambda;
     int32_t white_sum;
     float hist_hi[2];
+    const float* range;     // device [2] range that replaces hist_hi when non-NULL (see resolve_range)
 };
+
+// The parameters with the histogram range settled (every kernel calls this once at its start).
+__device__ inline P1Params p1_resolve(const P1Params& in) {
+    P1Params p = in;
+    p.hist_hi[0] = resolve_range(in.range, in.hist_hi[0]);
+    p.hist_hi[1] = resolve_range(in.range ? in.range + 1 : nullptr, in.hist_hi[1]);
+    p.range = nullptr;
+    return p;
+}
 
 // A fixed-point sum x (value + guard, in units of 2^-u bin) decides its bin only if it is not within
 // the guard band of an edge k * 2^u with k >= 1.  Edge 0 needs no decision: every value below

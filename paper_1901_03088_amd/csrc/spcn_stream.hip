@@ -118,7 +118,8 @@ hipError_t launch_stream_normalize(const uint8_t* host_src, uint8_t* host_out, i
         uint8_t* buf = resident + c * chunk;
         const bool first = c == 0;
         if ((e = launch_recolor(buf, px, w_src, w_tgt, scale_tgt, i0_out, pk, buf, hist, first ? p99_out : nullptr,
-                                first ? scale_out : nullptr, first ? flags_out : nullptr, dev, compute)) != hipSuccess)
+                                first ? scale_out : nullptr, first ? flags_out : nullptr, nullptr, dev,
+                                compute)) != hipSuccess)
             return e;
         if ((e = hipEventRecord(ev.out_ready[0], compute)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(copy_out, ev.out_ready[0], 0)) != hipSuccess) return e;
@@ -137,7 +138,8 @@ hipError_t launch_stream_normalize(const uint8_t* host_src, uint8_t* host_out, i
         if (out_used[s] && (e = hipStreamWaitEvent(compute, ev.out_free[s], 0)) != hipSuccess) return e;
         const bool first = c == 0;
         if ((e = launch_recolor(in[s], px, w_src, w_tgt, scale_tgt, i0_out, pk, out[s], hist, first ? p99_out : nullptr,
-                                first ? scale_out : nullptr, first ? flags_out : nullptr, dev, compute)) != hipSuccess)
+                                first ? scale_out : nullptr, first ? flags_out : nullptr, nullptr, dev,
+                                compute)) != hipSuccess)
             return e;
         if ((e = hipEventRecord(ev.in_free[s], compute)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev.out_ready[s], compute)) != hipSuccess) return e;

@@ -6,7 +6,10 @@
 //   k_pass2   every workgroup recomputes the percentile from the histogram in its prologue (no
 //             separate finalisation launch), then re-reads 3 B/px, recolours and writes 3 B/px;
 //   k_dens    optional FP32 density output (spcn_densities with h_out);
-//   k_finalize percentile + flags of a histogram for spcn_densities.
+//   k_finalize percentile + flags of a histogram for spcn_densities;
+//   k_u8_setup / k_range_check  histogram range kept on the device: the range of the call, and one
+//             automatic retry at twice a stain's range when its percentile lands in the open last
+//             bin (a second pass-1 launch that ends at once unless the check asked for it).
 //
 // Kernel variants (table replication, histogram columns, workgroups per CU) are selected at run
 // time through spcn_set_option; all variants compute identical results.
@@ -31,37 +34,89 @@ struct P1Args {
     P1Params pp;
     unsigned long long* hist;      // global [2][256]
     int64_t scatter, step;         // tile permutation of the grid-stride kernels (p1f_tiles)
+    const int32_t* gate;           // if non-NULL, the launch does nothing unless *gate != 0
 };
+
+__device__ __forceinline__ bool gated_off(const int32_t* gate) { return gate && *gate == 0; }
 
 // WAVES: minimum waves per SIMD the compiler must allow (register budget); 4 = one workgroup per CU,
 // 8 = two (the small-LDS variants).
 template <int COPIES, int COLS, int UNROLL, int WAVES>
 __global__ __launch_bounds__(P1_THREADS, WAVES) void k_pass1(const P1Args a) {
     __shared__ P1Lds<COPIES, COLS> S;
-    p1_setup(S, a.w, a.pp, true);
+    if (gated_off(a.gate)) return;
+    const P1Params pp = p1_resolve(a.pp);
+    p1_setup(S, a.w, pp, true);
     const int64_t n_units = a.n_px >> 2;
     const int64_t per = (n_units + gridDim.x - 1) / gridDim.x;
     const int64_t ubeg = min(n_units, (int64_t)blockIdx.x * per);
     const int cnt = (int)(min(n_units, ubeg + per) - ubeg);
-    p1_chunk<COPIES, COLS, UNROLL>(S, a.pp, chunk_rsrc(a.src, ubeg, cnt), a.src + 12 * ubeg, cnt, threadIdx.x,
+    p1_chunk<COPIES, COLS, UNROLL>(S, pp, chunk_rsrc(a.src, ubeg, cnt), a.src + 12 * ubeg, cnt, threadIdx.x,
                                       P1_THREADS);
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
-        p1_tail(S, a.pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
+        p1_tail(S, pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
     p1_merge(S, a.hist);
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const uint64_t* hist, double q, float hh0, float hh1,
-                                                  const float* w, float lambda, float* p99_out,
-                                                  int32_t* flags_out) {
+// Range and retry words of the single-image path, kept in the caller's workspace after the histogram.
+struct U8Ctl {
+    float range[2];     // histogram range of each stain for this call
+    int32_t retry;      // bit j: stain j's range was doubled and pass 1 must run again
+    int32_t pad;
+};
+
+// Zeroes the histogram and settles the call's range (device value if given, else the host one).
+__global__ __launch_bounds__(256) void k_u8_setup(uint64_t* hist, U8Ctl* ctl, const float* range_dev, float hh0,
+                                                  float hh1) {
+    for (int i = threadIdx.x; i < 2 * kHistBins; i += blockDim.x) hist[i] = 0;
+    if (threadIdx.x == 0) {
+        ctl->range[0] = resolve_range(range_dev, hh0);
+        ctl->range[1] = resolve_range(range_dev ? range_dev + 1 : nullptr, hh1);
+        ctl->retry = 0;
+    }
+}
+
+// Eq. 3's percentile of each stain from the histogram; a stain whose percentile lies in the open
+// last bin gets twice its range (up to 2^8) and the histogram is cleared for a second pass 1.
+__global__ __launch_bounds__(256) void k_range_check(uint64_t* hist, U8Ctl* ctl, double q) {
+    __shared__ FinalShared F;
+    __shared__ int bits;
+    const float hh[2] = {ctl->range[0], ctl->range[1]};
+    block_percentiles(hist, q, hh, F);
+    if (threadIdx.x == 0) {
+        int b = 0;
+        for (int j = 0; j < 2; ++j)
+            if (F.kstar[j] == kHistBins - 1 && hh[j] < 256.0f) b |= 1 << j;
+        bits = b;
+    }
+    __syncthreads();
+    if (bits) {
+        for (int i = threadIdx.x; i < 2 * kHistBins; i += blockDim.x) hist[i] = 0;
+        if (threadIdx.x == 0) {
+            for (int j = 0; j < 2; ++j)
+                if (bits & (1 << j)) ctl->range[j] = 2.0f * hh[j];
+            ctl->retry = bits;
+        }
+    }
+}
+
+__device__ __forceinline__ int retry_flag(const int32_t* retry, int j) {
+    return (retry && (*retry >> j) & 1) ? SPCN_FLAG_RANGE_RETRY : 0;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const uint64_t* hist, double q, const float* range, float hh0,
+                                                  float hh1, const int32_t* retry, const float* w, float lambda,
+                                                  float* p99_out, int32_t* flags_out, float* range_out) {
     __shared__ FinalShared F;
     __shared__ int basis_ok;
-    const float hh[2] = {hh0, hh1};
+    const float hh[2] = {resolve_range(range, hh0), resolve_range(range ? range + 1 : nullptr, hh1)};
     if (threadIdx.x == 0) { Basis64 B; derive_basis(w, lambda, B); basis_ok = B.ok; }
     block_percentiles(hist, q, hh, F);
     if (threadIdx.x < 2) {
         const int j = threadIdx.x;
         if (p99_out) p99_out[j] = (float)F.P[j];
-        if (flags_out) flags_out[j] = stain_flags(F, j, basis_ok);
+        if (flags_out) flags_out[j] = stain_flags(F, j, basis_ok) | retry_flag(retry, j);
+        if (range_out) range_out[j] = hh[j];
     }
 }
 
@@ -103,12 +158,15 @@ struct P2Args {
     float i0_out[3];
     float lambda;
     float hist_hi[2];
+    const float* range;        // device range [2] replacing hist_hi (resolve_range), or NULL
+    const int32_t* retry;      // retry bits of the call (SPCN_FLAG_RANGE_RETRY), or NULL
     double q;
     const uint64_t* hist;
     const float* p99_in;       // given source percentiles [2] (then hist is not read), or NULL
     float* p99_out;
     float* scale_out;
     int32_t* flags_out;
+    float* range_out;          // [2] range used, or NULL
 };
 
 // Prologue of every pass-2 workgroup: tables, percentile and recolouring constants (block 0 also
@@ -118,10 +176,11 @@ __device__ void p2_prologue(const P2Args& a, P2Lds<COPIES>& T, FinalShared& F, B
     if (threadIdx.x == 0) derive_basis(a.w_src, a.lambda, B);
     __syncthreads();
     p2_tables(T, B, a.i0);
+    const float hh[2] = {resolve_range(a.range, a.hist_hi[0]), resolve_range(a.range ? a.range + 1 : nullptr, a.hist_hi[1])};
     if (a.p99_in) {
         if (threadIdx.x < 2) F.P[threadIdx.x] = (double)a.p99_in[threadIdx.x];
     } else {
-        block_percentiles(a.hist, a.q, a.hist_hi, F);
+        block_percentiles(a.hist, a.q, hh, F);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -130,7 +189,7 @@ __device__ void p2_prologue(const P2Args& a, P2Lds<COPIES>& T, FinalShared& F, B
         for (int j = 0; j < 2; ++j) {
             // a given percentile that is not > 0 keeps the stain unscaled, like a bin-0 percentile
             fl[j] = a.p99_in ? ((F.P[j] > 0.0 ? 0 : SPCN_FLAG_BIN0) | (B.ok ? 0 : SPCN_FLAG_BASIS))
-                             : stain_flags(F, j, B.ok);
+                             : stain_flags(F, j, B.ok) | retry_flag(a.retry, j);
             s[j] = stain_scale((double)a.scale_tgt[j], F.P[j], fl[j]);
         }
         make_recolour(K, a.w_tgt, s, a.i0_out, B);
@@ -139,6 +198,7 @@ __device__ void p2_prologue(const P2Args& a, P2Lds<COPIES>& T, FinalShared& F, B
                 if (a.p99_out) a.p99_out[j] = (float)F.P[j];
                 if (a.scale_out) a.scale_out[j] = (float)s[j];
                 if (a.flags_out) a.flags_out[j] = fl[j];
+                if (a.range_out) a.range_out[j] = hh[j];
             }
         }
     }
@@ -183,14 +243,16 @@ __global__ __launch_bounds__(THREADS) void k_pass2g(const P2Args a) {
 template <bool WIDE, int THREADS, int UNROLL, int WAVES>
 __global__ __launch_bounds__(THREADS, WAVES) void k_pass1g(const P1Args a) {
     __shared__ P1FLds<WIDE> S;
-    p1f_setup(S, a.w, a.pp, true);
+    if (gated_off(a.gate)) return;
+    const P1Params pp = p1_resolve(a.pp);
+    p1f_setup(S, a.w, pp, true);
     const int64_t n_units = a.n_px >> 2;
     if (S.shift == 16)
-        p1f_tiles<WIDE, UNROLL, true>(S, a.pp, a.src, n_units, threadIdx.x, THREADS, a.scatter, a.step);
+        p1f_tiles<WIDE, UNROLL, true>(S, pp, a.src, n_units, threadIdx.x, THREADS, a.scatter, a.step);
     else
-        p1f_tiles<WIDE, UNROLL, false>(S, a.pp, a.src, n_units, threadIdx.x, THREADS, a.scatter, a.step);
+        p1f_tiles<WIDE, UNROLL, false>(S, pp, a.src, n_units, threadIdx.x, THREADS, a.scatter, a.step);
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        p1f_tail(S, a.pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
+        p1f_tail(S, pp, a.src + 12 * n_units, (int)(a.n_px - 4 * n_units));
     p1f_merge(S, a.hist);
 }
 
@@ -240,16 +302,22 @@ hipError_t run_pass2(const P2Args& a, int blocks_per_cu, const DevInfo& dev, hip
 
 // ----------------------------------------------------------------------------- launchers
 
-size_t u8_workspace_bytes() { return 2 * kHistBins * sizeof(uint64_t); }
+size_t u8_workspace_bytes() { return 2 * kHistBins * sizeof(uint64_t) + 256; }
+
+static U8Ctl* ctl_of(void* ws) {
+    return reinterpret_cast<U8Ctl*>(static_cast<uint8_t*>(ws) + 2 * kHistBins * sizeof(uint64_t));
+}
 
 static hipError_t launch_pass1(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, uint64_t* hist,
-                               const DevInfo& dev, hipStream_t s) {
+                               const float* range, const int32_t* gate, const DevInfo& dev, hipStream_t s) {
     P1Args a{};
     a.src = img; a.n_px = n_px; a.w = w;
     for (int c = 0; c < 3; ++c) a.pp.i0[c] = pk.i0[c];
     a.pp.lambda = pk.lambda; a.pp.white_sum = pk.white_sum;
     a.pp.hist_hi[0] = pk.hist_hi[0]; a.pp.hist_hi[1] = pk.hist_hi[1];
+    a.pp.range = range;
     a.hist = reinterpret_cast<unsigned long long*>(hist);
+    a.gate = gate;
     switch (option(SPCN_OPT_P1_VARIANT)) {
         case 0: return run_pass1<1, 64, 4, 4>(a, dev, s);
         case 1: return run_pass1<2, 64, 4, 4>(a, dev, s);
@@ -271,14 +339,25 @@ hipError_t launch_zero_hist(uint64_t* hist, hipStream_t s) {
 
 hipError_t launch_count(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, uint64_t* hist,
                         const DevInfo& dev, hipStream_t s) {
-    return launch_pass1(img, n_px, w, pk, hist, dev, s);
+    return launch_pass1(img, n_px, w, pk, hist, pk.hist_hi_dev, nullptr, dev, s);
+}
+
+// Histogram of the call with its range settled on the device: set-up, pass 1 and, with auto_range,
+// the range check and the gated second pass 1.  The range and retry words are in ctl.
+static hipError_t launch_hist_checked(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
+                                      uint64_t* hist, void* ctl_ws, const DevInfo& dev, hipStream_t s) {
+    U8Ctl* ctl = ctl_of(ctl_ws);
+    hipLaunchKernelGGL(k_u8_setup, dim3(1), dim3(256), 0, s, hist, ctl, pk.hist_hi_dev, pk.hist_hi[0], pk.hist_hi[1]);
+    hipError_t e = launch_pass1(img, n_px, w, pk, hist, ctl->range, nullptr, dev, s);
+    if (e != hipSuccess || !pk.auto_range) return e;
+    hipLaunchKernelGGL(k_range_check, dim3(1), dim3(256), 0, s, hist, ctl, pk.q64);
+    return launch_pass1(img, n_px, w, pk, hist, ctl->range, &ctl->retry, dev, s);
 }
 
 hipError_t launch_densities(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
-                            float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out,
-                            const DevInfo& dev, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, hist, 2 * kHistBins);
-    hipError_t e = launch_pass1(img, n_px, w, pk, hist, dev, s);
+                            float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out, float* range_out,
+                            void* ctl_ws, const DevInfo& dev, hipStream_t s) {
+    hipError_t e = launch_hist_checked(img, n_px, w, pk, hist, ctl_ws, dev, s);
     if (e != hipSuccess) return e;
     if (h_out) {
         int64_t want = (n_px + 255) / 256;
@@ -286,22 +365,26 @@ hipError_t launch_densities(const uint8_t* img, int64_t n_px, const float* w, co
         hipLaunchKernelGGL(k_dens, dim3((unsigned)(want < cap ? want : cap)), dim3(256), 0, s, img, n_px, w,
                            pk.i0[0], pk.i0[1], pk.i0[2], pk.lambda, h_out);
     }
-    if (p99_out || flags_out)
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, hist, pk.q64, pk.hist_hi[0], pk.hist_hi[1],
-                           w, pk.lambda, p99_out, flags_out);
+    if (p99_out || flags_out || range_out) {
+        U8Ctl* ctl = ctl_of(ctl_ws);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, hist, pk.q64, ctl->range, pk.hist_hi[0],
+                           pk.hist_hi[1], &ctl->retry, w, pk.lambda, p99_out, flags_out, range_out);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_recolor(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
-                          const float* scale_tgt, const float i0_out[3], const ParamsK& pk,
-                          uint8_t* out, const uint64_t* hist, float* p99_out, float* scale_out,
-                          int32_t* flags_out, const DevInfo& dev, hipStream_t s) {
+static P2Args p2_args(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
+                      const float* scale_tgt, const float i0_out[3], const ParamsK& pk, uint8_t* out) {
     P2Args b{};
     b.src = src; b.out = out; b.n_px = n_px; b.w_src = w_src; b.w_tgt = w_tgt; b.scale_tgt = scale_tgt;
     for (int c = 0; c < 3; ++c) { b.i0[c] = pk.i0[c]; b.i0_out[c] = i0_out[c]; }
     b.lambda = pk.lambda; b.hist_hi[0] = pk.hist_hi[0]; b.hist_hi[1] = pk.hist_hi[1];
-    b.q = pk.q64; b.hist = hist;
-    b.p99_out = p99_out; b.scale_out = scale_out; b.flags_out = flags_out;
+    b.range = pk.hist_hi_dev;
+    b.q = pk.q64;
+    return b;
+}
+
+static hipError_t run_recolor(const P2Args& b, const DevInfo& dev, hipStream_t s) {
     const int bpc = option(SPCN_OPT_P2_BLOCKS_PER_CU);
     switch (option(SPCN_OPT_P2_VARIANT)) {
         case 0: return run_pass2<1, 256>(b, bpc, dev, s);
@@ -311,37 +394,40 @@ hipError_t launch_recolor(const uint8_t* src, int64_t n_px, const float* w_src, 
         case 4: return run_pass2g<1, 512>(b, bpc, dev, s);
         default: return run_pass2g<16, 1024>(b, 1, dev, s);
     }
+}
+
+hipError_t launch_recolor(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
+                          const float* scale_tgt, const float i0_out[3], const ParamsK& pk,
+                          uint8_t* out, const uint64_t* hist, float* p99_out, float* scale_out,
+                          int32_t* flags_out, float* range_out, const DevInfo& dev, hipStream_t s) {
+    P2Args b = p2_args(src, n_px, w_src, w_tgt, scale_tgt, i0_out, pk, out);
+    b.hist = hist;
+    b.p99_out = p99_out; b.scale_out = scale_out; b.flags_out = flags_out; b.range_out = range_out;
+    return run_recolor(b, dev, s);
 }
 
 hipError_t launch_recolor_p99(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
                               const float* scale_tgt, const float i0_out[3], const ParamsK& pk, uint8_t* out,
                               const float* p99_in, float* scale_out, int32_t* flags_out, const DevInfo& dev,
                               hipStream_t s) {
-    P2Args b{};
-    b.src = src; b.out = out; b.n_px = n_px; b.w_src = w_src; b.w_tgt = w_tgt; b.scale_tgt = scale_tgt;
-    for (int c = 0; c < 3; ++c) { b.i0[c] = pk.i0[c]; b.i0_out[c] = i0_out[c]; }
-    b.lambda = pk.lambda; b.hist_hi[0] = pk.hist_hi[0]; b.hist_hi[1] = pk.hist_hi[1];
-    b.q = pk.q64; b.hist = nullptr; b.p99_in = p99_in;
-    b.p99_out = nullptr; b.scale_out = scale_out; b.flags_out = flags_out;
-    const int bpc = option(SPCN_OPT_P2_BLOCKS_PER_CU);
-    switch (option(SPCN_OPT_P2_VARIANT)) {
-        case 0: return run_pass2<1, 256>(b, bpc, dev, s);
-        case 1: return run_pass2<4, 256>(b, bpc, dev, s);
-        case 2: return run_pass2<16, 1024>(b, 1, dev, s);
-        case 3: return run_pass2g<1, 256>(b, bpc, dev, s);
-        case 4: return run_pass2g<1, 512>(b, bpc, dev, s);
-        default: return run_pass2g<16, 1024>(b, 1, dev, s);
-    }
+    P2Args b = p2_args(src, n_px, w_src, w_tgt, scale_tgt, i0_out, pk, out);
+    b.hist = nullptr; b.p99_in = p99_in;
+    b.scale_out = scale_out; b.flags_out = flags_out;
+    return run_recolor(b, dev, s);
 }
 
 hipError_t launch_normalize(const uint8_t* src, int64_t n_px, const float* w_src, const float* w_tgt,
                             const float* scale_tgt, const float i0_out[3], const ParamsK& pk,
-                            uint8_t* out, uint64_t* hist, float* p99_out, float* scale_out,
-                            int32_t* flags_out, const DevInfo& dev, hipStream_t s) {
-    hipError_t e = launch_densities(src, n_px, w_src, pk, nullptr, hist, nullptr, nullptr, dev, s);
+                            uint8_t* out, uint64_t* hist, void* ctl_ws, float* p99_out, float* scale_out,
+                            int32_t* flags_out, float* range_out, const DevInfo& dev, hipStream_t s) {
+    hipError_t e = launch_hist_checked(src, n_px, w_src, pk, hist, ctl_ws, dev, s);
     if (e != hipSuccess) return e;
-    return launch_recolor(src, n_px, w_src, w_tgt, scale_tgt, i0_out, pk, out, hist, p99_out, scale_out,
-                          flags_out, dev, s);
+    U8Ctl* ctl = ctl_of(ctl_ws);
+    P2Args b = p2_args(src, n_px, w_src, w_tgt, scale_tgt, i0_out, pk, out);
+    b.range = ctl->range; b.retry = &ctl->retry;
+    b.hist = hist;
+    b.p99_out = p99_out; b.scale_out = scale_out; b.flags_out = flags_out; b.range_out = range_out;
+    return run_recolor(b, dev, s);
 }
 
 }  // namespace spcn

@@ -46,6 +46,7 @@ def test_defaults_follow_the_paper(lib):
     q = lib.spcn_params()
     lib._L.spcn_default_params(C.byref(q))
     assert list(q.hist_hi) == [4.0, 4.0]
+    assert q.hist_hi_dev is None and q.auto_range == 1
 
 
 def test_status_strings(lib):
@@ -89,6 +90,8 @@ def test_normalize_rejects(lib, kw, frag):
     ("hist_hi", (3.0, 4.0), "power of two"),
     ("hist_hi", (4.0, 1024.0), "power of two"),
     ("i0", (255.0, 0.0, 255.0), "i0"),
+    ("auto_range", 2, "auto_range"),
+    ("hist_hi_dev", (1 << 24) + 2, "hist_hi_dev"),
 ])
 def test_params_rejected(lib, field, value, frag):
     p = lib.params()
@@ -104,9 +107,17 @@ def test_params_rejected(lib, field, value, frag):
 def test_densities_requires_histogram(lib):
     p = lib.params()
     st = lib._L.spcn_densities(C.c_void_p(1 << 20), 4, 4, C.c_void_p(1 << 24), C.byref(p), None, None, None, None,
-                               None, 0, None)
+                               None, None, 0, None)
     assert st == lib.SPCN_E_ARG
     assert "hist_out" in lib._L.spcn_last_error().decode()
+
+
+def test_densities_requires_workspace(lib):
+    """The range and retry words of the histogram live in the workspace."""
+    p = lib.params()
+    st = lib._L.spcn_densities(C.c_void_p(1 << 20), 4, 4, C.c_void_p(1 << 24), C.byref(p), None, C.c_void_p(1 << 24),
+                               None, None, None, None, 0, None)
+    assert st == lib.SPCN_E_WORKSPACE
 
 
 def test_workspace_sizes(lib):

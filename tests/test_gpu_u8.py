@@ -97,13 +97,13 @@ def test_histogram_exhaustive_rgb_cube(S, orc, case):
          "wide": synth.jitter_basis(np.random.default_rng(5), 20.0),
          "lam0": synth.make_image(1, 8, 8)["W"], "lam01_hi8": synth.make_image(2, 8, 8)["W"],
          "nomask_hi1": synth.make_image(3, 8, 8)["W"]}[case]
-    p = S.params()
+    p = S.params(auto_range=False)      # bins at the given range, whatever the percentile
     if case == "lam0":
-        p = S.params(lam=0.0)
+        p = S.params(lam=0.0, auto_range=False)
     if case == "lam01_hi8":
-        p = S.params(lam=0.1, hist_hi=(8.0, 2.0))
+        p = S.params(lam=0.1, hist_hi=(8.0, 2.0), auto_range=False)
     if case == "nomask_hi1":
-        p = S.params(white_sum=0, hist_hi=(1.0, 0.5))
+        p = S.params(white_sum=0, hist_hi=(1.0, 0.5), auto_range=False)
     img = torch.from_numpy(cube).to(DEV)
     w = S.as_basis(W, DEV)
     H, m = orc.densities_u8(cube, orc.f32(orc.basis(W)), list(p.i0), orc.f32(p.lambda_), p.white_sum)
@@ -181,14 +181,134 @@ def test_normalize_all_white(S, orc):
 
 
 def test_normalize_range_flag(S, orc):
-    """hist_hi far below the densities: the percentile lands in the overflow bin."""
+    """hist_hi far below the densities and no automatic retry: the percentile lands in the overflow
+    bin and the flag says so."""
     src = synth.make_image(5, 200, 200, device=DEV)
     tgt = synth.make_image(1, 200, 200, device=DEV)
-    p = S.params(hist_hi=(0.125, 0.125))
+    p = S.params(hist_hi=(0.125, 0.125), auto_range=False)
     out, st, sc = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], p)
     assert (st["flags"] & S.FLAG_RANGE).all(), st["flags"]
     o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, p)
     check_normalize("range", out, st, o_out, o_st, o_hist)
+
+
+def overflowing_ranges(orc, img, W, p):
+    """Per stain, the power of two just below the exact percentile (P in [r, 2r)): the histogram
+    percentile at r falls in the open last bin, at 2r inside the range."""
+    H, m = orc.densities_u8(np_img(img), orc.f32(orc.basis(W)), list(p.i0), orc.f32(p.lambda_), p.white_sum)
+    P = [orc.percentile_exact(H[j], m, orc.q_of(p.percentile))[0] for j in range(2)]
+    return [2.0 ** np.floor(np.log2(Pj)) for Pj in P]
+
+
+@pytest.mark.parametrize("stains", [(0,), (1,), (0, 1)])
+def test_normalize_range_retry(S, orc, stains):
+    """A range that the percentile overflows: pass 1 is repeated on the device at twice that
+    stain's range (the other stain keeps its range), and every result equals the oracle's at the
+    doubled range; the flags report the retry and no overflow."""
+    src = synth.make_image(5, 300, 200, device=DEV)
+    tgt = synth.make_image(1, 200, 200, device=DEV)
+    r = overflowing_ranges(orc, src["img"], src["W"], S.params())
+    given = [r[j] if j in stains else 4.0 * r[j] for j in range(2)]
+    used = [2.0 * r[j] if j in stains else 4.0 * r[j] for j in range(2)]
+    out, st, sc = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], S.params(hist_hi=given))
+    assert list(st["hist_hi"]) == used
+    o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, S.params(hist_hi=used))
+    st = dict(st, flags=st["flags"] & ~S.FLAG_RANGE_RETRY)
+    check_normalize("retry", out, st, o_out, o_st, o_hist)
+    retry = (run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], S.params(hist_hi=given))[1]["flags"]
+             & S.FLAG_RANGE_RETRY) != 0
+    assert list(retry) == [j in stains for j in range(2)]
+    # without the retry: the oracle at the given range, overflow flagged
+    out0, st0, _ = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], S.params(hist_hi=given, auto_range=False))
+    o_out0, o_st0, o_hist0 = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, S.params(hist_hi=given))
+    check_normalize("no retry", out0, st0, o_out0, o_st0, o_hist0)
+    assert [bool(f & S.FLAG_RANGE) for f in st0["flags"]] == [j in stains for j in range(2)]
+
+
+def test_densities_range_retry_and_recolor(S, orc):
+    """spcn_densities repeats pass 1 the same way and reports the range; spcn_recolor from that
+    histogram and range equals spcn_normalize byte for byte."""
+    src = synth.make_image(9, 256, 320, device=DEV)
+    tgt = synth.make_image(1, 200, 200, device=DEV)
+    r = overflowing_ranges(orc, src["img"], src["W"], S.params())
+    p = S.params(hist_hi=(r[0], 4.0 * r[1]))
+    w = S.as_basis(src["W"], DEV)
+    hh = torch.empty(2, dtype=torch.float32, device=DEV)
+    _, hist, p99, flags = S.spcn_densities(src["img"], w, p, want_h=False, hist_hi_out=hh)
+    torch.cuda.synchronize()
+    assert hh.cpu().tolist() == [2.0 * r[0], 4.0 * r[1]]
+    H, m, ohist, P, fl = oracle_densities(orc, src["img"], src["W"], S.params(hist_hi=hh.cpu().tolist()))
+    assert np.array_equal(hist.cpu().numpy().astype(np.uint64), ohist)
+    assert np.array_equal(p99.cpu().numpy(), P.astype(np.float32))
+    assert list(flags.cpu().numpy()) == [fl[0] | S.FLAG_RANGE_RETRY, fl[1]]
+    wt = S.as_basis(tgt["W"], DEV)
+    _, _, sc, _ = S.spcn_densities(tgt["img"], wt, S.params(), want_h=False)
+    ref, _ = S.spcn_normalize(src["img"], w, wt, sc, p)
+    out, st = S.spcn_recolor(src["img"], w, wt, sc, hist, S.params(hist_hi_dev=hh))
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    assert st["hist_hi"].cpu().tolist() == hh.cpu().tolist()
+
+
+def test_range_from_basis_sample(S, orc):
+    """spcn_estimate_basis derives the range from its sample percentile (the power of two at or
+    above twice it, within [2^-4, 2^6]); a normalisation that reads it from the device equals the
+    oracle's at that range, with no overflow."""
+    import math
+    src = synth.make_image(0, 1024, 1024, device=DEV)
+    tgt = synth.make_image(1, 256, 256, device=DEV)
+    hh = torch.empty(2, dtype=torch.float32, device=DEV)
+    w, sp, _ = S.spcn_estimate_basis(src["img"], 20000, seed=3, p=S.params(), hist_hi_out=hh)
+    torch.cuda.synchronize()
+    for j in range(2):
+        v = 2.0 * float(sp[j])
+        m_, e_ = math.frexp(v)
+        want = 0.0625 if v <= 0.0625 else 64.0 if v >= 64.0 else (v if m_ == 0.5 else 2.0 ** e_)
+        assert float(hh[j]) == want, (j, float(hh[j]), want)
+    p = S.params(hist_hi_dev=hh)
+    wt = S.as_basis(tgt["W"], DEV)
+    _, _, sc, _ = S.spcn_densities(tgt["img"], wt, S.params(), want_h=False)
+    out, st = S.spcn_normalize(src["img"], w, wt, sc, p)
+    torch.cuda.synchronize()
+    stn = {k: v.cpu().numpy() for k, v in st.items()}
+    assert stn["hist_hi"].tolist() == hh.cpu().tolist()
+    assert not (stn["flags"] & (S.FLAG_RANGE | S.FLAG_RANGE_RETRY)).any()
+    Wf = w.cpu().numpy().astype(np.float64)
+    o_out, o_st, o_hist = orc.normalize_u8(np_img(src["img"]), Wf, orc.f32(orc.basis(tgt["W"])),
+                                           sc.cpu().numpy().astype(np.float64), lam=orc.f32(0.01),
+                                           hist_hi=hh.cpu().numpy().astype(np.float64).tolist())
+    check_normalize("range from sample", out, stn, o_out, o_st, o_hist)
+
+
+def test_normalize_graph_replay_with_retry(S):
+    """spcn_normalize with a range that triggers the device-side retry, captured in a graph and
+    replayed with eager work in between: every replay equals the eager result."""
+    src = synth.make_image(5, 300, 200, device=DEV)
+    tgt = synth.make_image(1, 200, 200, device=DEV)
+    wt = S.as_basis(tgt["W"], DEV)
+    _, _, sc, _ = S.spcn_densities(tgt["img"], wt, S.params(), want_h=False)
+    ws = S.as_basis(src["W"], DEV)
+    p = S.params(hist_hi=(0.5, 0.5))
+    ref, st_ref = S.spcn_normalize(src["img"], ws, wt, sc, p)
+    torch.cuda.synchronize()
+    assert (st_ref["flags"].cpu() & S.FLAG_RANGE_RETRY).any()
+    out = torch.empty_like(src["img"])
+    wsp = S.workspace(S.workspace_size(S.OP_NORMALIZE), DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        S.spcn_normalize(src["img"], ws, wt, sc, p, out=out, stats=False, ws=wsp)
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.spcn_normalize(src["img"], ws, wt, sc, p, out=out, stats=False, ws=wsp)
+    for k in range(3):
+        out.zero_()
+        S.spcn_normalize(tgt["img"], wt, wt, sc, S.params(), out=torch.empty_like(tgt["img"]))   # eager work between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
 
 
 def test_normalize_bin0_flag(S, orc):
