@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-OK, NO_TISSUE, RANGE, BIN0 = 0, 1, 2, 4
+OK, NO_TISSUE, RANGE, BIN0, RANGE_RETRY = 0, 1, 2, 4, 256
 
 _d = C.POINTER(C.c_double)
 _u8 = C.POINTER(C.c_uint8)
@@ -47,6 +47,8 @@ def lib():
         L.orc_histogram.argtypes = [_d, _u8, C.c_int64, _d, C.c_int, _u64]
         L.orc_percentile_hist.restype = C.c_int
         L.orc_percentile_hist.argtypes = [_u64, C.c_int, C.c_double, C.c_double, _d, _i]
+        L.orc_settle_range.restype = C.c_int
+        L.orc_settle_range.argtypes = [_d, _u8, C.c_int64, _d, C.c_int, C.c_double, _d]
         L.orc_percentile_exact.restype = C.c_int
         L.orc_percentile_exact.argtypes = [_d, _u8, C.c_int64, C.c_double, _d, _i64]
         L.orc_normalize_u8.restype = C.c_int
@@ -165,6 +167,17 @@ def percentile_hist(counts, hist_hi, q):
     return P.value, fl, k.value
 
 
+def settle_range(H, mask, hist_hi, percentile=99.0, bins=256):
+    """Ranges after the one automatic retry (a stain whose percentile lands in the last bin, at a
+    range below 256, is counted again at twice its range).  Returns (ranges, retried-bits)."""
+    H = np.ascontiguousarray(H, dtype=np.float64); n = H.shape[1]
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    hh = _vec(hist_hi, 2); out = np.zeros(2)
+    bits = lib().orc_settle_range(_p(H, _d), None if m is None else _p(m, _u8), n, _p(hh, _d), int(bins),
+                                  q_of(percentile), _p(out, _d))
+    return [float(out[0]), float(out[1])], int(bits)
+
+
 def percentile_exact(h, mask, q):
     h = np.ascontiguousarray(h, dtype=np.float64)
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
@@ -182,17 +195,24 @@ def q_of(percentile) -> float:
 # ------------------------------------------------------------------ Eqs. (3)-(4)
 
 def normalize_u8(src, W_src, W_tgt, scale_tgt, i0_in=(255, 255, 255), i0_out=(255, 255, 255), lam=0.01,
-                 white_sum=660, percentile=99.0, hist_hi=(4.0, 4.0), bins=256):
-    """Returns (out uint8 same shape, stats dict, hist (2, bins) uint64)."""
+                 white_sum=660, percentile=99.0, hist_hi=(4.0, 4.0), bins=256, auto_range=False):
+    """Returns (out uint8 same shape, stats dict, hist (2, bins) uint64).  With auto_range the
+    histogram is built over the ranges settle_range returns (stats "hist_hi", flags with
+    RANGE_RETRY for a doubled stain)."""
     a = _img(src); n = a.shape[0]
+    bits = 0
+    if auto_range:
+        H, m = densities_u8(src, W_src, i0_in, lam, white_sum)
+        hist_hi, bits = settle_range(H, m, hist_hi, percentile, bins)
     out = np.empty_like(a); st = np.zeros(8); hist = np.zeros((2, bins), dtype=np.uint64)
     Ws, Wt = basis(W_src), basis(W_tgt)
     sc, ii, io, hh = _vec(scale_tgt, 2), _vec(i0_in, 3), _vec(i0_out, 3), _vec(hist_hi, 2)
     fl = lib().orc_normalize_u8(_p(a, _u8), n, _p(Ws, _d), _p(Wt, _d), _p(sc, _d), _p(ii, _d), _p(io, _d),
                                 float(lam), int(white_sum), q_of(percentile), _p(hh, _d), int(bins),
                                 _p(out, _u8), _p(st, _d), _p(hist, _u64))
-    stats = {"P": st[0:2].copy(), "scale": st[2:4].copy(), "flags": st[4:6].astype(int), "n_tissue": int(st[6]),
-             "status": fl}
+    flags = st[4:6].astype(int) | np.array([RANGE_RETRY if bits >> j & 1 else 0 for j in range(2)])
+    stats = {"P": st[0:2].copy(), "scale": st[2:4].copy(), "flags": flags, "n_tissue": int(st[6]),
+             "status": fl, "hist_hi": list(hh)}
     return out.reshape(np.asarray(src).shape), stats, hist
 
 

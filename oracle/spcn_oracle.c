@@ -156,6 +156,27 @@ int orc_percentile_hist(const uint64_t* counts, int bins, double hist_hi, double
     return flags;
 }
 
+/* One retry of the histogram range: count at hist_hi, and double the range of each stain whose
+ * percentile lands in the last bin (while that range is below 256). */
+int orc_settle_range(const double* H, const uint8_t* mask, int64_t n_px, const double hist_hi[2], int bins,
+                     double q, double range_out[2]) {
+    uint64_t* hist = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (size_t)bins);
+    orc_histogram(H, mask, n_px, hist_hi, bins, hist);
+    int bits = 0;
+    for (int j = 0; j < 2; ++j) {
+        double P;
+        int k;
+        orc_percentile_hist(hist + j * bins, bins, hist_hi[j], q, &P, &k);
+        range_out[j] = hist_hi[j];
+        if (k == bins - 1 && hist_hi[j] < 256.0) {
+            range_out[j] = 2.0 * hist_hi[j];
+            bits |= 1 << j;
+        }
+    }
+    free(hist);
+    return bits;
+}
+
 static int cmp_double(const void* a, const void* b) {
     double x = *(const double*)a, y = *(const double*)b;
     return (x > y) - (x < y);

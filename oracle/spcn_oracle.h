@@ -34,6 +34,7 @@ extern "C" {
 #define ORC_NO_TISSUE  1   /* no pixel passed the non-white mask: scale := 1                      */
 #define ORC_RANGE      2   /* the percentile fell into the last (overflow) histogram bin           */
 #define ORC_BIN0       4   /* the percentile fell into bin 0: the stain is absent, scale := 1      */
+#define ORC_RANGE_RETRY 256 /* the range was doubled once because the percentile fell in the last bin */
 
 /* Eq. (1) for one 8-bit channel; intensity 0 is read as 1 and OD is clamped at 0. */
 double orc_od_u8(double i0, int intensity);
@@ -58,6 +59,13 @@ void orc_histogram(const double* H, const uint8_t* mask, int64_t n_px, const dou
 
 /* Percentile from one stain's histogram (interpolated inside the crossing bin).  Returns flags. */
 int orc_percentile_hist(const uint64_t* counts, int bins, double hist_hi, double q, double* P, int* kstar);
+
+/* Histogram range of each stain after the one automatic retry (the paper fixes no range for the
+ * Eq. 3 percentile; the reading used: a stain whose percentile falls in the open last bin at
+ * hist_hi[j] < 256 is counted again at 2 hist_hi[j], once).  range_out gets the settled ranges;
+ * returns bit j set for each doubled stain. */
+int orc_settle_range(const double* H, const uint8_t* mask, int64_t n_px, const double hist_hi[2], int bins,
+                     double q, double range_out[2]);
 
 /* Exact nearest-rank percentile of h over tissue pixels: the k-th smallest, k = max(1, ceil(q n)).
  * *idx = smallest linear index whose value equals the result.  Returns ORC_NO_TISSUE if n = 0. */

@@ -35,14 +35,19 @@ def gpu_densities(S, img, W, p):
 
 
 def oracle_densities(orc, img, W, p):
+    """The oracle's densities, histogram, percentile and flags; with p.auto_range the histogram is
+    over the oracle's settled ranges (one doubling of a stain whose percentile lands in the last bin)."""
     i0 = list(p.i0)
     H, m = orc.densities_u8(np_img(img), orc.f32(orc.basis(W)), i0, orc.f32(p.lambda_), p.white_sum)
-    hist = orc.histogram(H, m, list(p.hist_hi), 256)
+    hh, bits = list(p.hist_hi), 0
+    if p.auto_range:
+        hh, bits = orc.settle_range(H, m, hh, p.percentile)
+    hist = orc.histogram(H, m, hh, 256)
     P = []
     fl = []
     for j in range(2):
-        Pj, f, _ = orc.percentile_hist(hist[j], float(p.hist_hi[j]), orc.q_of(p.percentile))
-        P.append(Pj); fl.append(f)
+        Pj, f, _ = orc.percentile_hist(hist[j], float(hh[j]), orc.q_of(p.percentile))
+        P.append(Pj); fl.append(f | (orc.RANGE_RETRY if bits >> j & 1 else 0))
     return H, m, hist, np.array(P), np.array(fl)
 
 
@@ -136,7 +141,8 @@ def run_normalize(S, src_img, Ws, tgt_img, Wt, p, i0_out=None):
 def oracle_normalize(orc, src, Ws, Wt, scale_tgt, p, i0_out=None):
     return orc.normalize_u8(np_img(src), orc.f32(orc.basis(Ws)), orc.f32(orc.basis(Wt)),
                             scale_tgt.astype(np.float64), list(p.i0), list(i0_out or p.i0),
-                            orc.f32(p.lambda_), p.white_sum, p.percentile, list(p.hist_hi), 256)
+                            orc.f32(p.lambda_), p.white_sum, p.percentile, list(p.hist_hi), 256,
+                            auto_range=bool(p.auto_range))
 
 
 def check_normalize(tag, out, st, o_out, o_st, o_hist):
@@ -212,15 +218,15 @@ def test_normalize_range_retry(S, orc, stains):
     used = [2.0 * r[j] if j in stains else 4.0 * r[j] for j in range(2)]
     out, st, sc = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], S.params(hist_hi=given))
     assert list(st["hist_hi"]) == used
-    o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, S.params(hist_hi=used))
-    st = dict(st, flags=st["flags"] & ~S.FLAG_RANGE_RETRY)
+    # the oracle settles the same range from the given one and reports the same retry bits
+    o_out, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, S.params(hist_hi=given))
+    assert o_st["hist_hi"] == used
     check_normalize("retry", out, st, o_out, o_st, o_hist)
-    retry = (run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], S.params(hist_hi=given))[1]["flags"]
-             & S.FLAG_RANGE_RETRY) != 0
-    assert list(retry) == [j in stains for j in range(2)]
+    assert [bool(f & S.FLAG_RANGE_RETRY) for f in st["flags"]] == [j in stains for j in range(2)]
     # without the retry: the oracle at the given range, overflow flagged
-    out0, st0, _ = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], S.params(hist_hi=given, auto_range=False))
-    o_out0, o_st0, o_hist0 = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc, S.params(hist_hi=given))
+    p0 = S.params(hist_hi=given, auto_range=False)
+    out0, st0, sc0 = run_normalize(S, src["img"], src["W"], tgt["img"], tgt["W"], p0)
+    o_out0, o_st0, o_hist0 = oracle_normalize(orc, src["img"], src["W"], tgt["W"], sc0, p0)
     check_normalize("no retry", out0, st0, o_out0, o_st0, o_hist0)
     assert [bool(f & S.FLAG_RANGE) for f in st0["flags"]] == [j in stains for j in range(2)]
 

@@ -87,6 +87,51 @@ def test_hist_percentile_flags(orc):
     assert fl == orc.RANGE and k == 255
 
 
+@pytest.mark.parametrize("hh", [(4.0, 2.0), (0.25, 8.0), (256.0, 0.5), (1.0, 1.0)])
+def test_settle_range_counts_below_last_edge(orc, hh):
+    """The range retry, pinned by counting: stain j's histogram percentile lies in the last bin
+    exactly when fewer than q n tissue values lie below the last bin's lower edge 255 hh/256; then
+    (and only below 256) its range doubles, once, and the other stain keeps its range."""
+    rng = np.random.default_rng(17)
+    q = float(np.float32(99.0)) / 100.0
+    for trial in range(40):
+        n = int(rng.integers(1, 400))
+        scale = rng.choice([0.1, 1.0, 3.0, 30.0, 600.0], size=2)
+        H = np.abs(rng.normal(0, 1, (2, n))) * scale[:, None]
+        mask = (rng.uniform(size=n) < 0.9).astype(np.uint8)
+        if mask.sum() == 0:
+            mask[0] = 1
+        ranges, bits = orc.settle_range(H, mask, hh)
+        t = mask.astype(bool)
+        for j in range(2):
+            below = int((H[j, t] < 255.0 * hh[j] / 256.0).sum())
+            overflow = below < q * int(t.sum())
+            want = overflow and hh[j] < 256.0
+            assert bool(bits >> j & 1) == want, (trial, j)
+            assert ranges[j] == (2.0 * hh[j] if want else hh[j])
+    # no tissue: nothing to retry
+    ranges, bits = orc.settle_range(np.ones((2, 5)), np.zeros(5, dtype=np.uint8), hh)
+    assert bits == 0 and ranges == list(hh)
+
+
+def test_normalize_auto_range_equals_doubled_range(orc):
+    """normalize with the retry equals normalize at the settled ranges, with RANGE_RETRY added."""
+    d = synth.make_image(5, 60, 50)
+    src = d["img"].numpy()
+    W = d["W"]
+    sc = np.array([0.9, 1.2])
+    H, m = orc.densities_u8(src, orc.f32(orc.basis(W)))
+    top = [float(np.quantile(H[j, m.astype(bool)], 0.995)) for j in range(2)]
+    given = [2.0 ** math.floor(math.log2(top[0])), 4.0 * 2.0 ** math.ceil(math.log2(top[1]))]
+    out_a, st_a, hist_a = orc.normalize_u8(src, orc.f32(orc.basis(W)), orc.f32(orc.basis(W)), sc, hist_hi=given,
+                                           auto_range=True)
+    assert st_a["hist_hi"] == [2.0 * given[0], given[1]]
+    out_b, st_b, hist_b = orc.normalize_u8(src, orc.f32(orc.basis(W)), orc.f32(orc.basis(W)), sc,
+                                           hist_hi=st_a["hist_hi"])
+    assert np.array_equal(out_a, out_b) and np.array_equal(hist_a, hist_b)
+    assert list(st_a["flags"]) == [st_b["flags"][0] | orc.RANGE_RETRY, st_b["flags"][1]]
+
+
 # ------------------------------------------------------------------ Eqs. (3)-(4)
 
 def noise_free_image(W, h, w, seed):
