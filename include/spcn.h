@@ -150,6 +150,20 @@ spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, co
                            const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
                            void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* spcn_normalize for callers that cannot allocate device memory (code under stream or graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the histogram and range words live in
+ * a static device array of the library (8192 bytes per GPU, held until the process ends) instead
+ * of a caller workspace.  The call itself allocates and frees nothing; the array's device address
+ * is looked up once per device on the first call.  Arguments, results and errors as for
+ * spcn_normalize (the needed scratch is fixed at 4352 bytes; a build needing more than the array
+ * holds returns SPCN_E_WORKSPACE).  Every call on one GPU shares that GPU's array and leaves its
+ * last contents there: the call clears what must start at zero, but two calls whose work overlaps
+ * on one GPU (other streams, or host threads) race on it and must be serialised by the caller. */
+spcn_status spcn_normalize_noalloc(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                                   const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                                   const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                                   hipStream_t stream);
+
 /* Pass 2 of spcn_normalize on its own: percentile of Eq. 3 from a given non-white histogram (from
  * spcn_densities on this image, or the element-wise sum of the histograms of its shards), scaling,
  * recolouring and Eq. 4.  Arguments as for spcn_normalize; hist is an input here and st->hist is

@@ -57,6 +57,8 @@ _SIGS = {
     "spcn_densities": (C.c_int, [_vp, _i64, _i64, _vp, _P, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, C.POINTER(spcn_norm_stats), _vp,
                                  _sz, _vp]),
+    "spcn_normalize_noalloc": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp,
+                                         C.POINTER(spcn_norm_stats), _vp]),
     "spcn_recolor": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, C.POINTER(spcn_norm_stats),
                                _vp]),
     "spcn_estimate_basis": (C.c_int, [_vp, _i64, _i64, _P, _f, _i64, _u64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -239,6 +241,29 @@ def spcn_normalize(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, 
                              _ptr(out), C.byref(st) if st is not None else None, wsp, wsn, _stream()),
            "spcn_normalize")
     return out, res
+
+
+def spcn_normalize_noalloc(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
+                           out: torch.Tensor, p: spcn_params | None = None, i0_out=None, stats: dict | None = None):
+    """spcn_normalize without a workspace (the library's static per-GPU scratch): out and the
+    optional stats tensors (keys hist, p99_src, scale, flags, hist_hi; any may be missing) are
+    the caller's, so the call allocates nothing."""
+    _dev(src, torch.uint8, "src")
+    _dev(out, torch.uint8, "out")
+    for t, nm in ((w_src, "w_src"), (w_tgt, "w_tgt"), (scale_tgt, "scale_tgt")):
+        _dev(t, torch.float32, nm)
+    p = p or params()
+    st = None
+    if stats is not None:
+        ptr = {k: (v.data_ptr() if v is not None else None) for k, v in stats.items()}
+        st = spcn_norm_stats(ptr.get("hist"), ptr.get("p99_src"), ptr.get("scale"), ptr.get("flags"),
+                             ptr.get("hist_hi"))
+    io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
+    _check(_L.spcn_normalize_noalloc(_ptr(src), int(src.shape[0]), int(src.shape[1]), _ptr(w_src), _ptr(w_tgt),
+                                     _ptr(scale_tgt), io, C.byref(p), _ptr(out),
+                                     C.byref(st) if st is not None else None, _stream()),
+           "spcn_normalize_noalloc")
+    return out
 
 
 def spcn_recolor(src: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,

@@ -4,6 +4,7 @@
 
 #include <atomic>
 #include <math.h>
+#include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -189,11 +190,10 @@ spcn_status spcn_densities(const uint8_t* img, int64_t height, int64_t width, co
 
 }  // extern "C"
 
-// spcn_normalize's checks and launches, with the workspace the caller or the library provides.
-static spcn_status normalize_into(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
-                                  const float* w_tgt, const float* scale_tgt, const float* i0_out,
-                                  const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
-                                  void* ws, size_t ws_bytes, hipStream_t stream) {
+// spcn_normalize's host-side argument checks (everything but the workspace).
+static spcn_status check_normalize(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                                   const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                                   const spcn_params* p, uint8_t* out) {
     SPCN_CHECK(check_image(src, height, width, "src"));
     SPCN_CHECK(check_image(out, height, width, "out"));
     SPCN_CHECK(check_params(p, true));
@@ -201,10 +201,22 @@ static spcn_status normalize_into(const uint8_t* src, int64_t height, int64_t wi
     const int64_t n = height * width;
     if ((const void*)src < (const void*)(out + 3 * n) && (const void*)out < (const void*)(src + 3 * n))
         return fail(SPCN_E_ARG, "out must not overlap src");
+    for (int c = 0; c < 3; ++c) {
+        const float io = i0_out ? i0_out[c] : p->i0[c];
+        if (!finite_pos(io)) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io);
+    }
+    return SPCN_OK;
+}
+
+// spcn_normalize's checks and launches, with the workspace the caller or the library provides.
+static spcn_status normalize_into(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                                  const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                                  const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                                  void* ws, size_t ws_bytes, hipStream_t stream) {
+    SPCN_CHECK(check_normalize(src, height, width, w_src, w_tgt, scale_tgt, i0_out, p, out));
+    const int64_t n = height * width;
     float io[3];
     for (int c = 0; c < 3; ++c) io[c] = i0_out ? i0_out[c] : p->i0[c];
-    for (int c = 0; c < 3; ++c)
-        if (!finite_pos(io[c])) return fail(SPCN_E_ARG, "i0_out[%d] = %g must be finite and > 0", c, (double)io[c]);
     SPCN_CHECK(check_ws(ws, ws_bytes, u8_workspace_bytes()));
     uint64_t* hist = st && st->hist ? st->hist : static_cast<uint64_t*>(ws);
     DevInfo dev;
@@ -223,6 +235,49 @@ spcn_status spcn_normalize(const uint8_t* src, int64_t height, int64_t width, co
                            const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
                            void* ws, size_t ws_bytes, hipStream_t stream) {
     return normalize_into(src, height, width, w_src, w_tgt, scale_tgt, i0_out, p, out, st, ws, ws_bytes, stream);
+}
+
+// Scratch of spcn_normalize_noalloc: the histogram and range words of one normalisation (the same
+// layout as the caller workspace of spcn_normalize).  Every device holds its own copy for the life
+// of the process; its device address is looked up once per device (the array's name is only a
+// host-side stand-in) and kept in g_scratch.
+constexpr size_t kStaticScratchBytes = 8192;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+static std::atomic<void*> g_scratch[64];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (dev is the current device).
+static spcn_status scratch_address(int dev, void** out) {
+    void* ptr = g_scratch[dev].load(std::memory_order_acquire);
+    if (!ptr) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ptr = g_scratch[dev].load(std::memory_order_relaxed);
+        if (!ptr) {
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            if (!ptr) return fail(SPCN_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+            g_scratch[dev].store(ptr, std::memory_order_release);
+        }
+    }
+    *out = ptr;
+    return SPCN_OK;
+}
+
+spcn_status spcn_normalize_noalloc(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
+                                   const float* w_tgt, const float* scale_tgt, const float* i0_out,
+                                   const spcn_params* p, uint8_t* out, const spcn_norm_stats* st,
+                                   hipStream_t stream) {
+    SPCN_CHECK(check_normalize(src, height, width, w_src, w_tgt, scale_tgt, i0_out, p, out));
+    const size_t need = u8_workspace_bytes();
+    if (need > kStaticScratchBytes)
+        return fail(SPCN_E_WORKSPACE, "spcn_normalize_noalloc needs %zu bytes of scratch, above its static %zu",
+                    need, kStaticScratchBytes);
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    void* ws = nullptr;
+    SPCN_CHECK(scratch_address(dev.id, &ws));
+    return normalize_into(src, height, width, w_src, w_tgt, scale_tgt, i0_out, p, out, st, ws, kStaticScratchBytes,
+                          stream);
 }
 
 spcn_status spcn_recolor(const uint8_t* src, int64_t height, int64_t width, const float* w_src,

@@ -82,6 +82,25 @@ def test_normalize_rejects(lib, kw, frag):
     assert frag in lib._L.spcn_last_error().decode()
 
 
+@pytest.mark.parametrize("kw,frag", [
+    (dict(src=None), "src is NULL"),
+    (dict(ws=None), "non-NULL"),
+    (dict(out=C.c_void_p((1 << 20) + 96)), "overlap"),
+    (dict(h=1 << 20, w=1 << 20), "2^36"),
+])
+def test_normalize_noalloc_rejects(lib, kw, frag):
+    """The allocation-free entry point checks its arguments on the host, before it touches the
+    device (no GPU here: a check that reached the device would report a HIP error instead)."""
+    p = kw.pop("p", lib.params())
+    args = dict(src=C.c_void_p(1 << 20), h=8, w=8, ws=C.c_void_p(1 << 24), wt=C.c_void_p(1 << 24),
+                sc=C.c_void_p(1 << 24), out=C.c_void_p(2 << 20))
+    args.update(kw)
+    st = lib._L.spcn_normalize_noalloc(args["src"], args["h"], args["w"], args["ws"], args["wt"], args["sc"], None,
+                                       C.byref(p), args["out"], None, None)
+    assert st == lib.SPCN_E_ARG
+    assert frag in lib._L.spcn_last_error().decode()
+
+
 @pytest.mark.parametrize("field,value,frag", [
     ("lambda_", -0.1, "lambda"),
     ("lambda_", float("nan"), "lambda"),
