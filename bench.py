@@ -122,7 +122,7 @@ def timed(fn, steps, warmup, stream):
     return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
 
 
-def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True):
+def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True, tune=True):
     """512 uneven tiles (sides 256..2048 step 64), per-tile basis fit (4096 samples, 50 rounds,
     lambda 0.1) and normalisation to one target, captured in one hipGraph and replayed; against a
     per-tile loop of the plain single-image path (same work, same results) unless loop is False."""
@@ -148,7 +148,8 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True):
         return W
     from paper_1901_03088_amd import autotune
     W_fit = run()
-    tuned = autotune.tune_batched(table, n_tiles, total, W_fit, wt, sc, outs, p_t)
+    tuned = (autotune.tune_batched(table, n_tiles, total, W_fit, wt, sc, outs, p_t) if tune else
+             {"options": {"batch_chunk_log2": S.get_option(S.OPT_BATCH_CHUNK)}})
     run()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -245,6 +246,9 @@ def main() -> int:
     ap.add_argument("--only", choices=["batched", "fwdbwd"], default=None,
                     help="run one extension workload alone (the batched graph without the per-tile loop, or the "
                          "differentiable batch), for profiling; no slide step")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the library's default kernel variants (for profiling runs, whose traces should "
+                         "hold only the timed kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg on float32), "
                          "whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM byte counters")
@@ -263,7 +267,7 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.only:
         if args.only == "batched":
-            r = bench_batched(dev, S, synth, args.steps, args.warmup, loop=False)
+            r = bench_batched(dev, S, synth, args.steps, args.warmup, loop=False, tune=args.autotune)
         else:
             r = bench_fwdbwd(dev, S, synth, args.steps, args.warmup)
         log(f"[bench] {args.only} {r}")
@@ -300,7 +304,9 @@ def main() -> int:
     # tune on the basis the step fits (the bin distribution, hence LDS contention, depends on it)
     S.spcn_estimate_basis(img, n_samples, seed=2024, p=S.params(), lambda_nmf=0.1, n_iter=50, want_p99=False,
                           w_out=w_fit, ws=ws_fit, hist_hi_out=hh_fit)
-    tuned = autotune.tune_image(img, w_fit, w_tgt, scale_tgt, p_fit)
+    tuned = (autotune.tune_image(img, w_fit, w_tgt, scale_tgt, p_fit) if args.autotune else
+             {"options": {"p1_variant": S.get_option(S.OPT_P1_VARIANT), "p2_variant": S.get_option(S.OPT_P2_VARIANT),
+                          "p2_blocks_per_cu": S.get_option(S.OPT_P2_BLOCKS_PER_CU)}})
     log(f"[bench] autotune chose {tuned['options']}")
 
     def step(ev=None):
@@ -435,7 +441,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         extras = {}
         try:
-            extras["batched"] = bench_batched(dev, S, synth, args.steps, args.warmup)
+            extras["batched"] = bench_batched(dev, S, synth, args.steps, args.warmup, tune=args.autotune)
             log(f"[bench] batched {extras['batched']}")
         except Exception as e:   # report, never hide, a failing extra
             extras["batched"] = {"error": repr(e)}
