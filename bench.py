@@ -172,7 +172,7 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True, tune=Tru
     wsn1 = S.workspace(S.workspace_size(S.OP_NORMALIZE), dev)
     w1 = torch.empty((n_tiles, 6), dtype=torch.float32, device=dev)
     hh1 = torch.empty((n_tiles, 2), dtype=torch.float32, device=dev)
-    p1 = [S.params(hist_hi_dev=hh1[t], auto_range=False) for t in range(n_tiles)]
+    p1 = [S.params(hist_hi_dev=hh1[t]) for t in range(n_tiles)]
 
     def per_tile():
         for t in range(n_tiles):

@@ -55,8 +55,8 @@ typedef enum {
 #define SPCN_FLAG_BIN0      4   /* percentile fell in bin 0 (stain absent): scale kept at 1       */
 #define SPCN_FLAG_BASIS     8   /* the basis has a singular Gram matrix: densities set to 0       */
 #define SPCN_FLAG_SHORT    16   /* basis estimation drew fewer tissue samples than requested      */
-#define SPCN_FLAG_BATCH    32   /* batched call: this tile was skipped (bad descriptor, total_px too
-                                   small for the tiles, or a bounded wait expired)                  */
+#define SPCN_FLAG_BATCH    32   /* batched call: this tile was skipped (bad descriptor, or total_px
+                                   too small for the tiles)                                         */
 #define SPCN_FLAG_TIMEOUT  64   /* a bounded device-side wait between workgroups expired: the
                                    results of this call are invalid                                 */
 #define SPCN_FLAG_NO_BACKGROUND 128 /* spcn_estimate_i0 found no background pixel: i0 set to 255    */
@@ -319,22 +319,25 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
                                         hipStream_t stream);
 
 /* Normalises every tile of a batch to one target (Eqs. 1-4, each tile with its own basis
- * w_src[t] and its own percentile) in ONE persistent kernel launch: a global work queue hands out
- * all pass-1 chunks before any pass-2 chunk; the last pass-1 chunk of a tile finalises that tile's
- * percentile and releases its pass-2 chunks.  (Two tiny set-up kernels precede it.)
+ * w_src[t] and its own percentile) with a fixed sequence of launches and no host synchronisation
+ * (the call can be captured into a graph): per-tile set-up, a work plan, a persistent pass 1 over
+ * all tiles' items, a per-tile percentile check, the retry round (a second pass 1 over the items of
+ * the tiles whose range was doubled, and their check), and one grid-stride pass 2 over all tiles.
  *   tiles    device array of n_tiles descriptors (1 <= n_tiles <= 8192), 4-byte aligned pointers
  *   total_px an upper bound of the tiles' total pixel count (sizes the workspace; if the tiles hold
  *            more, nothing is processed and every tile's flags get SPCN_FLAG_BATCH)
  *   w_src [n_tiles][6]; w_tgt [6]; scale_tgt [2]; i0_out host [3] or NULL;
- *   p99_out, scale_out [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL.
- * Tile t's histogram range is p->hist_hi_dev[2t .. 2t+1] when given, else p->hist_hi; there is no
- * automatic retry (a percentile in the last bin sets SPCN_FLAG_RANGE for that tile).
- * Results are identical to calling spcn_normalize on each tile with that range and auto_range 0. */
+ *   p99_out, scale_out [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL;
+ *   hist_out [n_tiles][2][256] uint64 or NULL: each tile's non-white histogram (at its final range).
+ * Tile t's histogram range is p->hist_hi_dev[2t .. 2t+1] when given, else p->hist_hi; with
+ * p->auto_range a tile whose percentile lands in the last bin is counted again at twice that stain's
+ * range (SPCN_FLAG_RANGE_RETRY), as spcn_normalize does.  Results are identical to calling
+ * spcn_normalize on each tile with that range and the same auto_range. */
 spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px,
                                    const float* w_src, const float* w_tgt, const float* scale_tgt,
                                    const float* i0_out, const spcn_params* p, float* p99_out,
-                                   float* scale_out, int32_t* flags_out, void* ws, size_t ws_bytes,
-                                   hipStream_t stream);
+                                   float* scale_out, int32_t* flags_out, uint64_t* hist_out, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
 
 /* Differentiable float path (extension: normalisation as a training-time augmentation layer).
  * x, y: [n][3][height][width] FP32 in [0, 1] (p->i0 is the input's i0, normally 1).  Per-sample

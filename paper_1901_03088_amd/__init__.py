@@ -73,7 +73,8 @@ _SIGS = {
     "spcn_normalize_streamed": (C.c_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _P, _i64, _vp, _vp, _sz, _vp,
                                           _vp, _vp]),
     "spcn_stream_resident_chunks": (_i64, [_i64, _i64, _i64, _sz]),
-    "spcn_normalize_batched": (C.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_normalize_batched": (C.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _P, _vp, _vp, _vp, _vp, _vp, _sz,
+                                         _vp]),
     "spcn_normalize_f32": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_backward": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp,
@@ -475,9 +476,10 @@ def spcn_estimate_basis_batched(tiles: torch.Tensor, n_tiles: int, n_samples: in
 
 def spcn_normalize_batched(tiles: torch.Tensor, n_tiles: int, total_px: int, w_src: torch.Tensor,
                            w_tgt: torch.Tensor, scale_tgt: torch.Tensor, p: spcn_params | None = None,
-                           i0_out=None, ws=None, stats: bool = True):
-    """Normalises every tile of a device tile table (tile_table(srcs, outs)) in one persistent launch.
-    w_src [n_tiles, 6].  Returns dict(p99 [n, 2], scale [n, 2], flags [n, 2]) (empty if stats=False)."""
+                           i0_out=None, ws=None, stats: bool = True, hist: bool = False):
+    """Normalises every tile of a device tile table (tile_table(srcs, outs)), graph-capturable.
+    w_src [n_tiles, 6].  Returns dict(p99 [n, 2], scale [n, 2], flags [n, 2]) (empty if stats=False),
+    plus hist [n, 2, 256] uint64 when hist is True."""
     _dev(w_src, torch.float32, "w_src")
     p = p or params()
     dev = tiles.device
@@ -486,13 +488,16 @@ def spcn_normalize_batched(tiles: torch.Tensor, n_tiles: int, total_px: int, w_s
         res = {"p99": torch.empty((n_tiles, 2), dtype=torch.float32, device=dev),
                "scale": torch.empty((n_tiles, 2), dtype=torch.float32, device=dev),
                "flags": torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)}
+    if hist:
+        res["hist"] = torch.empty((n_tiles, 2, HIST_BINS), dtype=torch.uint64, device=dev)
     if ws is None:
         ws = workspace(workspace_size(OP_NORMALIZE_BATCHED, total_px, n_tiles), dev)
     wsp, wsn = _ws_ptr(ws)
     io = None if i0_out is None else (C.c_float * 3)(*[float(v) for v in i0_out])
     _check(_L.spcn_normalize_batched(_ptr(tiles), int(n_tiles), int(total_px), _ptr(w_src), _ptr(w_tgt),
                                      _ptr(scale_tgt), io, C.byref(p), _ptr(res.get("p99")), _ptr(res.get("scale")),
-                                     _ptr(res.get("flags")), wsp, wsn, _stream()), "spcn_normalize_batched")
+                                     _ptr(res.get("flags")), _ptr(res.get("hist")), wsp, wsn, _stream()),
+           "spcn_normalize_batched")
     return res
 
 

@@ -492,7 +492,7 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
 spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px, const float* w_src,
                                    const float* w_tgt, const float* scale_tgt, const float* i0_out,
                                    const spcn_params* p, float* p99_out, float* scale_out, int32_t* flags_out,
-                                   void* ws, size_t ws_bytes, hipStream_t stream) {
+                                   uint64_t* hist_out, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!tiles) return fail(SPCN_E_ARG, "tiles is NULL");
     if (n_tiles < 1 || n_tiles > batched_max_tiles())
         return fail(SPCN_E_ARG, "n_tiles = %d must lie in [1, %lld]", (int)n_tiles, (long long)batched_max_tiles());
@@ -507,7 +507,7 @@ spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int6
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_normalize_batched(tiles, n_tiles, total_px, w_src, w_tgt, scale_tgt, io, make_params(p),
-                                            p99_out, scale_out, flags_out, ws, dev, stream);
+                                            p99_out, scale_out, flags_out, hist_out, ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_normalize_batched launch");
     return SPCN_OK;
 }

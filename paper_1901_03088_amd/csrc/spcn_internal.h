@@ -117,7 +117,7 @@ int64_t batched_max_tiles();
 hipError_t launch_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px,
                                     const float* w_src, const float* w_tgt, const float* scale_tgt,
                                     const float i0_out[3], const ParamsK& pk, float* p99_out,
-                                    float* scale_out, int32_t* flags_out, void* ws,
+                                    float* scale_out, int32_t* flags_out, uint64_t* hist_out, void* ws,
                                     const DevInfo& dev, hipStream_t s);
 
 // ---- differentiable float path (spcn_f32.hip)

@@ -653,6 +653,21 @@ __device__ inline void make_recolour(RecolourConsts& K, const float* w_tgt, cons
     K.a1 = (float)B.a[1];
 }
 
+// The constants moved to scalar registers (they are the same in every lane), which keeps ~11 vector
+// registers free in the recolour loops.
+__device__ __forceinline__ RecolourConsts uniform_consts(const RecolourConsts& K) {
+    RecolourConsts R;
+    auto u = [](float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); };
+    for (int c = 0; c < 3; ++c) {
+        R.M[c][0] = u(K.M[c][0]);
+        R.M[c][1] = u(K.M[c][1]);
+        R.L[c] = u(K.L[c]);
+    }
+    R.a0 = u(K.a0);
+    R.a1 = u(K.a1);
+    return R;
+}
+
 template <int COPIES>
 struct P2Lds {
     static_assert((COPIES & (COPIES - 1)) == 0, "power of two");

@@ -36,8 +36,9 @@ def target(S, p):
     [(256, 320), (64, 64), (1, 5), (300, 200), (512, 1024)],
     [(2048, 1984), (256, 256)] + [(64 * (1 + i % 5), 64 * (1 + (i * 7) % 9)) for i in range(40)],
 ])
-def test_batched_equals_per_tile(S, orc, shapes):
-    p = S.params()
+@pytest.mark.parametrize("auto_range", [True, False])
+def test_batched_equals_per_tile(S, orc, shapes, auto_range):
+    p = S.params(auto_range=auto_range)
     tiles, srcs, outs = make_batch(shapes)
     tgt, wt, sc = target(S, p)
     W = torch.stack([S.as_basis(d["W"], DEV) for d in tiles]).contiguous()
@@ -47,16 +48,16 @@ def test_batched_equals_per_tile(S, orc, shapes):
     torch.cuda.synchronize()
     flags = st["flags"].cpu().numpy(); p99 = st["p99"].cpu().numpy(); scale = st["scale"].cpu().numpy()
     scn = sc.cpu().numpy().astype(np.float64)
-    p1 = S.params(auto_range=False)     # the batched call has no automatic range retry
     for t, d in enumerate(tiles):
-        ref, rst = S.spcn_normalize(srcs[t], W[t].contiguous(), wt, sc, p1)
+        ref, rst = S.spcn_normalize(srcs[t], W[t].contiguous(), wt, sc, p)
         torch.cuda.synchronize()
         assert torch.equal(ref, outs[t]), t
         assert np.array_equal(rst["p99_src"].cpu().numpy(), p99[t])
         assert np.array_equal(rst["flags"].cpu().numpy(), flags[t])
         if t < 6:
             o_out, o_st, o_hist = orc.normalize_u8(srcs[t].cpu().numpy(), orc.f32(orc.basis(d["W"])),
-                                                   orc.f32(orc.basis(tgt["W"])), scn, lam=orc.f32(p.lambda_))
+                                                   orc.f32(orc.basis(tgt["W"])), scn, lam=orc.f32(p.lambda_),
+                                                   auto_range=bool(p.auto_range))
             dd = np.abs(o_out.astype(int) - outs[t].cpu().numpy().astype(int)).reshape(-1, 3).max(1)
             assert (dd <= 1).mean() >= 0.9999
             assert np.array_equal(o_st["P"].astype(np.float32), p99[t])
@@ -144,8 +145,8 @@ def test_batched_pipeline_graph_replay(S, orc):
 def test_batched_full_size(S, orc):
     """The 512-tile workload (sides 256..2048 in steps of 64, 698 Mpixel) through the benchmark's
     pipeline: every tile's basis fit from 4096 samples against the oracle's fit on the same samples,
-    every tile's percentile and flags equal to the oracle's (exact histograms), and 2048 seeded
-    output pixels per tile recoloured by the oracle one by one."""
+    every tile's histogram bit-exact and its percentile and flags equal to the oracle's, and 2048
+    seeded output pixels per tile recoloured by the oracle one by one."""
     import math
     p = S.params()
     shapes = synth.tile_shapes(512)
@@ -157,9 +158,10 @@ def test_batched_full_size(S, orc):
     total = sum(h * w for h, w in shapes)
     W, _, fl_fit = S.spcn_estimate_basis_batched(table, len(shapes), 4096, seed=30000, p=p, lambda_nmf=0.1,
                                                  n_iter=50)
-    st = S.spcn_normalize_batched(table, len(shapes), total, W, wt, sc, p)
+    st = S.spcn_normalize_batched(table, len(shapes), total, W, wt, sc, p, hist=True)
     torch.cuda.synchronize()
     Wc = W.cpu().numpy(); p99 = st["p99"].cpu().numpy(); flags = st["flags"].cpu().numpy()
+    ghist = st["hist"].cpu().numpy().astype(np.uint64)
     assert (fl_fit.cpu().numpy() == 0).all()
     scn = sc.cpu().numpy().astype(np.float64)
     Wtn = orc.f32(orc.basis(tgt["W"]))
@@ -176,12 +178,14 @@ def test_batched_full_size(S, orc):
             worst_ang = max(worst_ang, math.acos(min(1.0, a[j] @ b[j] / (np.linalg.norm(a[j]) * np.linalg.norm(b[j])))))
         Wn = orc.f32(orc.basis(Wc[t]))
         H, m = orc.densities_u8(img, Wn, list(p.i0), orc.f32(p.lambda_), p.white_sum)
-        hist = orc.histogram(H, m, list(p.hist_hi), 256)
+        hh, bits = orc.settle_range(H, m, list(p.hist_hi), p.percentile)
+        hist = orc.histogram(H, m, hh, 256)
         del H
+        assert np.array_equal(ghist[t], hist), t          # every tile's histogram, bit-exact
         P, fl = [], []
         for j in range(2):
-            Pj, f, _ = orc.percentile_hist(hist[j], float(p.hist_hi[j]), orc.q_of(p.percentile))
-            P.append(Pj); fl.append(f)
+            Pj, f, _ = orc.percentile_hist(hist[j], float(hh[j]), orc.q_of(p.percentile))
+            P.append(Pj); fl.append(f | (orc.RANGE_RETRY if bits >> j & 1 else 0))
         assert np.array_equal(p99[t], np.array(P).astype(np.float32)), t
         assert np.array_equal(flags[t], np.array(fl)), t
         flat = img.reshape(-1, 3)
