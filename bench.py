@@ -8,7 +8,7 @@ NMF, 50 rounds, the samples' percentile and the histogram range derived from it)
 recolour, uint8 write).  The flags of the timed step are checked: no overflow, timeout or skip.
 Inputs are resident in HBM before the timed region.  Extras (same JSON line): the batched workload
 (512 tiles in one graph) against a per-tile loop, and forward+backward of the float path against
-forward only.  Prints ONE JSON line.
+forward only, and the FP32 densities of an 8192^2 image.  Prints ONE JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload slide|cfg1|small]
 """
@@ -198,6 +198,29 @@ def bench_batched(dev, S, synth, steps, warmup, n_tiles=512, loop=True, tune=Tru
                 speedup_vs_graph_loop=round(ms_loop_graph / ms_graph, 2))
 
 
+def bench_densities(dev, S, synth, steps, warmup, size=8192):
+    """spcn_densities with the FP32 density planes on the 8192 x 8192 single image (67 Mpixel): the
+    whole call (set-up, pass 1 writing the densities, range check, gated repeat, percentile).  The
+    algorithmic traffic is 3 B/px read + 8 B/px written."""
+    import torch
+    d = synth.config1(size, device=dev)
+    img, w = d["img"], S.as_basis(d["W"], dev)
+    n = size * size
+    p = S.params()
+    h = torch.empty((2, n), dtype=torch.float32, device=dev)
+    hist = torch.empty((2, 256), dtype=torch.uint64, device=dev)
+    p99 = torch.empty(2, dtype=torch.float32, device=dev)
+    flags = torch.empty(2, dtype=torch.int32, device=dev)
+    ws = S.workspace(S.workspace_size(S.OP_DENSITIES), dev)
+    stream = torch.cuda.current_stream()
+    ms = timed(lambda: S.spcn_densities(img, w, p, h_out=h, hist_out=hist, p99_out=p99, flags_out=flags, ws=ws),
+               steps, warmup, stream)
+    gbs = 11.0 * n / (ms / 1e3) / 1e9
+    return {"workload": "single_image_8192", "pixels": n, "ms": round(ms, 4), "Mpx_s": round(n / ms / 1e3, 1),
+            "bytes_per_px": 11, "GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "flags": [int(v) for v in flags.cpu()]}
+
+
 def bench_fwdbwd(dev, S, synth, steps, warmup, n=64, size=512):
     """Differentiable path: 64 x 3 x 512 x 512 float images, per-sample target bases, forward +
     backward of L = sum(w * y^2) (fixed random weights w, so dL/dy = 2 w y, one elementwise product
@@ -243,9 +266,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="skip the batched and forward+backward measurements")
-    ap.add_argument("--only", choices=["batched", "fwdbwd"], default=None,
-                    help="run one extension workload alone (the batched graph without the per-tile loop, or the "
-                         "differentiable batch), for profiling; no slide step")
+    ap.add_argument("--only", choices=["batched", "fwdbwd", "densities"], default=None,
+                    help="run one extra workload alone (the batched graph without the per-tile loop, the "
+                         "differentiable batch, or the 8192^2 densities), for profiling; no slide step")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the library's default kernel variants (for profiling runs, whose traces should "
                          "hold only the timed kernels)")
@@ -268,6 +291,8 @@ def main() -> int:
     if args.only:
         if args.only == "batched":
             r = bench_batched(dev, S, synth, args.steps, args.warmup, loop=False, tune=args.autotune)
+        elif args.only == "densities":
+            r = bench_densities(dev, S, synth, args.steps, args.warmup)
         else:
             r = bench_fwdbwd(dev, S, synth, args.steps, args.warmup)
         log(f"[bench] {args.only} {r}")
@@ -440,6 +465,12 @@ def main() -> int:
         del img, out
         torch.cuda.empty_cache()
         extras = {}
+        try:
+            extras["densities_8192"] = bench_densities(dev, S, synth, args.steps, args.warmup)
+            log(f"[bench] densities {extras['densities_8192']}")
+        except Exception as e:   # report, never hide, a failing extra
+            extras["densities_8192"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
         try:
             extras["batched"] = bench_batched(dev, S, synth, args.steps, args.warmup, tune=args.autotune)
             log(f"[bench] batched {extras['batched']}")

@@ -29,6 +29,7 @@
 namespace spcn {
 
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufDword3 = 0x00020000;   // raw (untyped) buffer, gfx9-family descriptor word 3
 
 // Buffer resource over `units` 12-byte units starting at unit `unit0` of `base`.  Every argument
@@ -806,6 +807,69 @@ __device__ void p2_tail(const P2Lds<COPIES>& T, const RecolourConsts& K, const u
         float h0, h1;
         p2_densities(T, roff, K, src[3 * i], src[3 * i + 1], src[3 * i + 2], h0, h1);
         for (int c = 0; c < 3; ++c) out[3 * i + c] = (uint8_t)recolour_byte(h0, h1, K, c, 0, 0u);
+    }
+}
+
+// ================================================================================== pass 1 + densities
+
+// Pass 1 that also writes the FP32 densities of every pixel (Eq. 2, planar [2][n_px]): the same
+// histogram as p1f_tiles, plus, per unit, four densities per stain from the FP32 pass-2 tables T
+// (p2_densities, the arithmetic of the recolour pass), stored as one 16-byte write per stain plane.
+// The planes are addressed through buffer resources (plane 1 starts at h + n_px, which is 16-byte
+// aligned only when n_px is a multiple of 4; buffer stores need 4-byte alignment only).
+template <bool WIDE, int UNROLL, bool U16>
+__device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const RecolourConsts& K, const P1Params& pp,
+                               const uint8_t* src, int64_t n_units, float* h, int64_t n_px, int tid, int nthreads,
+                               int64_t scatter, int64_t step) {
+    const P1FLane L = p1f_lane<WIDE>(tid);
+    const int64_t tu = (int64_t)nthreads * UNROLL;
+    const int64_t n_tiles = (n_units + tu - 1) / tu;
+    int64_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    int64_t ph = (t * scatter) % n_tiles;
+    auto tile_rs = [&](int64_t tt, int64_t tile) {
+        const bool in = tt < n_tiles;
+        return chunk_rsrc(src, in ? tile * tu : 0, in ? min(tu, n_units - tile * tu) : 0);
+    };
+    // plane descriptors over whole units of this tile: 16 bytes per unit and stain
+    auto plane_rs = [&](const float* base, int64_t tile) {
+        const uint64_t addr = reinterpret_cast<uint64_t>(base) + 16 * (uint64_t)(tile * tu);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+        const int nb = __builtin_amdgcn_readfirstlane((int)(16 * min(tu, n_units - tile * tu)));
+        return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, nb, kBufDword3);
+    };
+    __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
+    u32x3 cur[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (; t < n_tiles; t += gridDim.x) {
+        int64_t pn = ph + step;
+        if (pn >= n_tiles) pn -= n_tiles;
+        const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);
+        u32x3 nxt[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
+        const int cnt = (int)min(tu, n_units - ph * tu);
+        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
+        const __amdgpu_buffer_rsrc_t w0 = plane_rs(h, ph), w1 = plane_rs(h + n_px, ph);
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) {
+            uint32_t px[4][3];
+            bytes_of_unit(cur[j], px);
+            float h0[4], h1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) p2_densities(T, 0u, K, px[q][0], px[q][1], px[q][2], h0[q], h1[q]);
+            const int off = 16 * (tid + j * nthreads);   // past the tile's units the stores are dropped
+            u32x4 v0, v1;
+            v0.x = __float_as_uint(h0[0]); v0.y = __float_as_uint(h0[1]); v0.z = __float_as_uint(h0[2]); v0.w = __float_as_uint(h0[3]);
+            v1.x = __float_as_uint(h1[0]); v1.y = __float_as_uint(h1[1]); v1.z = __float_as_uint(h1[2]); v1.w = __float_as_uint(h1[3]);
+            __builtin_amdgcn_raw_buffer_store_b128(v0, w0, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(v1, w1, off, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+        ph = pn;
     }
 }
 

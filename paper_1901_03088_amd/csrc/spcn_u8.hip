@@ -5,7 +5,7 @@
 //             (one workgroup per CU, a contiguous chunk each; see spcn_passes.hpp);
 //   k_pass2   every workgroup recomputes the percentile from the histogram in its prologue (no
 //             separate finalisation launch), then re-reads 3 B/px, recolours and writes 3 B/px;
-//   k_dens    optional FP32 density output (spcn_densities with h_out);
+//   k_pass1d  pass 1 writing the FP32 densities as well (spcn_densities with h_out);
 //   k_finalize percentile + flags of a histogram for spcn_densities;
 //   k_u8_setup / k_range_check  histogram range kept on the device: the range of the call, and one
 //             automatic retry at twice a stain's range when its percentile lands in the open last
@@ -124,27 +124,42 @@ __global__ void k_zero_u64(uint64_t* p, int n) {
     for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) p[i] = 0;
 }
 
-// FP32 densities of every pixel, planar [2][n_px] (Eq. 2 with W fixed).
-__global__ __launch_bounds__(256) void k_dens(const uint8_t* src, int64_t n_px, const float* w, float i00, float i01,
-                                              float i02, float lambda, float* h_out) {
+// Pass 1 with the FP32 densities of every pixel (Eq. 2 with W fixed), planar [2][n_px]: the exact
+// histogram of k_pass1g's wide layout and, from the same read of each unit, the densities from the
+// FP32 tables of the recolour pass, one 16-byte store per unit and stain (3 B/px read, 8 B/px
+// written).  One 1024-thread workgroup per CU, the tiles in the scattered order of k_pass1g.
+template <int UNROLL>
+__global__ __launch_bounds__(1024, 4) void k_pass1d(const P1Args a, float* h_out) {
+    __shared__ P1FLds<true> S;
     __shared__ P2Lds<1> T;
-    __shared__ Basis64 B;
-    __shared__ RecolourConsts K;
-    const float i0[3] = {i00, i01, i02};
-    if (threadIdx.x == 0) {
-        derive_basis(w, lambda, B);
-        K.a0 = (float)B.a[0];
-        K.a1 = (float)B.a[1];
-    }
+    __shared__ float s_a[2];
+    const P1Params pp = p1_resolve(a.pp);
+    p1f_setup(S, a.w, pp, true);
+    p2_tables(T, S.B, pp.i0);
+    if (threadIdx.x == 0) { s_a[0] = (float)S.B.a[0]; s_a[1] = (float)S.B.a[1]; }
     __syncthreads();
-    p2_tables(T, B, i0);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_px; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t* p = src + 3 * i;
-        float h0, h1;
-        p2_densities(T, 0u, K, p[0], p[1], p[2], h0, h1);
-        h_out[i] = h0;
-        h_out[n_px + i] = h1;
+    RecolourConsts K{};
+    K.a0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_a[0])));
+    K.a1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_a[1])));
+    const int64_t n_units = a.n_px >> 2;
+    if (S.shift == 16)
+        p1f_tiles_dens<true, UNROLL, true>(S, T, K, pp, a.src, n_units, h_out, a.n_px, threadIdx.x, 1024, a.scatter,
+                                          a.step);
+    else
+        p1f_tiles_dens<true, UNROLL, false>(S, T, K, pp, a.src, n_units, h_out, a.n_px, threadIdx.x, 1024, a.scatter,
+                                           a.step);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int tail = (int)(a.n_px - 4 * n_units);
+        const uint8_t* px = a.src + 12 * n_units;
+        p1f_tail(S, pp, px, tail);
+        for (int i = 0; i < tail; ++i) {
+            float h0, h1;
+            p2_densities(T, 0u, K, px[3 * i], px[3 * i + 1], px[3 * i + 2], h0, h1);
+            h_out[4 * n_units + i] = h0;
+            h_out[a.n_px + 4 * n_units + i] = h1;
+        }
     }
+    p1f_merge(S, a.hist);
 }
 
 struct P2Args {
@@ -278,6 +293,18 @@ hipError_t run_pass1g(const P1Args& a, int per_cu, const DevInfo& dev, hipStream
     return hipGetLastError();
 }
 
+template <int UNROLL>
+hipError_t run_pass1d(const P1Args& a, float* h_out, const DevInfo& dev, hipStream_t s) {
+    int64_t tiles = ((a.n_px >> 2) + 1024 * UNROLL - 1) / (1024 * UNROLL);
+    int64_t cap = dev.cus;
+    int grid = (int)(tiles < 1 ? 1 : (tiles < cap ? tiles : cap));
+    P1Args b = a;
+    b.scatter = tile_scatter(tiles, grid);
+    b.step = tiles > 0 ? ((int64_t)grid * b.scatter) % tiles : 0;
+    hipLaunchKernelGGL((k_pass1d<UNROLL>), dim3(grid), dim3(1024), 0, s, b, h_out);
+    return hipGetLastError();
+}
+
 template <int COPIES, int THREADS>
 hipError_t run_pass2g(const P2Args& a, int blocks_per_cu, const DevInfo& dev, hipStream_t s) {
     constexpr int U = p2g_unroll(THREADS);
@@ -309,7 +336,8 @@ static U8Ctl* ctl_of(void* ws) {
 }
 
 static hipError_t launch_pass1(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, uint64_t* hist,
-                               const float* range, const int32_t* gate, const DevInfo& dev, hipStream_t s) {
+                               const float* range, const int32_t* gate, const DevInfo& dev, hipStream_t s,
+                               float* h_out = nullptr) {
     P1Args a{};
     a.src = img; a.n_px = n_px; a.w = w;
     for (int c = 0; c < 3; ++c) a.pp.i0[c] = pk.i0[c];
@@ -318,6 +346,7 @@ static hipError_t launch_pass1(const uint8_t* img, int64_t n_px, const float* w,
     a.pp.range = range;
     a.hist = reinterpret_cast<unsigned long long*>(hist);
     a.gate = gate;
+    if (h_out) return run_pass1d<2>(a, h_out, dev, s);
     switch (option(SPCN_OPT_P1_VARIANT)) {
         case 0: return run_pass1<1, 64, 4, 4>(a, dev, s);
         case 1: return run_pass1<2, 64, 4, 4>(a, dev, s);
@@ -342,13 +371,15 @@ hipError_t launch_count(const uint8_t* img, int64_t n_px, const float* w, const 
     return launch_pass1(img, n_px, w, pk, hist, pk.hist_hi_dev, nullptr, dev, s);
 }
 
-// Histogram of the call with its range settled on the device: set-up, pass 1 and, with auto_range,
-// the range check and the gated second pass 1.  The range and retry words are in ctl.
+// Histogram of the call with its range settled on the device: set-up, pass 1 (writing the densities
+// too when h_out is given) and, with auto_range, the range check and the gated second pass 1 (the
+// densities do not depend on the range).  The range and retry words are in ctl.
 static hipError_t launch_hist_checked(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
-                                      uint64_t* hist, void* ctl_ws, const DevInfo& dev, hipStream_t s) {
+                                      uint64_t* hist, void* ctl_ws, const DevInfo& dev, hipStream_t s,
+                                      float* h_out = nullptr) {
     U8Ctl* ctl = ctl_of(ctl_ws);
     hipLaunchKernelGGL(k_u8_setup, dim3(1), dim3(256), 0, s, hist, ctl, pk.hist_hi_dev, pk.hist_hi[0], pk.hist_hi[1]);
-    hipError_t e = launch_pass1(img, n_px, w, pk, hist, ctl->range, nullptr, dev, s);
+    hipError_t e = launch_pass1(img, n_px, w, pk, hist, ctl->range, nullptr, dev, s, h_out);
     if (e != hipSuccess || !pk.auto_range) return e;
     hipLaunchKernelGGL(k_range_check, dim3(1), dim3(256), 0, s, hist, ctl, pk.q64);
     return launch_pass1(img, n_px, w, pk, hist, ctl->range, &ctl->retry, dev, s);
@@ -357,14 +388,8 @@ static hipError_t launch_hist_checked(const uint8_t* img, int64_t n_px, const fl
 hipError_t launch_densities(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
                             float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out, float* range_out,
                             void* ctl_ws, const DevInfo& dev, hipStream_t s) {
-    hipError_t e = launch_hist_checked(img, n_px, w, pk, hist, ctl_ws, dev, s);
+    hipError_t e = launch_hist_checked(img, n_px, w, pk, hist, ctl_ws, dev, s, h_out);
     if (e != hipSuccess) return e;
-    if (h_out) {
-        int64_t want = (n_px + 255) / 256;
-        int64_t cap = (int64_t)dev.cus * 8;
-        hipLaunchKernelGGL(k_dens, dim3((unsigned)(want < cap ? want : cap)), dim3(256), 0, s, img, n_px, w,
-                           pk.i0[0], pk.i0[1], pk.i0[2], pk.lambda, h_out);
-    }
     if (p99_out || flags_out || range_out) {
         U8Ctl* ctl = ctl_of(ctl_ws);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, hist, pk.q64, ctl->range, pk.hist_hi[0],

@@ -348,6 +348,41 @@ def test_degenerate_basis_flag(S):
     assert (h == 0).all()
 
 
+def test_config1_densities_full_size(S, orc):
+    """8192 x 8192 (67 Mpixel): spcn_densities with the FP32 density planes, in the benchmark's launch
+    shape (the fused pass 1); every density of both planes within 1e-4 max(|h|, 1) of the oracle's
+    FP64 value, the histogram bit-exact, percentile and flags equal."""
+    src = synth.config1(device=DEV)
+    p = S.params()
+    h, hist, p99, flags = gpu_densities(S, src["img"], src["W"], p)
+    H, m, ohist, P, fl = oracle_densities(orc, src["img"], src["W"], p)
+    assert np.array_equal(hist, ohist), "histogram counts differ"
+    err = np.abs(h - H) / np.maximum(np.abs(H), 1.0)
+    print(f"[cfg1 densities] max rel err {err.max():.3e} over {H.size} values", flush=True)
+    assert err.max() <= 1e-4
+    assert np.array_equal(p99, P.astype(np.float32))
+    assert np.array_equal(flags, fl)
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (2, 7), (5, 5), (3, 1)])
+def test_densities_plane_alignment(S, orc, shape):
+    """Pixel counts that are not a multiple of 4 (the second plane starts off a 16-byte boundary) and
+    a tail after the last unit: every density lands at its index, nothing is written past the planes."""
+    d = synth.make_image(60 + shape[1], shape[0], shape[1], device=DEV)
+    n = shape[0] * shape[1]
+    p = S.params()
+    w = S.as_basis(d["W"], DEV)
+    guard = torch.full((2 * n + 64,), -7.0, dtype=torch.float32, device=DEV)
+    h_out = guard[:2 * n]
+    _, hist, _, _ = S.spcn_densities(d["img"], w, p, h_out=h_out)
+    torch.cuda.synchronize()
+    H, m, ohist, P, fl = oracle_densities(orc, d["img"], d["W"], p)
+    g = h_out.cpu().numpy().astype(np.float64).reshape(2, n)
+    assert np.abs(g - H).max() <= 1e-4 * max(1.0, np.abs(H).max())
+    assert (guard[2 * n:].cpu().numpy() == -7.0).all()
+    assert np.array_equal(hist.cpu().numpy().astype(np.uint64), ohist)
+
+
 def test_config1_full_size(S, orc):
     """8192 x 8192 (67 Mpixel), the fused path at its benchmark launch shape: full histogram and
     output compared with the oracle."""
