@@ -421,7 +421,9 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
     // predicate is a plain compare whose ballot is its scalar mask; the masks are combined in scalar
     // registers and turned into the 0/1 increment by one select (a ballot of a combined predicate
     // would cost two vector instructions per pixel).
-    uint64_t near_waves = 0;   // lanes with a near-edge non-white pixel
+    uint64_t nearj[UNROLL];   // per unit: lanes with a near-edge non-white pixel
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) nearj[j] = 0;
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
         const bool valid = lb0 + j * nthreads < cnt;
@@ -455,17 +457,18 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
                 // scalar registers and turned into the 0/1 increment by one select
                 const uint64_t white = __ballot(sum[q] >= thr);
                 const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
-                near_waves |= nr & ~white & valid_lanes;
+                nearj[j] |= nr & ~white & valid_lanes;
                 const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
                 atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
                 atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
             }
         }
     }
-    if (near_waves) {   // rare: settle the near-edge pixels of these units in FP64 (bytes from registers)
+    // rare: settle the near-edge pixels in FP64 (bytes from registers), only in the units that hold
+    // one, and only on the lanes that do
 #pragma unroll
-        for (int j = 0; j < UNROLL; ++j) {
-            if (lb0 + j * nthreads >= cnt) continue;
+    for (int j = 0; j < UNROLL; ++j) {
+        if (nearj[j] && __builtin_amdgcn_inverse_ballot_w64(nearj[j])) {
             uint32_t px[4][3];
             bytes_of_unit(cur[j], px);
 #pragma unroll
