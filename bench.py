@@ -35,12 +35,9 @@ def build_slide(workload: str, dev):
     import torch
     import synth
     if workload == "slide":
-        tissue, bg, W = synth.slide_blocks(device=dev)
-        plan = synth.slide_layout()
-        img = synth.assemble_slide(tissue, bg, plan)
-        del tissue, bg
+        img, W, plan = synth.make_slide(device=dev)
         desc = {"workload": "gigapixel_slide", "height": synth.SLIDE_H, "width": synth.SLIDE_W,
-                "block": synth.SLIDE_BLOCK, "tissue_slots": sum(1 for s in plan if s[4] >= 0), "slots": len(plan)}
+                "block": synth.SLIDE_BLOCK, "tissue_slots": sum(1 for s in plan if s[4]), "slots": len(plan)}
     elif workload == "cfg1":
         d = synth.config1(device=dev)
         img, W = d["img"], d["W"]
@@ -53,26 +50,83 @@ def build_slide(workload: str, dev):
     return img, W, desc
 
 
-def cpu_baseline(img_dev, W_src, W_tgt, scale_tgt, min_seconds: float = 10.0, band_rows: int = 400):
-    """The FP64 oracle, as it stands, on bands of rows of the same slide until min_seconds of CPU
-    work have run; OpenMP uses every host core."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(img_dev, W_src, W_tgt, scale_tgt, n_px_total: int, hist_hi=(8.0, 8.0), n_samples: int = 200000,
+                 bands: int = 8, band_rows: int = 1000, single_rows: int = 100):
+    """The FP64 oracle, as it stands, timed stage by stage on the host cores: pass 1 (densities of
+    every pixel + the non-white histogram) and pass 2 (densities again + recolour + rounding) on
+    `bands` bands of `band_rows` rows spread over the slide, the percentile from their histogram,
+    and the sparse NMF on n_samples sampled tissue pixels of those bands (50 rounds).  The value is
+    the rate of the whole step at the slide's size: n_px_total / (pass-1 and pass-2 time per pixel
+    x n_px_total + percentile + NMF).  The two passes are timed again on one thread (a smaller band)."""
+    import ctypes
     import numpy as np
     import oracle as orc
-    H, W = int(img_dev.shape[0]), int(img_dev.shape[1])
+    H_img, W_img = int(img_dev.shape[0]), int(img_dev.shape[1])
+    starts = [int(k * (H_img - band_rows) / max(1, bands - 1)) for k in range(bands)]
+    sample = np.concatenate([img_dev[r0:r0 + band_rows].cpu().numpy() for r0 in starts])
+    Ws, Wt = orc.f32(orc.basis(W_src)), orc.f32(orc.basis(W_tgt))
     sc = np.asarray(scale_tgt, dtype=np.float64)
-    done_px, t_total, r0, bands = 0, 0.0, 0, 0
-    while t_total < min_seconds and r0 < H:
-        band = img_dev[r0:r0 + band_rows].cpu().numpy()
-        t = time.perf_counter()
-        orc.normalize_u8(band, orc.f32(orc.basis(W_src)), orc.f32(orc.basis(W_tgt)), sc)
-        t_total += time.perf_counter() - t
-        done_px += band.shape[0] * band.shape[1]
-        r0 += band_rows
-        bands += 1
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": done_px / t_total / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-            "sample": f"{bands} bands of {band_rows} rows x {W} px ({done_px / 1e6:.0f} Mpixel) of the same slide, "
-                      f"full normalisation per band, {t_total:.1f} s"}
+    lam = orc.f32(0.01)
+
+    def passes(img):
+        t0 = time.perf_counter()
+        H, m = orc.densities_u8(img, Ws, lam=lam)
+        hist = orc.histogram(H, m, hist_hi, 256)
+        t1 = time.perf_counter()
+        P = [orc.percentile_hist(hist[j], hist_hi[j], orc.q_of(99.0))[0] for j in range(2)]
+        t2 = time.perf_counter()
+        del H, m
+        orc.recolor_u8(img, Ws, Wt, sc, np.array(P), lam=lam)
+        t3 = time.perf_counter()
+        return t1 - t0, t2 - t1, t3 - t2, P
+
+    n = sample.shape[0] * sample.shape[1]
+    t_p1, t_fin, t_p2, _ = passes(sample)
+    idx = orc.sample_tissue(sample, n_samples, 2024, 660)
+    V = orc.od_samples(sample, idx)
+    H0 = np.array([0.65, 0.70, 0.29]); E0 = np.array([0.07, 0.99, 0.11])
+    W_init = orc.f32(np.stack([H0 / np.linalg.norm(H0), E0 / np.linalg.norm(E0)], axis=1))
+    t0 = time.perf_counter()
+    orc.nmf(V, orc.f32(0.1), 50, W_init, 99.0)
+    t_nmf = time.perf_counter() - t0
+    gomp = None
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    try:   # the same passes on one thread (the oracle's loops are OpenMP loops)
+        gomp = ctypes.CDLL("libgomp.so.1")
+        threads = gomp.omp_get_max_threads()
+        gomp.omp_set_num_threads(1)
+        one = sample[:single_rows]
+        s1, _, s2, _ = passes(one)
+        n1 = one.shape[0] * one.shape[1]
+        single = {"pixels": n1, "pass1_Mpx_s": round(n1 / s1 / 1e6, 2), "pass2_Mpx_s": round(n1 / s2 / 1e6, 2)}
+    except OSError:
+        single = None
+    finally:
+        if gomp is not None:
+            gomp.omp_set_num_threads(threads)
+    per_px = (t_p1 + t_p2) / n
+    step_s = per_px * n_px_total + t_fin + t_nmf
+    return {"value": round(n_px_total / step_s / 1e6, 1), "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "cpu": _cpu_model(),
+            "sample": f"{bands} bands of {band_rows} rows x {W_img} px ({n / 1e6:.0f} Mpixel) spread over the slide "
+                      f"for the two passes, {n_samples} tissue samples of them for the NMF; step time scaled to "
+                      f"{n_px_total / 1e9:.1f} Gpixel: {step_s:.1f} s",
+            "stages": {"pass1_Mpx_s": round(n / t_p1 / 1e6, 1), "percentile_ms": round(t_fin * 1e3, 3),
+                       "pass2_Mpx_s": round(n / t_p2 / 1e6, 1), "nmf_s": round(t_nmf, 3),
+                       "nmf_samples": int(V.shape[1]), "nmf_rounds": 50,
+                       "normalize_Mpx_s": round(1.0 / per_px / 1e6, 1)},
+            "single_thread": single}
 
 
 P1_KERNELS = ["k_pass1<1, 64, 4, 4>", "k_pass1<2, 64, 4, 4>", "k_pass1<4, 32, 4, 4>", "k_pass1<8, 16, 4, 4>",
@@ -262,7 +316,6 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="slide", choices=["slide", "cfg1", "small"])
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="skip the batched and forward+backward measurements")
@@ -272,6 +325,9 @@ def main() -> int:
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the library's default kernel variants (for profiling runs, whose traces should "
                          "hold only the timed kernels)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="also time the bandwidth reference kernels on the slide's buffers: a copy of the slide "
+                         "into the output buffer and a read-only pass over the slide")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg on float32), "
                          "whose FETCH_SIZE / WRITE_SIZE counters calibrate the HBM byte counters")
@@ -410,8 +466,27 @@ def main() -> int:
         res["copy_calibration"] = {"kernel": "torch.neg float32", "read_bytes": a.numel() * 4,
                                    "write_bytes": b.numel() * 4, "launches": 3}
         del a, b
+    if args.ceilings:
+        # what plain library kernels reach on the slide's own buffers: a copy of the input into the
+        # output (6 GB read + 6 GB written, pass 2's traffic) and a read-only reduction of the input
+        # (6 GB read, pass 1's traffic)
+        ms_copy = timed(lambda: S.spcn_bandwidth_probe(img, out, 0), args.steps, args.warmup, stream)
+        ws_probe = S.workspace(S.workspace_size(S.OP_BANDWIDTH_PROBE), dev)
+        ms_read = timed(lambda: S.spcn_bandwidth_probe(img, None, 1, ws=ws_probe), args.steps, args.warmup, stream)
+        ms_tcopy = timed(lambda: out.copy_(img), args.steps, args.warmup, stream)
+        res["ceilings"] = {
+            "copy": {"kernel": "k_probe copy (spcn_bandwidth_probe mode 0)", "ms": round(ms_copy, 4),
+                     "GBs": round(6.0 * n_px / (ms_copy / 1e3) / 1e9, 1)},
+            "read": {"kernel": "k_probe read (spcn_bandwidth_probe mode 1)", "ms": round(ms_read, 4),
+                     "GBs": round(3.0 * n_px / (ms_read / 1e3) / 1e9, 1)},
+            "torch_copy": {"kernel": "torch copy_ uint8", "ms": round(ms_tcopy, 4),
+                           "GBs": round(6.0 * n_px / (ms_tcopy / 1e3) / 1e9, 1)}}
+        log(f"[bench] ceilings {res['ceilings']}")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(img, W_src, tgt["W"], scale_tgt.cpu().numpy(), args.cpu_seconds)
+        t_cpu = time.time()
+        res["cpu_baseline"] = cpu_baseline(img, W_src, tgt["W"], scale_tgt.cpu().numpy(), n_px,
+                                           hist_hi=[float(v) for v in st["hist_hi"].cpu()])
+        log(f"[bench] cpu baseline {res['cpu_baseline']} ({time.time() - t_cpu:.0f} s)")
     if args.extras:
         # channel-wise background intensity (Sec. 3.1 item 1): 100k background samples of the slide
         i0_dev = torch.empty(3, dtype=torch.float32, device=dev)

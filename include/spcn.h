@@ -101,6 +101,7 @@ void spcn_default_params(spcn_params* p);
 #define SPCN_OP_BAND_PERCENTILES  9   /* n_items = number of bands */
 #define SPCN_OP_STREAM_NORMALIZE 10   /* n_px = image width, n_items = chunk_rows */
 #define SPCN_OP_EXACT_PERCENTILE 11   /* no size arguments: a fixed 2^28 + 2^26 + 37120 bytes */
+#define SPCN_OP_BANDWIDTH_PROBE  12   /* no size arguments: the read probe's 4 MiB sink */
 
 /* Bytes of workspace the operation needs.  n_px: pixels per image (per sample for the float path);
  * n_items: images / tiles / samples; n_samples: pixels sampled for basis estimation.  Returns 0
@@ -369,6 +370,16 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
                                     const float* grad_y, float* grad_x, float* grad_w_tgt,
                                     float* grad_scale, void* ws, size_t ws_bytes,
                                     hipStream_t stream);
+
+/* Memory-bandwidth reference for the roofline of the two passes (measurement only; it computes
+ * nothing of the method): mode 0 copies `bytes` from src to dst (pass 2's traffic), mode 1 reads
+ * them and XOR-reduces into the caller's workspace (pass 1's traffic), both grid-stride with
+ * 16-byte accesses in the recolour pass's launch shape.
+ *   src, dst  device buffers, 16-byte aligned, not overlapping (dst unused in mode 1)
+ *   bytes     a multiple of 16 in [16, 2^40]
+ *   ws        mode 1: spcn_workspace_size(SPCN_OP_BANDWIDTH_PROBE, 0, 0, 0) bytes; mode 0: unused */
+spcn_status spcn_bandwidth_probe(const void* src, void* dst, int64_t bytes, int32_t mode, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
 
 /* Tuning options (autotuner hooks).  They select among kernel variants that compute identical
  * results; they are process-wide and read when work is enqueued.

@@ -28,7 +28,7 @@ FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_
     FLAG_RANGE_RETRY = 1, 2, 4, 8, 16, 32, 64, 128, 256
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
     OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES, \
-    OP_STREAM_NORMALIZE, OP_EXACT_PERCENTILE = range(12)
+    OP_STREAM_NORMALIZE, OP_EXACT_PERCENTILE, OP_BANDWIDTH_PROBE = range(13)
 HIST_BINS = 256
 OPT_P1_VARIANT, OPT_P2_VARIANT, OPT_P2_BLOCKS_PER_CU, OPT_BATCH_CHUNK = range(4)
 
@@ -79,6 +79,7 @@ _SIGS = {
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
     "spcn_normalize_backward": (C.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _P, _vp,
                                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "spcn_bandwidth_probe": (C.c_int, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
     "spcn_set_option": (C.c_int, [C.c_int, C.c_int]),
     "spcn_get_option": (C.c_int, [C.c_int]),
     "spcn_status_string": (C.c_char_p, [C.c_int]),
@@ -499,6 +500,16 @@ def spcn_normalize_batched(tiles: torch.Tensor, n_tiles: int, total_px: int, w_s
                                      _ptr(res.get("flags")), _ptr(res.get("hist")), wsp, wsn, _stream()),
            "spcn_normalize_batched")
     return res
+
+
+def spcn_bandwidth_probe(src: torch.Tensor, dst: torch.Tensor | None, mode: int, ws=None):
+    """Bandwidth reference: mode 0 copies src's bytes into dst, mode 1 only reads them."""
+    n = src.numel() * src.element_size()
+    if ws is None and mode == 1:
+        ws = workspace(workspace_size(OP_BANDWIDTH_PROBE), src.device)
+    wsp, wsn = _ws_ptr(ws) if ws is not None else (None, 0)
+    _check(_L.spcn_bandwidth_probe(_ptr(src), _ptr(dst), int(n), int(mode), wsp, wsn, _stream()),
+           "spcn_bandwidth_probe")
 
 
 def float_params(lam=0.01, white_sum=660, percentile=99.0) -> spcn_params:

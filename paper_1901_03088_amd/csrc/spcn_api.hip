@@ -163,6 +163,8 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
             return n_items <= kMaxBands ? band_workspace_bytes(n_items) : 0;
         case SPCN_OP_STREAM_NORMALIZE:
             return stream_workspace_bytes(n_px, n_items);
+        case SPCN_OP_BANDWIDTH_PROBE:
+            return probe_sink_bytes();
         case SPCN_OP_EXACT_PERCENTILE:
             return exact_workspace_bytes();
         default:
@@ -571,6 +573,25 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
     hipError_t e = launch_backward_f32(a, make_params(p), p99, sel_idx, flags, grad_y, grad_x, grad_w_tgt, grad_scale,
                                        ws, dev, stream);
     if (e != hipSuccess) return hip_fail(e, "spcn_normalize_backward launch");
+    return SPCN_OK;
+}
+
+spcn_status spcn_bandwidth_probe(const void* src, void* dst, int64_t bytes, int32_t mode, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+    if (mode != 0 && mode != 1) return fail(SPCN_E_ARG, "mode = %d must be 0 (copy) or 1 (read)", (int)mode);
+    if (!src) return fail(SPCN_E_ARG, "src is NULL");
+    if (mode == 0 && !dst) return fail(SPCN_E_ARG, "dst is NULL");
+    if (bytes < 16 || (bytes & 15) || bytes > ((int64_t)1 << 40))
+        return fail(SPCN_E_ARG, "bytes = %lld must be a multiple of 16 in [16, 2^40]", (long long)bytes);
+    if ((((uintptr_t)src) | (mode == 0 ? (uintptr_t)dst : 0)) & 15) return fail(SPCN_E_ARG, "src and dst must be 16-byte aligned");
+    if (mode == 0 && (const uint8_t*)src < (const uint8_t*)dst + bytes && (const uint8_t*)dst < (const uint8_t*)src + bytes)
+        return fail(SPCN_E_ARG, "dst must not overlap src");
+    if (mode == 1) SPCN_CHECK(check_ws(ws, ws_bytes, probe_sink_bytes()));
+    DevInfo dev;
+    SPCN_CHECK(dev_info(&dev));
+    hipError_t e = launch_probe(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), static_cast<uint32_t*>(ws),
+                                bytes, mode, dev, stream);
+    if (e != hipSuccess) return hip_fail(e, "spcn_bandwidth_probe launch");
     return SPCN_OK;
 }
 

@@ -114,6 +114,11 @@ hipError_t launch_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles
 // ---- batched persistent normalisation (spcn_batched.hip)
 size_t batched_workspace_bytes(int64_t n_tiles, int64_t total_px);
 int64_t batched_max_tiles();
+// ---- bandwidth reference kernels (spcn_probe.hip)
+size_t probe_sink_bytes();
+hipError_t launch_probe(const uint8_t* src, uint8_t* dst, uint32_t* sink, int64_t n, int mode, const DevInfo& dev,
+                        hipStream_t s);
+
 hipError_t launch_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int64_t total_px,
                                     const float* w_src, const float* w_tgt, const float* scale_tgt,
                                     const float i0_out[3], const ParamsK& pk, float* p99_out,

@@ -177,11 +177,10 @@ SLIDE_H, SLIDE_W, SLIDE_BLOCK = 40000, 50000, 4096
 
 
 def slide_layout(seed: int = 20, height: int = SLIDE_H, width: int = SLIDE_W, block: int = SLIDE_BLOCK,
-                 tissue_slot_frac: float = 0.57, n_unique: int = 4):
-    """Slot plan of the gigapixel slide: a grid of block-sized slots, each either background or one
-    of `n_unique` tissue blocks (with one of 4 flips), cropped at the slide edge.  Returns a list of
-    (y0, x0, hh, ww, kind, flip) with kind = -1 for background, else the tissue block id.
-    With 30% background inside tissue blocks and 57% tissue slots, ~60% of the slide is background."""
+                 tissue_slot_frac: float = 0.57):
+    """Slot plan of the gigapixel slide: a grid of block-sized slots, each tissue or background,
+    cropped at the slide edge.  Returns a list of (y0, x0, hh, ww, tissue) tuples.  With 30%
+    background inside tissue slots and 57% tissue slots, ~60% of the slide is background."""
     rng = np.random.default_rng(seed)
     rows, cols = -(-height // block), -(-width // block)
     plan = []
@@ -189,43 +188,31 @@ def slide_layout(seed: int = 20, height: int = SLIDE_H, width: int = SLIDE_W, bl
         for c in range(cols):
             y0, x0 = r * block, c * block
             hh, ww = min(block, height - y0), min(block, width - x0)
-            tissue = rng.uniform() < tissue_slot_frac
-            kind = int(rng.integers(0, n_unique)) if tissue else -1
-            flip = int(rng.integers(0, 4))
-            plan.append((y0, x0, hh, ww, kind, flip))
+            plan.append((y0, x0, hh, ww, bool(rng.uniform() < tissue_slot_frac)))
     return plan
 
 
-def slide_blocks(seed: int = 20, block: int = SLIDE_BLOCK, n_unique: int = 4, device="cpu"):
-    """Unique tissue blocks and one background block of the slide ((block, block, 3) uint8 each).
-    All tissue blocks share one stain basis (one slide, one staining).  Returns (tissue, bg, W)."""
-    rng = np.random.default_rng(seed + 1000)
-    W = jitter_basis(rng, 5.0)
-    tissue = [make_image(seed + 1 + b, block, block, bg_frac=0.3, W=W, device=device)["img"]
-              for b in range(n_unique)]
-    bg = make_image(seed + 999, block, block, bg_frac=1.0, W=W, device=device)["img"]
-    return tissue, bg, W
+def slide_basis(seed: int = 20) -> np.ndarray:
+    """The stain basis of the slide (one slide, one staining)."""
+    return jitter_basis(np.random.default_rng(seed + 1000), 5.0)
 
 
-def _flip(a: torch.Tensor, flip: int) -> torch.Tensor:
-    dims = [d for d, bit in ((0, 1), (1, 2)) if flip & bit]
-    return torch.flip(a, dims) if dims else a
+def slot_image(plan, k: int, W: np.ndarray, seed: int = 20, device="cpu") -> torch.Tensor:
+    """Pixels (hh, ww, 3) uint8 of slot k: a field of its own seed (seed * 1000 + k), tissue with
+    30% background blobs, or all background."""
+    y0, x0, hh, ww, tissue = plan[k]
+    return make_image(seed * 1000 + k, hh, ww, bg_frac=0.3 if tissue else 1.0, W=W, device=device)["img"]
 
 
-def slot_pixels(tissue, bg, slot) -> torch.Tensor:
-    """uint8 pixels of one slot as a contiguous (hh, ww, 3) tensor."""
-    y0, x0, hh, ww, kind, flip = slot
-    src = bg if kind < 0 else tissue[kind]
-    return _flip(src, flip)[:hh, :ww].contiguous()
-
-
-def assemble_slide(tissue, bg, plan, height: int = SLIDE_H, width: int = SLIDE_W) -> torch.Tensor:
-    """The (height, width, 3) uint8 slide, on the blocks' device."""
-    out = torch.empty((height, width, 3), dtype=torch.uint8, device=bg.device)
-    for slot in plan:
-        y0, x0, hh, ww, kind, flip = slot
-        out[y0:y0 + hh, x0:x0 + ww] = slot_pixels(tissue, bg, slot)
-    return out
+def make_slide(seed: int = 20, height: int = SLIDE_H, width: int = SLIDE_W, block: int = SLIDE_BLOCK, device="cpu"):
+    """The (height, width, 3) uint8 slide, every slot drawn from its own seeded field on `device`.
+    Returns (img, W, plan)."""
+    plan = slide_layout(seed, height, width, block)
+    W = slide_basis(seed)
+    out = torch.empty((height, width, 3), dtype=torch.uint8, device=device)
+    for k, (y0, x0, hh, ww, _) in enumerate(plan):
+        out[y0:y0 + hh, x0:x0 + ww] = slot_image(plan, k, W, seed, device)
+    return out, W, plan
 
 
 def tile_shapes(n_tiles: int = 512, seed: int = 30000, lo: int = 256, hi: int = 2048, step: int = 64):

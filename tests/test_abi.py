@@ -231,3 +231,21 @@ def test_recolor_p99_rejects(lib):
     assert "overlap" in lib._L.spcn_last_error().decode()
     assert call(C.c_void_p(1 << 22), (C.c_float * 3)(255.0, -1.0, 255.0)) == lib.SPCN_E_ARG
     assert "i0_out" in lib._L.spcn_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(mode=2), "mode"),
+    (dict(src=None), "src is NULL"),
+    (dict(dst=None), "dst is NULL"),
+    (dict(n=15), "multiple of 16"),
+    (dict(src=C.c_void_p((1 << 20) + 8)), "aligned"),
+    (dict(dst=C.c_void_p((1 << 20) + 64)), "overlap"),
+    (dict(mode=1, ws=None), "workspace"),
+])
+def test_bandwidth_probe_rejects(lib, kw, frag):
+    args = dict(src=C.c_void_p(1 << 20), dst=C.c_void_p(1 << 24), n=1 << 12, mode=0, ws=C.c_void_p(1 << 26),
+                wsn=1 << 22)
+    args.update(kw)
+    st = lib._L.spcn_bandwidth_probe(args["src"], args["dst"], args["n"], args["mode"], args["ws"], args["wsn"], None)
+    assert st in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
+    assert frag in lib._L.spcn_last_error().decode()

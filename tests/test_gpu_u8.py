@@ -452,3 +452,18 @@ def test_autotune_image_sets_a_measured_choice(S, orc):
         check_normalize("autotuned", out, st, o_out, o_st, o_hist)
     finally:
         autotune.apply(saved)
+
+
+def test_bandwidth_probe(S):
+    """The bandwidth reference kernels: the copy reproduces its source byte for byte (ragged tail of
+    the last tile included), the read pass runs and leaves its source untouched."""
+    g = torch.Generator(device=DEV)
+    g.manual_seed(3)
+    src = torch.randint(0, 256, ((1 << 22) + 48,), dtype=torch.uint8, device=DEV, generator=g)
+    dst = torch.zeros_like(src)
+    S.spcn_bandwidth_probe(src, dst, 0)
+    keep = src.clone()
+    S.spcn_bandwidth_probe(src, None, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    assert torch.equal(src, keep)
