@@ -524,18 +524,37 @@ def main() -> int:
         host = torch.empty((rows, Ww, 3), dtype=torch.uint8, pin_memory=True)
         host.copy_(img[:rows])
         host_out = torch.empty_like(host, pin_memory=True)
-        ws_st = S.workspace(S.workspace_size(S.OP_STREAM_NORMALIZE, Ww, 512, 0), dev)
+        ws_min = S.workspace_size(S.OP_STREAM_NORMALIZE, Ww, 512, 0)
+        n_chunks = (rows + 511) // 512
+        ws_all = ws_min + n_chunks * (((3 * 512 * Ww) + 255) // 256 * 256)   # every chunk resident
         cin, cout = torch.cuda.Stream(), torch.cuda.Stream()
-        ms_st = timed(lambda: S.spcn_normalize_streamed(host, w_fit, w_tgt, scale_tgt, p, chunk_rows=512,
-                                                        host_out=host_out, ws=ws_st, copy_in=cin, copy_out=cout),
-                      max(2, args.steps // 2), 1, stream)
         npx = rows * Ww
+        # the link on its own: pinned host -> device and back, 1.2 GB each way, on a copy stream
+        dbuf = torch.empty_like(host, device=dev)
+        ms_h2d = timed(lambda: dbuf.copy_(host, non_blocking=True), 3, 1, stream)
+        ms_d2h = timed(lambda: host_out.copy_(dbuf, non_blocking=True), 3, 1, stream)
+        del dbuf
+        h2d_peak, d2h_peak = 3 * npx / ms_h2d / 1e6, 3 * npx / ms_d2h / 1e6
+        runs = {}
+        for tag, wsb in (("minimal_workspace", ws_min), ("all_chunks_resident", ws_all)):
+            ws_st = S.workspace(wsb, dev)
+            ms_st = timed(lambda: S.spcn_normalize_streamed(host, w_fit, w_tgt, scale_tgt, p, chunk_rows=512,
+                                                            host_out=host_out, ws=ws_st, copy_in=cin, copy_out=cout),
+                          max(2, args.steps // 2), 1, stream)
+            res_c = S.stream_resident_chunks(rows, Ww, 512, wsb)
+            h2d_bytes = 3 * npx * (2 - res_c / n_chunks)    # resident chunks cross the link once
+            runs[tag] = {"workspace_bytes": int(wsb), "resident_chunks": res_c, "chunks": n_chunks,
+                         "resident_frac": round(res_c / n_chunks, 3), "ms": round(ms_st, 3),
+                         "Mpx_s_pcie_inclusive": round(npx / ms_st / 1e3, 1),
+                         "link_GBs_h2d": round(h2d_bytes / ms_st / 1e6, 1),
+                         "link_GBs_d2h": round(3 * npx / ms_st / 1e6, 1),
+                         "h2d_util": round(h2d_bytes / ms_st / 1e6 / h2d_peak, 3)}
+            del ws_st
         res["extras"]["streamed_host_slide"] = {
-            "rows": rows, "pixels": npx, "chunk_rows": 512, "ms": round(ms_st, 3),
-            "Mpx_s_pcie_inclusive": round(npx / ms_st / 1e3, 1),
-            "link_GBs_h2d": round(6 * npx / ms_st / 1e6, 1), "link_GBs_d2h": round(3 * npx / ms_st / 1e6, 1)}
+            "rows": rows, "pixels": npx, "chunk_rows": 512, "copy_peak_GBs_h2d": round(h2d_peak, 1),
+            "copy_peak_GBs_d2h": round(d2h_peak, 1), **runs}
         log(f"[bench] streamed {res['extras']['streamed_host_slide']}")
-        del host, host_out, ws_st
+        del host, host_out
     if args.extras and args.workload == "slide":
         del img, out
         torch.cuda.empty_cache()

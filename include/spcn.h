@@ -17,7 +17,8 @@
  *     caller's workspace `ws` (size from spcn_workspace_size); it needs no initialisation.
  *   - uint8 images are interleaved RGB (HWC), contiguous, 3 bytes per pixel, 4-byte aligned.
  *   - A stain basis W is 6 floats, 3x2 column-major: W[c + 3*j], c = R,G,B, j = 0 (hematoxylin),
- *     1 (eosin).  Columns should be non-negative and non-parallel (unit norm is not required).
+ *     1 (eosin).  Entries must be non-negative (Eq. 2) and the columns non-parallel (unit norm is
+ *     not required); any other basis is refused on the device (SPCN_FLAG_BASIS, densities 0).
  *   - Densities are planar FP32: H[j*n_px + i].
  *   - lambda follows Eq. (2) literally (no 1/2 on the squared error): a per-pixel penalty
  *     lambda*(h0 + h1) against ||v - W h||^2.
@@ -53,7 +54,8 @@ typedef enum {
 #define SPCN_FLAG_RANGE     2   /* percentile fell in the last histogram bin (after the automatic
                                    retry, if any): raise hist_hi                                   */
 #define SPCN_FLAG_BIN0      4   /* percentile fell in bin 0 (stain absent): scale kept at 1       */
-#define SPCN_FLAG_BASIS     8   /* the basis has a singular Gram matrix: densities set to 0       */
+#define SPCN_FLAG_BASIS     8   /* the basis is unusable (a negative or non-finite entry, or a
+                                   singular Gram matrix): densities set to 0                        */
 #define SPCN_FLAG_SHORT    16   /* basis estimation drew fewer tissue samples than requested      */
 #define SPCN_FLAG_BATCH    32   /* batched call: this tile was skipped (bad descriptor, or total_px
                                    too small for the tiles)                                         */

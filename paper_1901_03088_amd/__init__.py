@@ -15,7 +15,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libspcn.so")
+# SPCN_LIB: another build of the same sources (the sanitizer test loads an instrumented one)
+LIB_PATH = os.environ.get("SPCN_LIB") or os.path.join(HERE, "libspcn.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libspcn.so is not built ({LIB_PATH}); run paper_1901_03088_amd/build.py")

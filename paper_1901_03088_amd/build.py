@@ -43,5 +43,43 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer for the C-ABI layer (argument checks,
+# workspace carving, error reporting): each flag applies to the host compilation only; device code
+# is built as usual.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """A copy of libspcn.so at `out` whose host code in spcn_api.hip is instrumented (the other
+    objects come from the regular build); load it with the clang ASan runtime preloaded
+    (sanitizer_runtime())."""
+    if not all(os.path.exists(os.path.join(OBJ, os.path.basename(s) + ".o"))
+               for s in glob.glob(os.path.join(CSRC, "*.hip"))):
+        build(verbose)
+    api = os.path.join(CSRC, "spcn_api.hip")
+    obj = out + ".api.o"
+    cmd = ["hipcc", *HIPFLAGS, *HOST_SANITIZE, "-c", api, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {api}:\n{r.stderr}")
+    others = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+              if os.path.basename(s) != "spcn_api.hip"]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out, obj, *others,
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """Path of the clang ASan runtime the instrumented library needs preloaded."""
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found under /opt/rocm/llvm")
+    return hits[-1]
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

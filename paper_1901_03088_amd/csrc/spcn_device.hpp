@@ -32,7 +32,7 @@ struct Basis64 {
 };
 
 // Plain sequential FP64 sums (no contraction) so the recheck path rounds like a textbook
-// evaluation of the same expressions.
+// evaluation of the same expressions.  B.ok: finite, non-negative, Gram matrix positive definite.
 __device__ inline void derive_basis(const float* __restrict__ w, float lambda, Basis64& B) {
 #pragma clang fp contract(off)
     for (int i = 0; i < 6; ++i) B.w[i] = (double)w[i];
@@ -42,9 +42,14 @@ __device__ inline void derive_basis(const float* __restrict__ w, float lambda, B
     double g11 = W[3] * W[3]; g11 = g11 + W[4] * W[4]; g11 = g11 + W[5] * W[5];
     double det = g00 * g11 - g01 * g01;
     B.g00 = g00; B.g01 = g01; B.g11 = g11; B.det = det;
-    bool finite = true;
-    for (int i = 0; i < 6; ++i) finite = finite && (W[i] == W[i]) && (W[i] - W[i] == 0.0);
-    B.ok = finite && g00 > 0.0 && g11 > 0.0 && det > 1e-12 * g00 * g11;
+    bool finite = true, nonneg = true;
+    for (int i = 0; i < 6; ++i) {
+        finite = finite && (W[i] == W[i]) && (W[i] - W[i] == 0.0);
+        nonneg = nonneg && W[i] >= 0.0;
+    }
+    // Eq. 2 constrains W >= 0, and the closed form below needs g01 >= 0, which W >= 0 gives: a basis
+    // with a negative entry is outside the method and is refused like a singular one
+    B.ok = finite && nonneg && g00 > 0.0 && g11 > 0.0 && det > 1e-12 * g00 * g11;
     double id = B.ok ? 1.0 / det : 0.0;
     double ig00 = B.ok ? 1.0 / g00 : 0.0, ig11 = B.ok ? 1.0 / g11 : 0.0;
     B.half_lambda = 0.5 * (double)lambda;

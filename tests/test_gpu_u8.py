@@ -348,6 +348,26 @@ def test_degenerate_basis_flag(S):
     assert (h == 0).all()
 
 
+@pytest.mark.parametrize("W", [
+    [[0.65, -0.05], [0.70, 0.99], [0.29, 0.11]],    # a negative entry with a positive Gram cross term
+    [[0.9, -0.3], [0.1, 0.9], [0.4, 0.3]],          # negative cross term g01 < 0
+])
+def test_negative_basis_refused(S, W):
+    """Eq. 2 requires W >= 0 (the closed-form density solve relies on it): a basis with a negative
+    entry is refused on the device -- SPCN_FLAG_BASIS, every density 0, the normalisation leaves
+    every pixel unscaled -- instead of returning densities of another problem."""
+    img = synth.make_image(4, 64, 96, device=DEV)["img"]
+    W = np.array(W)
+    h, hist, p99, flags = gpu_densities(S, img, W, S.params())
+    assert (flags & S.FLAG_BASIS).all()
+    assert (h == 0).all()
+    tgt = synth.make_image(1, 64, 64, device=DEV)
+    out, st = S.spcn_normalize(img, S.as_basis(W, DEV), S.as_basis(tgt["W"], DEV),
+                               torch.tensor([1.0, 1.0], device=DEV), S.params())
+    torch.cuda.synchronize()
+    assert (st["flags"].cpu().numpy() & S.FLAG_BASIS).all()
+
+
 def test_config1_densities_full_size(S, orc):
     """8192 x 8192 (67 Mpixel): spcn_densities with the FP32 density planes, in the benchmark's launch
     shape (the fused pass 1); every density of both planes within 1e-4 max(|h|, 1) of the oracle's
