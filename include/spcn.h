@@ -362,8 +362,10 @@ spcn_status spcn_normalize_f32(const float* x, int64_t n, int64_t height, int64_
  * density Jacobian comes from the active set's KKT system (h_F = G_FF^-1 (W_F^T v - lambda/2));
  * the percentile contributes through the density of the selected pixel sel_idx.
  *   p99, sel_idx, flags: the forward's saved outputs
- *   grad_x [n][3][h][w]; grad_w_tgt [n][6] per sample; grad_scale [n][2] per sample
- *   (sum over samples for a shared parameter). */
+ *   grad_x [n][3][h][w]
+ *   grad_w_tgt  [n][6] per sample when w_tgt_stride > 0; [6] when the basis is shared by the batch
+ *               (w_tgt_stride 0): the sum of the per-sample gradients, taken in sample order in FP64
+ *   grad_scale  likewise: [n][2] when scale_stride > 0, else [2], the sum over samples. */
 spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, int64_t width,
                                     const float* w_src, int64_t w_src_stride, const float* w_tgt,
                                     int64_t w_tgt_stride, const float* scale_tgt,

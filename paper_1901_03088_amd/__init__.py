@@ -557,7 +557,8 @@ def spcn_normalize_f32(x: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor
 
 def spcn_normalize_backward(x: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.Tensor, scale_tgt: torch.Tensor,
                             saved: dict, grad_y: torch.Tensor, p: spcn_params | None = None, i0_out=None, ws=None):
-    """Adjoint of spcn_normalize_f32.  Returns (grad_x, grad_w_tgt (n, 6), grad_scale (n, 2)) per sample."""
+    """Adjoint of spcn_normalize_f32.  Returns (grad_x, grad_w_tgt, grad_scale): per sample ((n, 6), (n, 2))
+    for per-sample parameters, or ((6,), (2,)) summed over the batch (by the library) for shared ones."""
     _dev(x, torch.float32, "x")
     _dev(grad_y, torch.float32, "grad_y")
     n, _, H, W_ = (int(v) for v in x.shape)
@@ -565,8 +566,8 @@ def spcn_normalize_backward(x: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.T
     p = p or float_params()
     dev = x.device
     gx = torch.empty_like(x)
-    gw = torch.empty((n, 6), dtype=torch.float32, device=dev)
-    gs = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    gw = torch.empty((n, 6) if st_ else (6,), dtype=torch.float32, device=dev)
+    gs = torch.empty((n, 2) if ss else (2,), dtype=torch.float32, device=dev)
     if ws is None:
         ws = workspace(workspace_size(OP_BACKWARD_F32, H * W_, n), dev)
     wsp, wsn = _ws_ptr(ws)
@@ -581,7 +582,7 @@ def spcn_normalize_backward(x: torch.Tensor, w_src: torch.Tensor, w_tgt: torch.T
 class SPCNNormalize(torch.autograd.Function):
     """y = SPCN(x; W_src, W_tgt, scale_tgt) on float images, differentiable in x, W_tgt and scale_tgt
     (W_src is treated as a constant).  Shapes as in spcn_normalize_f32; a (6,) W_tgt or (2,) scale
-    shared by the batch receives the sum of the per-sample gradients."""
+    shared by the batch receives the sum of the per-sample gradients (summed by the library)."""
 
     @staticmethod
     def forward(ctx, x, w_src, w_tgt, scale_tgt, p=None, i0_out=None):
@@ -597,10 +598,6 @@ class SPCNNormalize(torch.autograd.Function):
         x, w_src, w_tgt, scale_tgt, p99, sel, flags = ctx.saved_tensors
         gx, gw, gs = spcn_normalize_backward(x, w_src, w_tgt, scale_tgt, {"p99": p99, "sel": sel, "flags": flags},
                                              gy.contiguous(), ctx.p, ctx.i0_out)
-        if w_tgt.dim() == 1:
-            gw = gw.sum(0)
-        if scale_tgt.dim() == 1:
-            gs = gs.sum(0)
         return gx, None, gw, gs, None, None
 
 

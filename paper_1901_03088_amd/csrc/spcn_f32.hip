@@ -21,7 +21,8 @@
 //                 across threads and workgroups);
 //   k_bw_reduce   per sample: ordered sums -> dWt, dS = ds / P; the percentile's adjoint
 //                 Pbar_j = -(s_j / P_j) ds_j enters through the selected pixel's density (added to
-//                 its input gradient).
+//                 its input gradient);
+//   k_bw_shared   a target basis or scale shared by the batch: the sum over samples.
 #include "spcn_internal.h"
 #include "spcn_device.hpp"
 
@@ -441,6 +442,7 @@ struct BwArgs {
     const float* gy;
     float* gx; float* gw; float* gs;
     double* partial;        // [n][blocks][8]
+    double* per_sample;     // [n][8]: each sample's dWt (6) and dscale (2), for parameters shared by the batch
 };
 
 struct BwConsts {
@@ -564,7 +566,10 @@ __global__ __launch_bounds__(64) void k_bw_reduce(BwArgs a, int nblk) {
     if (threadIdx.x != 0) return;
     double t[8];
     for (int q = 0; q < 8; ++q) t[q] = s_t[q];
-    for (int i = 0; i < 6; ++i) a.gw[6 * s + i] = (float)t[i];
+    for (int i = 0; i < 6; ++i) {
+        if (a.w_tgt_stride) a.gw[6 * s + i] = (float)t[i];
+        else a.per_sample[8 * s + i] = t[i];
+    }
     F32Basis F;
     f32_basis(a.w_src + s * a.w_src_stride, a.lambda, a.i0, a.log2i0, F);
     BwConsts K;
@@ -575,7 +580,9 @@ __global__ __launch_bounds__(64) void k_bw_reduce(BwArgs a, int nblk) {
         const int fl = a.flags[2 * s + j];
         const bool scaled = !(fl & (SPCN_FLAG_NO_TISSUE | SPCN_FLAG_BIN0));
         const float P = a.p99[2 * s + j];
-        a.gs[2 * s + j] = scaled ? (float)(t[6 + j] / (double)P) : 0.0f;
+        const double gsj = scaled ? t[6 + j] / (double)P : 0.0;
+        if (a.scale_stride) a.gs[2 * s + j] = (float)gsj;
+        else a.per_sample[8 * s + 6 + j] = gsj;
         if (!scaled) continue;
         // the percentile is the density of the selected pixel: its adjoint joins that pixel's hbar
         const double Pbar = -((double)K.s[j] / (double)P) * t[6 + j];
@@ -587,6 +594,26 @@ __global__ __launch_bounds__(64) void k_bw_reduce(BwArgs a, int nblk) {
         pixel_vjp(F, p, j == 0 ? (float)Pbar : 0.0f, j == 1 ? (float)Pbar : 0.0f, x[i], x[a.n_px + i],
                   x[2 * a.n_px + i], g);
         for (int c = 0; c < 3; ++c) gx[c * a.n_px + i] += g[c];
+    }
+}
+
+// A target basis or scale shared by the whole batch (stride 0) gets the sum of the per-sample
+// gradients in FP64, in a fixed association (deterministic): thread t of quantity q's 64 threads
+// sums samples t, t + 64, ... in order, then the 64 partial sums are added pairwise in LDS.
+__global__ __launch_bounds__(512) void k_bw_shared(BwArgs a) {
+    __shared__ double s_v[8][64];
+    const int q = threadIdx.x >> 6, t = threadIdx.x & 63;
+    double v = 0.0;
+    for (int64_t s = t; s < a.n; s += 64) v += a.per_sample[8 * s + q];
+    s_v[q][t] = v;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if (t < h) s_v[q][t] += s_v[q][t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (q < 6 && !a.w_tgt_stride) a.gw[q] = (float)s_v[q][0];
+        if (q >= 6 && !a.scale_stride) a.gs[q - 6] = (float)s_v[q][0];
     }
 }
 
@@ -613,7 +640,7 @@ size_t f32_forward_workspace_bytes(int64_t n_px, int64_t n) {
 size_t f32_backward_workspace_bytes(int64_t n_px, int64_t n) {
     if (n_px <= 0 || n <= 0) return 0;
     (void)n_px;
-    return a256((size_t)n * BLOCKS_PER_SAMPLE_MAX * 8 * sizeof(double));
+    return a256((size_t)n * BLOCKS_PER_SAMPLE_MAX * 8 * sizeof(double)) + a256((size_t)n * 8 * sizeof(double));
 }
 
 hipError_t launch_forward_f32(const F32Args& g, const ParamsK& pk, float* y, float* p99_out, float* scale_out,
@@ -665,11 +692,14 @@ hipError_t launch_backward_f32(const F32Args& g, const ParamsK& pk, const float*
     a.p99 = p99; a.sel = sel_idx; a.flags = flags; a.gy = grad_y;
     a.gx = grad_x; a.gw = grad_w_tgt; a.gs = grad_scale;
     a.partial = static_cast<double*>(ws);
+    a.per_sample = reinterpret_cast<double*>(static_cast<uint8_t*>(ws) +
+                                             a256((size_t)g.n * BLOCKS_PER_SAMPLE_MAX * 8 * sizeof(double)));
     const int bps = blocks_per_sample(g.n_px, g.n, dev);
     const bool v4 = g.n_px % 4 == 0 && aligned16(g.x) && aligned16(grad_y) && aligned16(grad_x);
     if (v4) hipLaunchKernelGGL(k_bw_main<4>, dim3(bps, (unsigned)g.n), dim3(FT), 0, s, a);
     else hipLaunchKernelGGL(k_bw_main<1>, dim3(bps, (unsigned)g.n), dim3(FT), 0, s, a);
     hipLaunchKernelGGL(k_bw_reduce, dim3((unsigned)g.n), dim3(64), 0, s, a, bps);
+    if (g.w_tgt_stride == 0 || g.scale_stride == 0) hipLaunchKernelGGL(k_bw_shared, dim3(1), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 

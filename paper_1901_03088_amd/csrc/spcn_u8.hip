@@ -78,7 +78,8 @@ __global__ __launch_bounds__(256) void k_u8_setup(uint64_t* hist, U8Ctl* ctl, co
 
 // Eq. 3's percentile of each stain from the histogram; a stain whose percentile lies in the open
 // last bin gets twice its range (up to 2^8) and the histogram is cleared for a second pass 1.
-__global__ __launch_bounds__(256) void k_range_check(uint64_t* hist, U8Ctl* ctl, double q) {
+// range_out (or NULL) receives the settled range.
+__global__ __launch_bounds__(256) void k_range_check(uint64_t* hist, U8Ctl* ctl, double q, float* range_out) {
     __shared__ FinalShared F;
     __shared__ int bits;
     const float hh[2] = {ctl->range[0], ctl->range[1]};
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(256) void k_range_check(uint64_t* hist, U8Ctl* ctl,
             ctl->retry = bits;
         }
     }
+    if (range_out && threadIdx.x < 2) range_out[threadIdx.x] = (bits >> threadIdx.x & 1) ? 2.0f * hh[threadIdx.x] : hh[threadIdx.x];
 }
 
 __device__ __forceinline__ int retry_flag(const int32_t* retry, int j) {
@@ -376,21 +378,23 @@ hipError_t launch_count(const uint8_t* img, int64_t n_px, const float* w, const 
 // densities do not depend on the range).  The range and retry words are in ctl.
 static hipError_t launch_hist_checked(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
                                       uint64_t* hist, void* ctl_ws, const DevInfo& dev, hipStream_t s,
-                                      float* h_out = nullptr) {
+                                      float* h_out = nullptr, float* range_out = nullptr) {
     U8Ctl* ctl = ctl_of(ctl_ws);
     hipLaunchKernelGGL(k_u8_setup, dim3(1), dim3(256), 0, s, hist, ctl, pk.hist_hi_dev, pk.hist_hi[0], pk.hist_hi[1]);
     hipError_t e = launch_pass1(img, n_px, w, pk, hist, ctl->range, nullptr, dev, s, h_out);
     if (e != hipSuccess || !pk.auto_range) return e;
-    hipLaunchKernelGGL(k_range_check, dim3(1), dim3(256), 0, s, hist, ctl, pk.q64);
+    hipLaunchKernelGGL(k_range_check, dim3(1), dim3(256), 0, s, hist, ctl, pk.q64, range_out);
     return launch_pass1(img, n_px, w, pk, hist, ctl->range, &ctl->retry, dev, s);
 }
 
 hipError_t launch_densities(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk,
                             float* h_out, uint64_t* hist, float* p99_out, int32_t* flags_out, float* range_out,
                             void* ctl_ws, const DevInfo& dev, hipStream_t s) {
-    hipError_t e = launch_hist_checked(img, n_px, w, pk, hist, ctl_ws, dev, s, h_out);
+    // the range check reports the settled range itself when the percentile is not asked for
+    const bool range_only = pk.auto_range && range_out && !p99_out && !flags_out;
+    hipError_t e = launch_hist_checked(img, n_px, w, pk, hist, ctl_ws, dev, s, h_out, range_only ? range_out : nullptr);
     if (e != hipSuccess) return e;
-    if (p99_out || flags_out || range_out) {
+    if (!range_only && (p99_out || flags_out || range_out)) {
         U8Ctl* ctl = ctl_of(ctl_ws);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, hist, pk.q64, ctl->range, pk.hist_hi[0],
                            pk.hist_hi[1], &ctl->retry, w, pk.lambda, p99_out, flags_out, range_out);

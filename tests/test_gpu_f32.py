@@ -76,7 +76,8 @@ def run_case(S, orc, n, size, scale_shared=True, lam=0.01):
         torch.rand((n, 2), device=DEV) * 0.5 + 0.75
     y, saved = S.spcn_normalize_f32(x, ws, wt, sc, p)
     gy = 2.0 * wts * y
-    gx, gw, gs = S.spcn_normalize_backward(x, ws, wt, sc, saved, gy, p)
+    # per-sample gradients (a shared scale given once per sample: same forward, gradients not summed)
+    gx, gw, gs = S.spcn_normalize_backward(x, ws, wt, sc.expand(n, 2).contiguous(), saved, gy, p)
     torch.cuda.synchronize()
     xs_all = x.cpu().numpy().astype(np.float64)
     for i in range(n):
@@ -106,7 +107,7 @@ def test_f32_config4_shape(S, orc):
     sc = torch.tensor([0.9, 1.1], dtype=torch.float32, device=DEV)
     y, saved = S.spcn_normalize_f32(x, ws, wt, sc, p)
     gy = 2.0 * wts * y
-    gx, gw, gs = S.spcn_normalize_backward(x, ws, wt, sc, saved, gy, p)
+    gx, gw, gs = S.spcn_normalize_backward(x, ws, wt, sc.expand(n, 2).contiguous(), saved, gy, p)
     torch.cuda.synchronize()
     sci = sc.cpu().numpy().astype(np.float64)
     grad_samples = set(np.random.default_rng(4).choice(n, 4, replace=False).tolist())
@@ -132,6 +133,13 @@ def test_autograd_function(S):
     torch.cuda.synchronize()
     y2, saved = S.spcn_normalize_f32(x, ws, wt.detach(), sc.detach(), p)
     gx, gw, gs = S.spcn_normalize_backward(x, ws, wt.detach(), sc.detach(), saved, 2.0 * wts * y2, p)
-    assert torch.allclose(xr.grad, gx)
-    assert torch.allclose(wt.grad, gw.sum(0), rtol=1e-5, atol=1e-6 * float(gw.abs().max()))
-    assert torch.allclose(sc.grad, gs.sum(0), rtol=1e-5, atol=1e-6 * float(gs.abs().max()))
+    assert gw.shape == (6,) and gs.shape == (2,)      # shared parameters: summed by the library
+    assert torch.equal(xr.grad, gx) and torch.equal(wt.grad, gw) and torch.equal(sc.grad, gs)
+    # the same parameters given per sample: per-sample gradients whose sum is the shared one
+    n = x.shape[0]
+    wt_n, sc_n = wt.detach().expand(n, 6).contiguous(), sc.detach().expand(n, 2).contiguous()
+    gx_n, gw_n, gs_n = S.spcn_normalize_backward(x, ws, wt_n, sc_n, saved, 2.0 * wts * y2, p)
+    assert gw_n.shape == (n, 6) and gs_n.shape == (n, 2)
+    assert torch.equal(gx_n, gx)
+    assert torch.allclose(gw, gw_n.double().sum(0).float(), rtol=1e-6, atol=1e-7 * float(gw_n.abs().max()))
+    assert torch.allclose(gs, gs_n.double().sum(0).float(), rtol=1e-6, atol=1e-7 * float(gs_n.abs().max()))
