@@ -470,15 +470,21 @@ def main() -> int:
         # what plain library kernels reach on the slide's own buffers: a copy of the input into the
         # output (6 GB read + 6 GB written, pass 2's traffic) and a read-only reduction of the input
         # (6 GB read, pass 1's traffic)
-        ms_copy = timed(lambda: S.spcn_bandwidth_probe(img, out, 0), args.steps, args.warmup, stream)
+        # (streaming cache policy as the passes use, and the default policy)
         ws_probe = S.workspace(S.workspace_size(S.OP_BANDWIDTH_PROBE), dev)
-        ms_read = timed(lambda: S.spcn_bandwidth_probe(img, None, 1, ws=ws_probe), args.steps, args.warmup, stream)
+        ms = {}
+        for mode in range(4):
+            dst = out if mode in (0, 2) else None
+            ms[mode] = timed(lambda: S.spcn_bandwidth_probe(img, dst, mode, ws=ws_probe), args.steps, args.warmup,
+                             stream)
         ms_tcopy = timed(lambda: out.copy_(img), args.steps, args.warmup, stream)
+        def ceil(mode, what, per_px):
+            return {"kernel": f"k_probe {what} (spcn_bandwidth_probe mode {mode})", "ms": round(ms[mode], 4),
+                    "GBs": round(per_px * n_px / (ms[mode] / 1e3) / 1e9, 1)}
         res["ceilings"] = {
-            "copy": {"kernel": "k_probe copy (spcn_bandwidth_probe mode 0)", "ms": round(ms_copy, 4),
-                     "GBs": round(6.0 * n_px / (ms_copy / 1e3) / 1e9, 1)},
-            "read": {"kernel": "k_probe read (spcn_bandwidth_probe mode 1)", "ms": round(ms_read, 4),
-                     "GBs": round(3.0 * n_px / (ms_read / 1e3) / 1e9, 1)},
+            "copy": ceil(0, "copy, streaming policy", 6.0), "read": ceil(1, "read, streaming policy", 3.0),
+            "copy_default_policy": ceil(2, "copy, default policy", 6.0),
+            "read_default_policy": ceil(3, "read, default policy", 3.0),
             "torch_copy": {"kernel": "torch copy_ uint8", "ms": round(ms_tcopy, 4),
                            "GBs": round(6.0 * n_px / (ms_tcopy / 1e3) / 1e9, 1)}}
         log(f"[bench] ceilings {res['ceilings']}")

@@ -378,10 +378,12 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
 /* Memory-bandwidth reference for the roofline of the two passes (measurement only; it computes
  * nothing of the method): mode 0 copies `bytes` from src to dst (pass 2's traffic), mode 1 reads
  * them and XOR-reduces into the caller's workspace (pass 1's traffic), both grid-stride with
- * 16-byte accesses in the recolour pass's launch shape.
- *   src, dst  device buffers, 16-byte aligned, not overlapping (dst unused in mode 1)
+ * 16-byte accesses in the recolour pass's launch shape and with the passes' streaming cache policy
+ * (non-temporal loads, non-temporal device-scope stores); modes 2 and 3 are the copy and the read
+ * with the default cache policy.
+ *   src, dst  device buffers, 16-byte aligned, not overlapping (dst unused in modes 1 and 3)
  *   bytes     a multiple of 16 in [16, 2^40]
- *   ws        mode 1: spcn_workspace_size(SPCN_OP_BANDWIDTH_PROBE, 0, 0, 0) bytes; mode 0: unused */
+ *   ws        modes 1, 3: spcn_workspace_size(SPCN_OP_BANDWIDTH_PROBE, 0, 0, 0) bytes; else unused */
 spcn_status spcn_bandwidth_probe(const void* src, void* dst, int64_t bytes, int32_t mode, void* ws,
                                  size_t ws_bytes, hipStream_t stream);
 

@@ -504,9 +504,10 @@ def spcn_normalize_batched(tiles: torch.Tensor, n_tiles: int, total_px: int, w_s
 
 
 def spcn_bandwidth_probe(src: torch.Tensor, dst: torch.Tensor | None, mode: int, ws=None):
-    """Bandwidth reference: mode 0 copies src's bytes into dst, mode 1 only reads them."""
+    """Bandwidth reference: mode 0 copies src's bytes into dst, mode 1 only reads them, both with the
+    passes' streaming cache policy; modes 2 and 3 the same with the default policy."""
     n = src.numel() * src.element_size()
-    if ws is None and mode == 1:
+    if ws is None and mode in (1, 3):
         ws = workspace(workspace_size(OP_BANDWIDTH_PROBE), src.device)
     wsp, wsn = _ws_ptr(ws) if ws is not None else (None, 0)
     _check(_L.spcn_bandwidth_probe(_ptr(src), _ptr(dst), int(n), int(mode), wsp, wsn, _stream()),

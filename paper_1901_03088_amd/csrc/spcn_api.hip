@@ -578,15 +578,17 @@ spcn_status spcn_normalize_backward(const float* x, int64_t n, int64_t height, i
 
 spcn_status spcn_bandwidth_probe(const void* src, void* dst, int64_t bytes, int32_t mode, void* ws, size_t ws_bytes,
                                  hipStream_t stream) {
-    if (mode != 0 && mode != 1) return fail(SPCN_E_ARG, "mode = %d must be 0 (copy) or 1 (read)", (int)mode);
+    if (mode < 0 || mode > 3)
+        return fail(SPCN_E_ARG, "mode = %d must be 0 or 2 (copy) or 1 or 3 (read)", (int)mode);
+    const bool copy = mode == 0 || mode == 2;
     if (!src) return fail(SPCN_E_ARG, "src is NULL");
-    if (mode == 0 && !dst) return fail(SPCN_E_ARG, "dst is NULL");
+    if (copy && !dst) return fail(SPCN_E_ARG, "dst is NULL");
     if (bytes < 16 || (bytes & 15) || bytes > ((int64_t)1 << 40))
         return fail(SPCN_E_ARG, "bytes = %lld must be a multiple of 16 in [16, 2^40]", (long long)bytes);
-    if ((((uintptr_t)src) | (mode == 0 ? (uintptr_t)dst : 0)) & 15) return fail(SPCN_E_ARG, "src and dst must be 16-byte aligned");
-    if (mode == 0 && (const uint8_t*)src < (const uint8_t*)dst + bytes && (const uint8_t*)dst < (const uint8_t*)src + bytes)
+    if ((((uintptr_t)src) | (copy ? (uintptr_t)dst : 0)) & 15) return fail(SPCN_E_ARG, "src and dst must be 16-byte aligned");
+    if (copy && (const uint8_t*)src < (const uint8_t*)dst + bytes && (const uint8_t*)dst < (const uint8_t*)src + bytes)
         return fail(SPCN_E_ARG, "dst must not overlap src");
-    if (mode == 1) SPCN_CHECK(check_ws(ws, ws_bytes, probe_sink_bytes()));
+    if (!copy) SPCN_CHECK(check_ws(ws, ws_bytes, probe_sink_bytes()));
     DevInfo dev;
     SPCN_CHECK(dev_info(&dev));
     hipError_t e = launch_probe(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), static_cast<uint32_t*>(ws),

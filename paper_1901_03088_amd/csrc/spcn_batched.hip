@@ -267,7 +267,7 @@ __device__ void p1_item(P1FLds<true>& S, const P1RunArgs& a, int t, uint32_t ite
     }
     uint32_t* words = reinterpret_cast<uint32_t*>(S.mem);
     for (int i = tid; i < kHistBins * 2 * Y::kCols; i += P1_THREADS)
-        words[(Y::kHRegion + (uint32_t)(i / (2 * Y::kCols)) * 256u + Y::kH) / 4 + (i % (2 * Y::kCols))] = 0u;
+        words[Y::hist_word(i / (2 * Y::kCols), i % (2 * Y::kCols))] = 0u;
     if (tid == 0) { S.B = a.w.basis[t]; S.shift = I.shift; }
     __syncthreads();
     P1Params pp = a.pp;                        // the tile's range
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(P2_THREADS, 3) void k_tiles_p2(P2RunArgs a) {
         const __amdgpu_buffer_rsrc_t rs = chunk_rsrc(cw.t >= 0 ? a.tiles[cw.t].src : nullptr, cw.u0, cw.cnt);
 #pragma unroll
         for (int j = 0; j < P2_UNROLL; ++j)
-            cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * P2_THREADS), 0, 0);
+            cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * P2_THREADS), 0, kLoadStream);
     }
     int staged = -1;
     for (int64_t k = 0; cw.t >= 0; ++k) {     // workgroup-uniform
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(P2_THREADS, 3) void k_tiles_p2(P2RunArgs a) {
             const __amdgpu_buffer_rsrc_t rn = chunk_rsrc(nw.t >= 0 ? a.tiles[nw.t].src : nullptr, nw.u0, nw.cnt);
 #pragma unroll
             for (int j = 0; j < P2_UNROLL; ++j)
-                nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * P2_THREADS), 0, 0);
+                nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * P2_THREADS), 0, kLoadStream);
         }
         if (cw.t != staged) {                  // the tile's tables and constants
             __syncthreads();
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(P2_THREADS, 3) void k_tiles_p2(P2RunArgs a) {
             float h0[4], h1[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) p2_densities(T2, 0u, K, px[q][0], px[q][1], px[q][2], h0[q], h1[q]);
-            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (tid + j * P2_THREADS), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (tid + j * P2_THREADS), 0, kStoreStream);
         }
         const TileInfo& I = a.w.info[cw.t];
         if (cw.last && tid == 0 && I.tail && !I.bad)

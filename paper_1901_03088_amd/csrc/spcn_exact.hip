@@ -167,12 +167,9 @@ template <bool U16>
 __device__ __forceinline__ void refine_units(const P1FLds<true>& S, const P1Params& pp, const P1FLane& L,
                                              const u32x3 (&cur)[RF_UNROLL], int lb0, int cnt, int nthreads, int kb0,
                                              int kb1, unsigned long long* t0, unsigned long long* t1) {
-    using Y = P1FLayout<true>;
     const int u = U16 ? 16 : S.shift;
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(u);
-    const char* base = reinterpret_cast<const char*>(S.mem);
-    auto rd = [&](uint32_t addr) -> int4 { return *reinterpret_cast<const int4*>(base + addr); };
     uint64_t near_waves = 0;
 #pragma unroll
     for (int j = 0; j < RF_UNROLL; ++j) {
@@ -186,20 +183,14 @@ __device__ __forceinline__ void refine_units(const P1FLds<true>& S, const P1Para
         const int32_t darkest = min(min(sum[0], sum[1]), min(sum[2], sum[3]));
         const uint64_t valid_lanes = __ballot(valid);
         if (valid && darkest < thr) {
-            const uint32_t aR[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(0)), __builtin_amdgcn_perm(X, L.la, perm_sel(3)),
-                                    __builtin_amdgcn_perm(Y0, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
-            const uint32_t aG[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(1)), __builtin_amdgcn_perm(Y0, L.la, perm_sel(0)),
-                                    __builtin_amdgcn_perm(Y0, L.la, perm_sel(3)), __builtin_amdgcn_perm(Z, L.la, perm_sel(2))};
-            const uint32_t aB[4] = {__builtin_amdgcn_perm(X, L.lb, perm_sel(2)), __builtin_amdgcn_perm(Y0, L.lb, perm_sel(1)),
-                                    __builtin_amdgcn_perm(Z, L.lb, perm_sel(0)), __builtin_amdgcn_perm(Z, L.lb, perm_sel(3))};
+            int32_t ys0[4], ys1[4];
+            p1f_unit_sums(S, L, X, Y0, Z, ys0, ys1);
             // colour index (R | G << 8 | B << 16) of each pixel from the unit's dwords
             const uint32_t col[4] = {X & 0xFFFFFFu, __builtin_amdgcn_perm(Y0, X, 0x0c050403u),
                                      __builtin_amdgcn_perm(Z, Y0, 0x0c040302u), Z >> 8};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int4 a = rd(aR[q]), b = rd(aG[q] + Y::kG), c = rd(aB[q] + Y::kB);
-                const int32_t y0 = min(a.x + b.x + c.x, a.y + b.y + c.y);
-                const int32_t y1 = min(a.z + b.z + c.z, a.w + b.w + c.w);
+                const int32_t y0 = ys0[q], y1 = ys1[q];
                 const uint64_t white = __ballot(sum[q] >= thr);
                 const uint64_t nr = __ballot(p1f_near(y0, nmask)) | __ballot(p1f_near(y1, nmask));
                 near_waves |= nr & ~white & valid_lanes;
@@ -248,14 +239,14 @@ __device__ void refine_tiles(const P1FLds<true>& S, const RefineArgs& a, int kb0
     const __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
     u32x3 cur[RF_UNROLL];
 #pragma unroll
-    for (int j = 0; j < RF_UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * RF_THREADS), 0, 0);
+    for (int j = 0; j < RF_UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * RF_THREADS), 0, kLoadStream);
     for (; t < n_tiles; t += gridDim.x) {
         int64_t pn = ph + a.step;
         if (pn >= n_tiles) pn -= n_tiles;
         const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);
         u32x3 nxt[RF_UNROLL];
 #pragma unroll
-        for (int j = 0; j < RF_UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * RF_THREADS), 0, 0);
+        for (int j = 0; j < RF_UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * RF_THREADS), 0, kLoadStream);
         const int cnt = (int)min(tu, a.units - ph * tu);
         refine_units<U16>(S, a.pp, L, cur, tid, cnt, RF_THREADS, kb0, kb1, t0, t1);
 #pragma unroll

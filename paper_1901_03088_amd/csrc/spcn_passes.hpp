@@ -16,9 +16,10 @@
 // sums are exact, every entry is within 1/2 unit of its FP64 value, and a pixel whose value lies
 // within kGuardUnits of a bin edge is re-solved in FP64 before it is counted.  Each 16-byte entry is
 // replicated COPIES times and interleaved (entry k, copy r at (k * COPIES + r) * 16 bytes); lane l
-// reads copy l % COPIES, so the 8 lanes that share an LDS cycle for 16-byte reads hit distinct banks
-// whatever their intensities.  The histogram keeps one private column per lane % COLS, so lanes that
-// share an LDS cycle never increment the same word.
+// reads copy l % COPIES.  gfx950 serves 16-byte LDS reads 16 lanes per cycle (64 banks), so with
+// fewer than 16 copies lanes l and l + COPIES of a cycle meet in the same banks unless they read the
+// same entry.  The histogram keeps one private column per lane % COLS; LDS atomics are served 16 lanes
+// per cycle, so 16 columns keep the lanes of a cycle in distinct banks.
 #pragma once
 
 #include "spcn_device.hpp"
@@ -31,6 +32,12 @@ namespace spcn {
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufDword3 = 0x00020000;   // raw (untyped) buffer, gfx9-family descriptor word 3
+// Cache policy of the streaming accesses (the cache-policy operand of the buffer instructions).
+// Each pass reads the image once and writes its output once, so loads are non-temporal (nt) and
+// stores non-temporal at device scope (sc1 nt): on a 6 GB buffer this takes a read-only sweep from
+// 0.96 to 0.86 ms and a copy from 2.29 to 2.14 ms against the default policy.
+constexpr int kLoadStream = 2;
+constexpr int kStoreStream = 18;
 
 // Buffer resource over `units` 12-byte units starting at unit `unit0` of `base`.  Every argument
 // must be the same in all lanes of the wavefront (a workgroup's chunk): the fields are moved to
@@ -171,12 +178,12 @@ __device__ void p1_chunk(P1Lds<COPIES, COLS>& S, const P1Params& pp, __amdgpu_bu
     const int stride = nthreads * UNROLL;
     u32x3 cur[UNROLL];
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
     for (int lb = tid; lb < cnt; lb += stride) {
         u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j)   // prefetch; past the chunk the loads return zeros
-            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb + stride + j * nthreads), 0, 0);
+            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb + stride + j * nthreads), 0, kLoadStream);
         bool any_near = false;
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) {
@@ -277,8 +284,13 @@ __device__ void p1_merge(P1Lds<COPIES, COLS>& S, unsigned long long* ghist) {
 // The same exact counting with a table layout chosen so that every LDS address is one v_perm_b32
 // away from the pixel's dword: slot k (256 B) belongs to byte value k.  Two layouts:
 //   wide (two 64 KB regions, 8 table copies, 16 histogram columns):
-//     region 0: R entry copy r at r*16, G entry copy r at 128 + r*16                (r = lane & 7)
-//     region 1: B entry copy r at r*16; histogram words of bin k at 128 + j*64 + col*4
+//     region 0: R entry copies in bank groups 0..7 (16 B each), G copies in groups 8..15
+//     region 1: B copies in groups 4..11; histogram of bin k: stain 0 words col*4 (groups 0..3),
+//               stain 1 words 192 + col*4 (groups 12..15)
+//   A lane reads its pixel's three entries in a lane-dependent order and bank group (P1FLane's
+//   schedule) such that the 16 lanes of every LDS cycle use 16 distinct bank groups: no bank
+//   conflicts with 8 copies, where a fixed (R, G, B) order would meet pairwise in 8 groups.  The
+//   sums are the same integer sums in another order.
 //   narrow (one 64 KB region, 4 copies, 8 columns; two workgroups fit on a CU):
 //     R copy r at r*16, G at 64 + r*16, B at 128 + r*16, histogram at 192 + j*32 + col*4  (r = lane & 3)
 // An address is (value << 8) | (region << 16) | lane bits; the perm takes the value byte from the
@@ -297,10 +309,14 @@ struct P1FLayout {
     static constexpr uint32_t kBytes = WIDE ? 2u * kHistBins * 256u : kHistBins * 256u;
     static constexpr uint32_t kG = WIDE ? 128u : 64u;              // G entries within the slot
     static constexpr uint32_t kBRegion = WIDE ? 0x10000u : 0u;     // region of the B entries
-    static constexpr uint32_t kB = WIDE ? 0u : 128u;               // B entries within the slot
+    static constexpr uint32_t kB = WIDE ? 64u : 128u;              // B entries within the slot
     static constexpr uint32_t kHRegion = WIDE ? 0x10000u : 0u;     // region of the histogram
-    static constexpr uint32_t kH = WIDE ? 128u : 192u;             // histogram words within the slot
-    static constexpr uint32_t kStain1 = 4u * kCols;                // stain 1 after stain 0's columns
+    static constexpr uint32_t kH = WIDE ? 0u : 192u;               // histogram words within the slot
+    static constexpr uint32_t kStain1 = WIDE ? 192u : 4u * kCols;  // stain 1's columns after stain 0's
+    // word index of histogram word i (0 .. 2 kCols - 1: stain i / kCols, column i % kCols) of bin k
+    static __device__ __forceinline__ uint32_t hist_word(uint32_t k, uint32_t i) {
+        return (kHRegion + k * 256u + kH + (i / kCols) * kStain1) / 4u + i % kCols;
+    }
 };
 
 template <bool WIDE>
@@ -323,8 +339,7 @@ __device__ void p1f_setup(P1FLds<WIDE>& S, const float* w, const P1Params& pp, b
     uint32_t* words = reinterpret_cast<uint32_t*>(S.mem);
     if (zero_hist) {
         constexpr int per = 2 * Y::kCols;     // histogram words per slot
-        for (int i = tid; i < kHistBins * per; i += blockDim.x)
-            words[(Y::kHRegion + (uint32_t)(i / per) * 256u + Y::kH) / 4 + (i % per)] = 0u;
+        for (int i = tid; i < kHistBins * per; i += blockDim.x) words[Y::hist_word(i / per, i % per)] = 0u;
     }
     if (tid == 0) {
         derive_basis(w, pp.lambda, S.B);
@@ -385,9 +400,17 @@ __device__ __forceinline__ void p1f_sums(const P1FLds<WIDE>& S, uint32_t R, uint
     x1 = min(a.z + b.z + c.z, a.w + b.w + c.w);
 }
 
-// Per-lane constants of the byte-permute layout.
+// Per-lane constants of the byte-permute layout.  Wide layout: read k (0..2) of a pixel takes
+// channel ch (0 R, 1 G, 2 B) from bank group g, by quad q = (lane & 15) >> 2 and j = lane & 3:
+//   q = 0: B in 4+j, R in j,    G in 8+j        q = 2: R in j,    B in 4+j, G in 12+j
+//   q = 1: B in 8+j, G in 12+j, R in 4+j        q = 3: G in 12+j, B in 8+j, R in j
+// In each read the 16 lanes of a cycle use groups 0..15 once (R copies live in groups 0..7 and G in
+// 8..15 of region 0, B in 4..11 of region 1).  la[k] holds the read's region and group, sel[k] the
+// perm selector of its channel's byte in a dword holding the pixel as (R, G, B) in bytes 0..2, selz[k]
+// in one holding it in bytes 1..3.
 struct P1FLane {
     uint32_t r16, la, lb, lh, lh1;
+    uint32_t lk[3], sel[3], selz[3];
 };
 
 template <bool WIDE>
@@ -399,7 +422,52 @@ __device__ __forceinline__ P1FLane p1f_lane(int tid) {
     L.lb = Y::kBRegion | L.r16;
     L.lh = Y::kHRegion | (Y::kH + ((uint32_t)(tid & (Y::kCols - 1)) << 2));   // stain 0 column word
     L.lh1 = L.lh + Y::kStain1;                                                 // stain 1
+    const int q = (tid & 15) >> 2, j = tid & 3;
+    const int ch = (q == 0 ? 0x102 : q == 1 ? 0x012 : q == 2 ? 0x120 : 0x021);   // channel of read k: nibble k
+    const int gb = (q == 0 ? 0x804 : q == 1 ? 0x4C8 : q == 2 ? 0xC40 : 0x08C);   // group base of read k
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int c = (ch >> (4 * k)) & 15, g = ((gb >> (4 * k)) & 15) + j;
+        L.lk[k] = (c == 2 ? Y::kBRegion : 0u) | ((uint32_t)g << 4);
+        L.sel[k] = perm_sel(c);
+        L.selz[k] = perm_sel(c + 1);
+    }
     return L;
+}
+
+// Fixed-point sums (shifted guard, see above) of the four pixels of a unit (dwords X, Y0, Z).
+template <bool WIDE>
+__device__ __forceinline__ void p1f_unit_sums(const P1FLds<WIDE>& S, const P1FLane& L, uint32_t X, uint32_t Y0,
+                                              uint32_t Z, int32_t (&y0)[4], int32_t (&y1)[4]) {
+    using Y = P1FLayout<WIDE>;
+    const char* base = reinterpret_cast<const char*>(S.mem);
+    auto rd = [&](uint32_t addr) -> int4 { return *reinterpret_cast<const int4*>(base + addr); };
+    if constexpr (WIDE) {
+        // pixels 1 and 2 gathered as (R, G, B, 0); pixel 0 is bytes 0..2 of X, pixel 3 bytes 1..3 of Z
+        const uint32_t w[3] = {X, __builtin_amdgcn_perm(Y0, X, 0x0c050403u), __builtin_amdgcn_perm(Z, Y0, 0x0c040302u)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int4 e[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                e[k] = rd(q < 3 ? __builtin_amdgcn_perm(w[q], L.lk[k], L.sel[k]) : __builtin_amdgcn_perm(Z, L.lk[k], L.selz[k]));
+            y0[q] = min(e[0].x + e[1].x + e[2].x, e[0].y + e[1].y + e[2].y);
+            y1[q] = min(e[0].z + e[1].z + e[2].z, e[0].w + e[1].w + e[2].w);
+        }
+    } else {
+        const uint32_t aR[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(0)), __builtin_amdgcn_perm(X, L.la, perm_sel(3)),
+                                __builtin_amdgcn_perm(Y0, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
+        const uint32_t aG[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(1)), __builtin_amdgcn_perm(Y0, L.la, perm_sel(0)),
+                                __builtin_amdgcn_perm(Y0, L.la, perm_sel(3)), __builtin_amdgcn_perm(Z, L.la, perm_sel(2))};
+        const uint32_t aB[4] = {__builtin_amdgcn_perm(X, L.lb, perm_sel(2)), __builtin_amdgcn_perm(Y0, L.lb, perm_sel(1)),
+                                __builtin_amdgcn_perm(Z, L.lb, perm_sel(0)), __builtin_amdgcn_perm(Z, L.lb, perm_sel(3))};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 a = rd(aR[q]), b = rd(aG[q] + Y::kG), c = rd(aB[q] + Y::kB);
+            y0[q] = min(a.x + b.x + c.x, a.y + b.y + c.y);
+            y1[q] = min(a.z + b.z + c.z, a.w + b.w + c.w);
+        }
+    }
 }
 
 // Counts the non-white pixels among UNROLL units of one thread: unit j is unit lb0 + j * nthreads
@@ -407,12 +475,10 @@ __device__ __forceinline__ P1FLane p1f_lane(int tid) {
 template <bool WIDE, int UNROLL, bool U16>
 __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L,
                                           const u32x3 (&cur)[UNROLL], int lb0, int cnt, int nthreads) {
-    using Y = P1FLayout<WIDE>;
     const int u = U16 ? 16 : S.shift;
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(u);
     char* base = reinterpret_cast<char*>(S.mem);
-    auto rd = [&](uint32_t addr) -> int4 { return *reinterpret_cast<const int4*>(base + addr); };
     auto bin_addr = [&](int32_t y, uint32_t lh) -> uint32_t {
         return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
                    : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
@@ -437,20 +503,8 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
         const int32_t darkest = min(min(sum[0], sum[1]), min(sum[2], sum[3]));
         const uint64_t valid_lanes = __ballot(valid);
         if (valid && darkest < thr) {   // this lane has a non-white pixel
-            // table addresses: (word holding the byte, byte position) per pixel and channel
-            const uint32_t aR[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(0)), __builtin_amdgcn_perm(X, L.la, perm_sel(3)),
-                                    __builtin_amdgcn_perm(Y0, L.la, perm_sel(2)), __builtin_amdgcn_perm(Z, L.la, perm_sel(1))};
-            const uint32_t aG[4] = {__builtin_amdgcn_perm(X, L.la, perm_sel(1)), __builtin_amdgcn_perm(Y0, L.la, perm_sel(0)),
-                                    __builtin_amdgcn_perm(Y0, L.la, perm_sel(3)), __builtin_amdgcn_perm(Z, L.la, perm_sel(2))};
-            const uint32_t aB[4] = {__builtin_amdgcn_perm(X, L.lb, perm_sel(2)), __builtin_amdgcn_perm(Y0, L.lb, perm_sel(1)),
-                                    __builtin_amdgcn_perm(Z, L.lb, perm_sel(0)), __builtin_amdgcn_perm(Z, L.lb, perm_sel(3))};
             int32_t y0[4], y1[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int4 a = rd(aR[q]), b = rd(aG[q] + Y::kG), c = rd(aB[q] + Y::kB);
-                y0[q] = min(a.x + b.x + c.x, a.y + b.y + c.y);
-                y1[q] = min(a.z + b.z + c.z, a.w + b.w + c.w);
-            }
+            p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 // ballots of plain compares are their scalar masks: the predicates are combined in
@@ -492,12 +546,12 @@ __device__ void p1f_run(P1FLds<WIDE>& S, const P1Params& pp, __amdgpu_buffer_rsr
     const int stride = nthreads * UNROLL;
     u32x3 cur[UNROLL];
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
     for (int lb0 = tid; lb0 < cnt; lb0 += stride) {
         u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j)   // prefetch; past the run the loads return zeros
-            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb0 + stride + j * nthreads), 0, 0);
+            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb0 + stride + j * nthreads), 0, kLoadStream);
         p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, lb0, cnt, nthreads);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
@@ -526,14 +580,14 @@ __device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* sr
     __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
     u32x3 cur[UNROLL];
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
     for (; t < n_tiles; t += gridDim.x) {
         int64_t pn = ph + step;
         if (pn >= n_tiles) pn -= n_tiles;
         const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);   // empty past the end: loads return zeros
         u32x3 nxt[UNROLL];
 #pragma unroll
-        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const int cnt = (int)min(tu, n_units - ph * tu);
         p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
 #pragma unroll
@@ -744,12 +798,12 @@ __device__ void p2_chunk(const P2Lds<COPIES>& T, const RecolourConsts& K, __amdg
     const int stride = nthreads * UNROLL;
     u32x3 cur[UNROLL];
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
     for (int lb = tid; lb < cnt; lb += stride) {
         u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j)
-            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb + stride + j * nthreads), 0, 0);
+            nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb + stride + j * nthreads), 0, kLoadStream);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) {
             uint32_t px[4][3];
@@ -757,7 +811,7 @@ __device__ void p2_chunk(const P2Lds<COPIES>& T, const RecolourConsts& K, __amdg
             float h0[4], h1[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) p2_densities(T, roff, K, px[q][0], px[q][1], px[q][2], h0[q], h1[q]);
-            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (lb + j * nthreads), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (lb + j * nthreads), 0, kStoreStream);
         }
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
@@ -781,12 +835,12 @@ __device__ void p2_tiles(const P2Lds<COPIES>& T, const RecolourConsts& K, const 
     const __amdgpu_buffer_rsrc_t rs0 = tile_rs(src, t);
     u32x3 cur[UNROLL];
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs0, 12 * (tid + j * nthreads), 0, 0);
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs0, 12 * (tid + j * nthreads), 0, kLoadStream);
     for (; t < n_tiles; t += gridDim.x) {
         const __amdgpu_buffer_rsrc_t rn = tile_rs(src, t + gridDim.x);   // empty past the end
         u32x3 nxt[UNROLL];
 #pragma unroll
-        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const __amdgpu_buffer_rsrc_t ws = tile_rs(out, t);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) {
@@ -795,7 +849,7 @@ __device__ void p2_tiles(const P2Lds<COPIES>& T, const RecolourConsts& K, const 
             float h0[4], h1[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) p2_densities(T, roff, K, px[q][0], px[q][1], px[q][2], h0[q], h1[q]);
-            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (tid + j * nthreads), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b96(recolour_unit(h0, h1, K), ws, 12 * (tid + j * nthreads), 0, kStoreStream);
         }
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
@@ -845,14 +899,14 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
     __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
     u32x3 cur[UNROLL];
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, 0);
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
     for (; t < n_tiles; t += gridDim.x) {
         int64_t pn = ph + step;
         if (pn >= n_tiles) pn -= n_tiles;
         const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);
         u32x3 nxt[UNROLL];
 #pragma unroll
-        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, 0);
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const int cnt = (int)min(tu, n_units - ph * tu);
         p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
         const __amdgpu_buffer_rsrc_t w0 = plane_rs(h, ph), w1 = plane_rs(h + n_px, ph);
@@ -867,8 +921,8 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
             u32x4 v0, v1;
             v0.x = __float_as_uint(h0[0]); v0.y = __float_as_uint(h0[1]); v0.z = __float_as_uint(h0[2]); v0.w = __float_as_uint(h0[3]);
             v1.x = __float_as_uint(h1[0]); v1.y = __float_as_uint(h1[1]); v1.z = __float_as_uint(h1[2]); v1.w = __float_as_uint(h1[3]);
-            __builtin_amdgcn_raw_buffer_store_b128(v0, w0, off, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b128(v1, w1, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(v0, w0, off, 0, kStoreStream);
+            __builtin_amdgcn_raw_buffer_store_b128(v1, w1, off, 0, kStoreStream);
         }
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];

@@ -234,13 +234,16 @@ def test_recolor_p99_rejects(lib):
 
 
 @pytest.mark.parametrize("kw,frag", [
-    (dict(mode=2), "mode"),
+    (dict(mode=4), "mode"),
+    (dict(mode=-1), "mode"),
     (dict(src=None), "src is NULL"),
     (dict(dst=None), "dst is NULL"),
     (dict(n=15), "multiple of 16"),
     (dict(src=C.c_void_p((1 << 20) + 8)), "aligned"),
     (dict(dst=C.c_void_p((1 << 20) + 64)), "overlap"),
     (dict(mode=1, ws=None), "workspace"),
+    (dict(mode=3, ws=None), "workspace"),
+    (dict(mode=2, dst=None), "dst is NULL"),
 ])
 def test_bandwidth_probe_rejects(lib, kw, frag):
     args = dict(src=C.c_void_p(1 << 20), dst=C.c_void_p(1 << 24), n=1 << 12, mode=0, ws=C.c_void_p(1 << 26),

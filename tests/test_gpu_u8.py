@@ -480,10 +480,11 @@ def test_bandwidth_probe(S):
     g = torch.Generator(device=DEV)
     g.manual_seed(3)
     src = torch.randint(0, 256, ((1 << 22) + 48,), dtype=torch.uint8, device=DEV, generator=g)
-    dst = torch.zeros_like(src)
-    S.spcn_bandwidth_probe(src, dst, 0)
     keep = src.clone()
-    S.spcn_bandwidth_probe(src, None, 1)
-    torch.cuda.synchronize()
-    assert torch.equal(src, dst)
-    assert torch.equal(src, keep)
+    for copy_mode, read_mode in ((0, 1), (2, 3)):     # streaming and default cache policy
+        dst = torch.zeros_like(src)
+        S.spcn_bandwidth_probe(src, dst, copy_mode)
+        S.spcn_bandwidth_probe(src, None, read_mode)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), copy_mode
+        assert torch.equal(src, keep), read_mode
