@@ -409,7 +409,7 @@ __device__ __forceinline__ void p1f_sums(const P1FLds<WIDE>& S, uint32_t R, uint
 // perm selector of its channel's byte in a dword holding the pixel as (R, G, B) in bytes 0..2, selz[k]
 // in one holding it in bytes 1..3.
 struct P1FLane {
-    uint32_t r16, la, lb, lh, lh1;
+    uint32_t lane, r16, la, lb, lh, lh1;
     uint32_t lk[3], sel[3], selz[3];
 };
 
@@ -417,6 +417,7 @@ template <bool WIDE>
 __device__ __forceinline__ P1FLane p1f_lane(int tid) {
     using Y = P1FLayout<WIDE>;
     P1FLane L;
+    L.lane = (uint32_t)(tid & 63);
     L.r16 = (uint32_t)(tid & (Y::kCopies - 1)) << 4;
     L.la = L.r16;
     L.lb = Y::kBRegion | L.r16;
@@ -470,11 +471,11 @@ __device__ __forceinline__ void p1f_unit_sums(const P1FLds<WIDE>& S, const P1FLa
     }
 }
 
-// Counts the non-white pixels among UNROLL units of one thread: unit j is unit lb0 + j * nthreads
-// of a run of cnt units (cur holds their bytes).
-template <bool WIDE, int UNROLL, bool U16>
-__device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L,
-                                          const u32x3 (&cur)[UNROLL], int lb0, int cnt, int nthreads) {
+// Counts the non-white pixels of one unit per lane (dwords X, Y0, Z) on the lanes where `valid`, and
+// settles the unit's near-edge pixels in FP64 right away (rare; only on the lanes that hold one).
+template <bool WIDE, bool U16>
+__device__ __forceinline__ void p1f_count(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L, uint32_t X,
+                                          uint32_t Y0, uint32_t Z, bool valid) {
     const int u = U16 ? 16 : S.shift;
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(u);
@@ -483,58 +484,127 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
         return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
                    : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
     };
-    // Lanes without a non-white pixel skip the table reads and histogram adds (exec mask).  Every lane
-    // predicate is a plain compare whose ballot is its scalar mask; the masks are combined in scalar
-    // registers and turned into the 0/1 increment by one select (a ballot of a combined predicate
-    // would cost two vector instructions per pixel).
-    uint64_t nearj[UNROLL];   // per unit: lanes with a near-edge non-white pixel
+    // R + G + B of the four pixels (byte dot products)
+    int32_t sum[4];
+    sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
+    sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
+    sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
+    sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
+    const uint64_t valid_lanes = __ballot(valid);
+    uint64_t nearm = 0;       // lanes with a near-edge non-white pixel
+    if (valid) {
+        int32_t y0[4], y1[4];
+        p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
 #pragma unroll
-    for (int j = 0; j < UNROLL; ++j) nearj[j] = 0;
+        for (int q = 0; q < 4; ++q) {
+            // every lane predicate is a plain compare whose ballot is its scalar mask: the masks are
+            // combined in scalar registers and turned into the 0/1 increment by one select (a ballot
+            // of a combined predicate would cost two vector instructions per pixel)
+            const uint64_t white = __ballot(sum[q] >= thr);
+            const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
+            nearm |= nr & ~white & valid_lanes;
+            const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
+            atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
+        }
+    }
+    if (nearm && __builtin_amdgcn_inverse_ballot_w64(nearm)) {
+        u32x3 un;
+        un.x = X; un.y = Y0; un.z = Z;
+        uint32_t px[4][3];
+        bytes_of_unit(un, px);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t R = px[q][0], G = px[q][1], Bc = px[q][2];
+            if ((int32_t)(R + G + Bc) >= thr) continue;
+            int32_t y0, y1;
+            p1f_sums(S, R, G, Bc, L.r16, y0, y1);
+            if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
+        }
+    }
+}
+
+// Units with a non-white pixel waiting for a full wavefront of counting work (wide layout): lanes
+// 0 .. n-1 of u hold one each; n is the same in every lane.
+struct P1FPend {
+    u32x3 u;
+    int n;
+};
+
+__device__ __forceinline__ P1FPend p1f_pend() {
+    P1FPend P;
+    P.u.x = 0u; P.u.y = 0u; P.u.z = 0u;
+    P.n = 0;
+    return P;
+}
+
+// Counts the non-white pixels among UNROLL units of one thread: unit j is unit lb0 + j * nthreads
+// of a run of cnt units (cur holds their bytes).  Every lane of the wavefront must be active.
+//
+// A wavefront pays for an LDS or vector instruction whatever its exec mask, and inside tissue most
+// 256-pixel spans mix units with and without tissue, so with the wide layout the units that hold a
+// non-white pixel are packed into full wavefronts first: the units of one slot j are permuted
+// (ds_permute_b32, a full permutation of the 64 lanes: tissue units to lanes n, n+1, ... modulo 64
+// in lane order, the others to the remaining lanes) and merged into the pending units P; whenever 64
+// are pending they are counted as one wavefront.  The caller counts what is left with p1f_flush.
+template <bool WIDE, int UNROLL, bool U16>
+__device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L,
+                                          const u32x3 (&cur)[UNROLL], int lb0, int cnt, int nthreads, P1FPend& P) {
+    const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) {
         const bool valid = lb0 + j * nthreads < cnt;
         const uint32_t X = cur[j].x, Y0 = cur[j].y, Z = cur[j].z;
-        // R + G + B of the four pixels (byte dot products)
-        int32_t sum[4];
-        sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
-        sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
-        sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
-        sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
-        const int32_t darkest = min(min(sum[0], sum[1]), min(sum[2], sum[3]));
-        const uint64_t valid_lanes = __ballot(valid);
-        if (valid && darkest < thr) {   // this lane has a non-white pixel
-            int32_t y0[4], y1[4];
-            p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // ballots of plain compares are their scalar masks: the predicates are combined in
-                // scalar registers and turned into the 0/1 increment by one select
-                const uint64_t white = __ballot(sum[q] >= thr);
-                const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
-                nearj[j] |= nr & ~white & valid_lanes;
-                const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
-                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
-                atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
+        const int32_t s0 = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
+        const int32_t s1 = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
+        const int32_t s2 = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
+        const int32_t s3 = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
+        const bool tissue = valid && min(min(s0, s1), min(s2, s3)) < thr;   // a non-white pixel in the unit
+        if constexpr (!WIDE) {
+            p1f_count<WIDE, U16>(S, pp, L, X, Y0, Z, tissue);
+        } else {
+            const uint64_t m = __ballot(tissue);
+            if (m == 0) continue;
+            const int c = __popcll(m);
+            P.n = __builtin_amdgcn_readfirstlane(P.n);   // uniform by construction: keep it scalar
+            if (c == 64 && P.n == 0) {   // a full wavefront as it is
+                p1f_count<WIDE, U16>(S, pp, L, X, Y0, Z, true);
+                continue;
+            }
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t n0 = (uint32_t)P.n;
+            const uint32_t to_t = n0 + r, to_w = n0 + (uint32_t)c + L.lane - r;
+            const uint32_t dst = ((__builtin_amdgcn_inverse_ballot_w64(m) ? to_t : to_w) & 63u) << 2;
+            u32x3 v;
+            v.x = (uint32_t)__builtin_amdgcn_ds_permute((int)dst, (int)X);
+            v.y = (uint32_t)__builtin_amdgcn_ds_permute((int)dst, (int)Y0);
+            v.z = (uint32_t)__builtin_amdgcn_ds_permute((int)dst, (int)Z);
+            const int e = __builtin_amdgcn_readfirstlane(P.n + c);
+            if (e < 64) {
+                const bool take = L.lane >= n0 && L.lane < (uint32_t)e;
+                P.u.x = take ? v.x : P.u.x;
+                P.u.y = take ? v.y : P.u.y;
+                P.u.z = take ? v.z : P.u.z;
+                P.n = e;
+            } else {
+                const bool take = L.lane >= n0;
+                P.u.x = take ? v.x : P.u.x;
+                P.u.y = take ? v.y : P.u.y;
+                P.u.z = take ? v.z : P.u.z;
+                p1f_count<WIDE, U16>(S, pp, L, P.u.x, P.u.y, P.u.z, true);
+                P.u = v;                 // lanes 0 .. e - 65 hold the units that did not fit
+                P.n = e - 64;
             }
         }
     }
-    // rare: settle the near-edge pixels in FP64 (bytes from registers), only in the units that hold
-    // one, and only on the lanes that do
-#pragma unroll
-    for (int j = 0; j < UNROLL; ++j) {
-        if (nearj[j] && __builtin_amdgcn_inverse_ballot_w64(nearj[j])) {
-            uint32_t px[4][3];
-            bytes_of_unit(cur[j], px);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t R = px[q][0], G = px[q][1], Bc = px[q][2];
-                if ((int32_t)(R + G + Bc) >= thr) continue;
-                int32_t y0, y1;
-                p1f_sums(S, R, G, Bc, L.r16, y0, y1);
-                if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
-            }
-        }
-    }
+}
+
+// Counts the pending units (a partial wavefront) and empties P.
+template <bool WIDE, bool U16>
+__device__ __forceinline__ void p1f_flush(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L, P1FPend& P) {
+    P.n = __builtin_amdgcn_readfirstlane(P.n);
+    if (WIDE && P.n > 0) p1f_count<WIDE, U16>(S, pp, L, P.u.x, P.u.y, P.u.z, L.lane < (uint32_t)P.n);
+    P.n = 0;
 }
 
 // Contiguous run of cnt units (buffer resource rs over its bytes): each thread takes units tid,
@@ -544,18 +614,21 @@ __device__ void p1f_run(P1FLds<WIDE>& S, const P1Params& pp, __amdgpu_buffer_rsr
                         int nthreads) {
     const P1FLane L = p1f_lane<WIDE>(tid);
     const int stride = nthreads * UNROLL;
+    P1FPend P = p1f_pend();
     u32x3 cur[UNROLL];
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
-    for (int lb0 = tid; lb0 < cnt; lb0 += stride) {
+    for (int b0 = 0; b0 < cnt; b0 += stride) {   // the same trip count in every lane
+        const int lb0 = b0 + tid;
         u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j)   // prefetch; past the run the loads return zeros
             nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb0 + stride + j * nthreads), 0, kLoadStream);
-        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, lb0, cnt, nthreads);
+        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, lb0, cnt, nthreads, P);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
     }
+    p1f_flush<WIDE, U16>(S, pp, L, P);
 }
 
 // Grid-stride form: the image's units form tiles of nthreads * UNROLL units.  Workgroup b takes the
@@ -578,6 +651,7 @@ __device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* sr
         return chunk_rsrc(src, in ? tile * tu : 0, in ? min(tu, n_units - tile * tu) : 0);
     };
     __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
+    P1FPend P = p1f_pend();
     u32x3 cur[UNROLL];
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
@@ -589,11 +663,12 @@ __device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* sr
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const int cnt = (int)min(tu, n_units - ph * tu);
-        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
+        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads, P);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
         ph = pn;
     }
+    p1f_flush<WIDE, U16>(S, pp, L, P);
 }
 
 // Multiplier of the tile permutation above: 1 when the grid covers every tile at once, else the
@@ -897,6 +972,7 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
         return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, nb, kBufDword3);
     };
     __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
+    P1FPend P = p1f_pend();
     u32x3 cur[UNROLL];
 #pragma unroll
     for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
@@ -908,7 +984,7 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const int cnt = (int)min(tu, n_units - ph * tu);
-        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads);
+        p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads, P);
         const __amdgpu_buffer_rsrc_t w0 = plane_rs(h, ph), w1 = plane_rs(h + n_px, ph);
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) {
@@ -928,6 +1004,7 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
         ph = pn;
     }
+    p1f_flush<WIDE, U16>(S, pp, L, P);
 }
 
 }  // namespace spcn
