@@ -471,43 +471,46 @@ __device__ __forceinline__ void p1f_unit_sums(const P1FLds<WIDE>& S, const P1FLa
     }
 }
 
-// Counts the non-white pixels of one unit per lane (dwords X, Y0, Z) on the lanes where `valid`, and
-// settles the unit's near-edge pixels in FP64 right away (rare; only on the lanes that hold one).
+// R + G + B of the four pixels of a unit (byte dot products).
+__device__ __forceinline__ void p1f_white_sums(uint32_t X, uint32_t Y0, uint32_t Z, int32_t (&sum)[4]) {
+    sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
+    sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
+    sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
+    sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
+}
+
+// Histogram adds of one unit per active lane from its white sums and fixed-point candidate sums;
+// returns the lanes with a near-edge non-white pixel (left out here, for p1f_settle).
 template <bool WIDE, bool U16>
-__device__ __forceinline__ void p1f_count(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L, uint32_t X,
-                                          uint32_t Y0, uint32_t Z, bool valid) {
+__device__ __forceinline__ uint64_t p1f_bins(P1FLds<WIDE>& S, const P1FLane& L, const int32_t (&sum)[4],
+                                             const int32_t (&y0)[4], const int32_t (&y1)[4], int32_t thr,
+                                             uint32_t nmask, uint64_t valid_lanes) {
     const int u = U16 ? 16 : S.shift;
-    const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
-    const uint32_t nmask = p1f_nmask(u);
     char* base = reinterpret_cast<char*>(S.mem);
     auto bin_addr = [&](int32_t y, uint32_t lh) -> uint32_t {
         return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
                    : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
     };
-    // R + G + B of the four pixels (byte dot products)
-    int32_t sum[4];
-    sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
-    sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
-    sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
-    sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
-    const uint64_t valid_lanes = __ballot(valid);
-    uint64_t nearm = 0;       // lanes with a near-edge non-white pixel
-    if (valid) {
-        int32_t y0[4], y1[4];
-        p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
+    uint64_t nearm = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            // every lane predicate is a plain compare whose ballot is its scalar mask: the masks are
-            // combined in scalar registers and turned into the 0/1 increment by one select (a ballot
-            // of a combined predicate would cost two vector instructions per pixel)
-            const uint64_t white = __ballot(sum[q] >= thr);
-            const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
-            nearm |= nr & ~white & valid_lanes;
-            const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
-            atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
-            atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
-        }
+    for (int q = 0; q < 4; ++q) {
+        // every lane predicate is a plain compare whose ballot is its scalar mask: the masks are
+        // combined in scalar registers and turned into the 0/1 increment by one select (a ballot
+        // of a combined predicate would cost two vector instructions per pixel)
+        const uint64_t white = __ballot(sum[q] >= thr);
+        const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
+        nearm |= nr & ~white & valid_lanes;
+        const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
+        atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
+        atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
     }
+    return nearm;
+}
+
+// Settles the near-edge non-white pixels of one unit per lane in FP64 (lanes in nearm; rare).
+template <bool WIDE>
+__device__ __forceinline__ void p1f_settle(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L, uint32_t X,
+                                           uint32_t Y0, uint32_t Z, uint64_t nearm, int32_t thr, uint32_t nmask) {
     if (nearm && __builtin_amdgcn_inverse_ballot_w64(nearm)) {
         u32x3 un;
         un.x = X; un.y = Y0; un.z = Z;
@@ -522,6 +525,25 @@ __device__ __forceinline__ void p1f_count(P1FLds<WIDE>& S, const P1Params& pp, c
             if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
         }
     }
+}
+
+// Counts the non-white pixels of one unit per lane (dwords X, Y0, Z) on the lanes where `valid`, and
+// settles the unit's near-edge pixels in FP64 right away (rare; only on the lanes that hold one).
+template <bool WIDE, bool U16>
+__device__ __forceinline__ void p1f_count(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L, uint32_t X,
+                                          uint32_t Y0, uint32_t Z, bool valid) {
+    const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
+    const uint32_t nmask = p1f_nmask(U16 ? 16 : S.shift);
+    int32_t sum[4];
+    p1f_white_sums(X, Y0, Z, sum);
+    const uint64_t valid_lanes = __ballot(valid);
+    uint64_t nearm = 0;       // lanes with a near-edge non-white pixel
+    if (valid) {
+        int32_t y0[4], y1[4];
+        p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
+        nearm = p1f_bins<WIDE, U16>(S, L, sum, y0, y1, thr, nmask, valid_lanes);
+    }
+    p1f_settle(S, pp, L, X, Y0, Z, nearm, thr, nmask);
 }
 
 // Units with a non-white pixel waiting for a full wavefront of counting work (wide layout): lanes
@@ -574,7 +596,8 @@ __device__ __forceinline__ void p1f_units(P1FLds<WIDE>& S, const P1Params& pp, c
             const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             const uint32_t n0 = (uint32_t)P.n;
             const uint32_t to_t = n0 + r, to_w = n0 + (uint32_t)c + L.lane - r;
-            const uint32_t dst = ((__builtin_amdgcn_inverse_ballot_w64(m) ? to_t : to_w) & 63u) << 2;
+            // byte address; ds_permute_b32 takes the destination lane modulo 64
+            const uint32_t dst = (__builtin_amdgcn_inverse_ballot_w64(m) ? to_t : to_w) << 2;
             u32x3 v;
             v.x = (uint32_t)__builtin_amdgcn_ds_permute((int)dst, (int)X);
             v.y = (uint32_t)__builtin_amdgcn_ds_permute((int)dst, (int)Y0);
@@ -1005,6 +1028,78 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
         ph = pn;
     }
     p1f_flush<WIDE, U16>(S, pp, L, P);
+}
+
+// Pass 1 with the densities for u = 16, from one set of fixed-point sums per unit: the candidate
+// sums y_j of every pixel (p1f_unit_sums, all lanes) give both the histogram bins (as in pass 1, on
+// the lanes whose unit holds a non-white pixel) and the densities h_j = max(0, y_j + kGuardUnits) /
+// (2^16 * 256 / hist_hi_j) -- the table entries are within half a unit of their FP64 values, so a
+// density is within 1.5 * hist_hi_j / 2^24 of the exact one.  Planes as in p1f_tiles_dens.
+template <int UNROLL>
+__device__ void p1f_tiles_dens16(P1FLds<true>& S, const P1Params& pp, const uint8_t* src, int64_t n_units, float* h,
+                                 int64_t n_px, int tid, int nthreads, int64_t scatter, int64_t step) {
+    const P1FLane L = p1f_lane<true>(tid);
+    const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
+    const uint32_t nmask = p1f_nmask(16);
+    const float c0 = (float)((double)pp.hist_hi[0] / 16777216.0), c1 = (float)((double)pp.hist_hi[1] / 16777216.0);
+    const int64_t tu = (int64_t)nthreads * UNROLL;
+    const int64_t n_tiles = (n_units + tu - 1) / tu;
+    int64_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    int64_t ph = (t * scatter) % n_tiles;
+    auto tile_rs = [&](int64_t tt, int64_t tile) {
+        const bool in = tt < n_tiles;
+        return chunk_rsrc(src, in ? tile * tu : 0, in ? min(tu, n_units - tile * tu) : 0);
+    };
+    auto plane_rs = [&](const float* base, int64_t tile) {
+        const uint64_t addr = reinterpret_cast<uint64_t>(base) + 16 * (uint64_t)(tile * tu);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+        const int nb = __builtin_amdgcn_readfirstlane((int)(16 * min(tu, n_units - tile * tu)));
+        return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, nb, kBufDword3);
+    };
+    __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
+    u32x3 cur[UNROLL];
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
+    for (; t < n_tiles; t += gridDim.x) {
+        int64_t pn = ph + step;
+        if (pn >= n_tiles) pn -= n_tiles;
+        const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);
+        u32x3 nxt[UNROLL];
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
+        const int cnt = (int)min(tu, n_units - ph * tu);
+        const __amdgpu_buffer_rsrc_t w0 = plane_rs(h, ph), w1 = plane_rs(h + n_px, ph);
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) {
+            const bool valid = tid + j * nthreads < cnt;
+            const uint32_t X = cur[j].x, Y0 = cur[j].y, Z = cur[j].z;
+            int32_t sum[4], y0[4], y1[4];
+            p1f_white_sums(X, Y0, Z, sum);
+            p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
+            u32x4 v0, v1;
+            v0.x = __float_as_uint(fmaxf(0.0f, (float)(y0[0] + kGuardUnits) * c0));
+            v0.y = __float_as_uint(fmaxf(0.0f, (float)(y0[1] + kGuardUnits) * c0));
+            v0.z = __float_as_uint(fmaxf(0.0f, (float)(y0[2] + kGuardUnits) * c0));
+            v0.w = __float_as_uint(fmaxf(0.0f, (float)(y0[3] + kGuardUnits) * c0));
+            v1.x = __float_as_uint(fmaxf(0.0f, (float)(y1[0] + kGuardUnits) * c1));
+            v1.y = __float_as_uint(fmaxf(0.0f, (float)(y1[1] + kGuardUnits) * c1));
+            v1.z = __float_as_uint(fmaxf(0.0f, (float)(y1[2] + kGuardUnits) * c1));
+            v1.w = __float_as_uint(fmaxf(0.0f, (float)(y1[3] + kGuardUnits) * c1));
+            const int off = 16 * (tid + j * nthreads);   // past the tile's units the stores are dropped
+            __builtin_amdgcn_raw_buffer_store_b128(v0, w0, off, 0, kStoreStream);
+            __builtin_amdgcn_raw_buffer_store_b128(v1, w1, off, 0, kStoreStream);
+            const bool tissue = valid && min(min(sum[0], sum[1]), min(sum[2], sum[3])) < thr;
+            const uint64_t tl = __ballot(tissue);
+            uint64_t nearm = 0;
+            if (tissue) nearm = p1f_bins<true, true>(S, L, sum, y0, y1, thr, nmask, tl);
+            p1f_settle(S, pp, L, X, Y0, Z, nearm, thr, nmask);
+        }
+#pragma unroll
+        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+        ph = pn;
+    }
 }
 
 }  // namespace spcn

@@ -144,9 +144,9 @@ __global__ __launch_bounds__(1024, 4) void k_pass1d(const P1Args a, float* h_out
     K.a0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_a[0])));
     K.a1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_a[1])));
     const int64_t n_units = a.n_px >> 2;
-    if (S.shift == 16)
-        p1f_tiles_dens<true, UNROLL, true>(S, T, K, pp, a.src, n_units, h_out, a.n_px, threadIdx.x, 1024, a.scatter,
-                                          a.step);
+    const bool u16 = S.shift == 16;
+    if (u16)
+        p1f_tiles_dens16<UNROLL>(S, pp, a.src, n_units, h_out, a.n_px, threadIdx.x, 1024, a.scatter, a.step);
     else
         p1f_tiles_dens<true, UNROLL, false>(S, T, K, pp, a.src, n_units, h_out, a.n_px, threadIdx.x, 1024, a.scatter,
                                            a.step);
@@ -154,9 +154,17 @@ __global__ __launch_bounds__(1024, 4) void k_pass1d(const P1Args a, float* h_out
         const int tail = (int)(a.n_px - 4 * n_units);
         const uint8_t* px = a.src + 12 * n_units;
         p1f_tail(S, pp, px, tail);
+        const P1FLane L = p1f_lane<true>(0);
         for (int i = 0; i < tail; ++i) {
             float h0, h1;
-            p2_densities(T, 0u, K, px[3 * i], px[3 * i + 1], px[3 * i + 2], h0, h1);
+            if (u16) {   // the densities from the fixed-point sums, as in the body
+                int32_t y0, y1;
+                p1f_sums(S, px[3 * i], px[3 * i + 1], px[3 * i + 2], L.r16, y0, y1);
+                h0 = fmaxf(0.0f, (float)(y0 + kGuardUnits) * (float)((double)pp.hist_hi[0] / 16777216.0));
+                h1 = fmaxf(0.0f, (float)(y1 + kGuardUnits) * (float)((double)pp.hist_hi[1] / 16777216.0));
+            } else {
+                p2_densities(T, 0u, K, px[3 * i], px[3 * i + 1], px[3 * i + 2], h0, h1);
+            }
             h_out[4 * n_units + i] = h0;
             h_out[a.n_px + 4 * n_units + i] = h1;
         }
