@@ -114,7 +114,9 @@ size_t spcn_workspace_size(int op, int64_t n_px, int64_t n_items, int64_t n_samp
  * percentile (Eq. 3 numerator when applied to a target image).
  *   img       uint8 HWC, height*width pixels
  *   w         [6] basis
- *   h_out     [2][n_px] FP32 densities, 16-byte aligned, or NULL (histogram only)
+ *   h_out     [2][n_px] FP32 densities, 16-byte aligned, or NULL (histogram only); each within
+ *             2e-6 * max(1, hist_hi) of the exact value (fixed-point sums of 2^-16 bin when the
+ *             basis allows them, else FP32 tables)
  *   hist_out  [2][256] uint64 counts over non-white pixels (overwritten)
  *   p99_out   [2] histogram percentile per stain (interpolated in the crossing bin), or NULL
  *   flags_out [2] SPCN_FLAG_* per stain, or NULL
