@@ -573,13 +573,27 @@ struct SelState {
     unsigned long long prefix[2];   // key bits fixed so far
     long long r[2];                 // 1-based rank still to find among the values sharing the prefix
     long long n;                    // values (kept samples)
+    unsigned int n_cand[2];         // values gathered after the first two digits (may exceed SEL_CAND_CAP)
 };
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// After two digits (22 key bits) few values still share the prefix: they are gathered once and the
+// last four digits are taken over them inside one workgroup (over all values again if more than
+// SEL_CAND_CAP share it, e.g. many equal densities).
+constexpr int SEL_GATHER_PASSES = 2;
+constexpr int SEL_CAND_CAP = 16384;
+
+size_t sel_workspace_bytes() {
+    return align256(sizeof(SelState)) + align256((size_t)2 * SEL_BINS * sizeof(uint32_t)) +
+           align256((size_t)2 * SEL_CAND_CAP * sizeof(unsigned long long));
+}
 
 __global__ __launch_bounds__(64) void k_sel_init(const BasisWork* bw, double q, SelState* st, uint32_t* dhist) {
     const long long n = bw->n_acc;
     long long k = n > 0 ? (long long)ceil(q * (double)n) : 0;
     k = n > 0 ? (k < 1 ? 1 : (k > n ? n : k)) : 0;
-    if (threadIdx.x < 2) { st->prefix[threadIdx.x] = 0ull; st->r[threadIdx.x] = k; }
+    if (threadIdx.x < 2) { st->prefix[threadIdx.x] = 0ull; st->r[threadIdx.x] = k; st->n_cand[threadIdx.x] = 0u; }
     if (threadIdx.x == 0) st->n = n;
     for (int i = threadIdx.x; i < 2 * SEL_BINS; i += blockDim.x) dhist[i] = 0u;
 }
@@ -605,60 +619,158 @@ __global__ __launch_bounds__(256) void k_sel_digits(const double* H, int64_t ns,
         if (s_h[i]) atomicAdd(dhist + j * SEL_BINS + i, s_h[i]);
 }
 
-// One workgroup of 256 threads per stain: the digit holding the remaining rank (parallel prefix sums),
-// the digit histogram cleared for the next pass; after the last pass the value and the flags.
-__global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* dhist, int pass, int64_t ns,
-                                                  float* p99_out, int32_t* flags_out, float* range_out = nullptr) {
-    __shared__ uint32_t s_wsum[4];
-    __shared__ int s_g;
-    __shared__ uint32_t s_below;
-    const int j = blockIdx.x, t = threadIdx.x, lane = t & 63;
-    const long long n = st->n;
+// Threads 0..255 of the workgroup: the bin of a 2048-bin digit histogram dh (global or LDS) that
+// holds rank r (1-based, parallel prefix sums); returns the digit and the rank left inside its bin,
+// valid in thread 0.  Barriers inside (every thread of the workgroup must call).
+__device__ void sel_choose(const uint32_t* dh, uint32_t r, uint32_t* s_wsum, int* s_g, uint32_t* s_below,
+                           uint32_t& digit, uint32_t& r_left) {
+    const int t = threadIdx.x, lane = t & 63;
     constexpr int per = SEL_BINS / 256;
-    uint32_t* dh = dhist + j * SEL_BINS;
-    if (n > 0) {
-        const uint32_t r = (uint32_t)st->r[j];
-        uint32_t sum = 0;
+    uint32_t sum = 0, incl = 0;
+    if (t < 256) {
 #pragma unroll
         for (int i = 0; i < per; ++i) sum += dh[t * per + i];
-        uint32_t incl = sum;
+        incl = sum;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t up = __shfl_up(incl, o);
             if (lane >= o) incl += up;
         }
         if (lane == 63) s_wsum[t >> 6] = incl;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (t < 256) {
         for (int w = 0; w < (t >> 6); ++w) incl += s_wsum[w];
-        if (t == 255) { s_g = 255; s_below = incl - sum; }   // default if the counts fall short of r
-        __syncthreads();
-        if (incl - sum < r && r <= incl) { s_g = t; s_below = incl - sum; }   // at most one thread
-        __syncthreads();
-        if (t < 64) {
-            const int g = s_g;
-            const uint32_t c = t < per ? dh[g * per + t] : 0u;
-            uint32_t in = c;
-            for (int o = 1; o < per; o <<= 1) {
-                const uint32_t up = __shfl_up(in, o);
-                if (t >= o) in += up;
-            }
-            const uint32_t rr = r - s_below;
-            const uint64_t m = __ballot(t < per && in - c < rr && rr <= in);
-            const int who = m ? __ffsll((unsigned long long)m) - 1 : per - 1;
-            const uint32_t before = __shfl(in - c, who);
-            if (t == 0) {
-                st->r[j] = (long long)(rr - before);
-                st->prefix[j] |= (unsigned long long)(g * per + who) << sel_shift(pass);
-            }
+        if (t == 255) { *s_g = 255; *s_below = incl - sum; }   // default if the counts fall short of r
+    }
+    __syncthreads();
+    if (t < 256 && incl - sum < r && r <= incl) { *s_g = t; *s_below = incl - sum; }   // at most one thread
+    __syncthreads();
+    if (t < 64) {
+        const int g = *s_g;
+        const uint32_t c = t < per ? dh[g * per + t] : 0u;
+        uint32_t in = c;
+        for (int o = 1; o < per; o <<= 1) {
+            const uint32_t up = __shfl_up(in, o);
+            if (t >= o) in += up;
         }
-        __syncthreads();
+        const uint32_t rr = r - *s_below;
+        const uint64_t m = __ballot(t < per && in - c < rr && rr <= in);
+        const int who = m ? __ffsll((unsigned long long)m) - 1 : per - 1;
+        const uint32_t before = __shfl(in - c, who);
+        digit = (uint32_t)(g * per + who);
+        r_left = rr - before;
+    }
+    __syncthreads();
+}
+
+// The value's outputs (thread 0 of the stain's workgroup).
+__device__ void sel_outputs(const SelState* st, int j, int64_t ns, float* p99_out, int32_t* flags_out,
+                            float* range_out) {
+    const long long n = st->n;
+    const double P = n > 0 ? __longlong_as_double((long long)st->prefix[j]) : 0.0;
+    if (p99_out) p99_out[j] = (float)P;
+    if (range_out) range_out[j] = range_for_percentile((double)(float)P);
+    if (flags_out) flags_out[j] = (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
+}
+
+// One workgroup of 256 threads per stain: the digit holding the remaining rank, the digit histogram
+// cleared for the next pass; after the last pass the value and the flags.
+__global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* dhist, int pass, int64_t ns,
+                                                  float* p99_out, int32_t* flags_out, float* range_out = nullptr) {
+    __shared__ uint32_t s_wsum[4];
+    __shared__ int s_g;
+    __shared__ uint32_t s_below;
+    const int j = blockIdx.x, t = threadIdx.x;
+    const long long n = st->n;
+    uint32_t* dh = dhist + j * SEL_BINS;
+    if (n > 0) {
+        uint32_t digit = 0, r_left = 0;
+        sel_choose(dh, (uint32_t)st->r[j], s_wsum, &s_g, &s_below, digit, r_left);
+        if (t == 0) {
+            st->r[j] = (long long)r_left;
+            st->prefix[j] |= (unsigned long long)digit << sel_shift(pass);
+        }
         for (int i = t; i < SEL_BINS; i += blockDim.x) dh[i] = 0u;
     }
-    if (pass == SEL_PASSES - 1 && t == 0) {
-        const double P = n > 0 ? __longlong_as_double((long long)st->prefix[j]) : 0.0;
-        if (p99_out) p99_out[j] = (float)P;
-        if (range_out) range_out[j] = range_for_percentile((double)(float)P);
-        if (flags_out) flags_out[j] = (n == 0 ? SPCN_FLAG_NO_TISSUE : 0) | (n < ns ? SPCN_FLAG_SHORT : 0);
+    if (pass == SEL_PASSES - 1 && t == 0) sel_outputs(st, j, ns, p99_out, flags_out, range_out);
+}
+
+// Gathers the key bits of the values that share the prefix of the first SEL_GATHER_PASSES digits
+// (one append per wavefront: a ballot, one atomic, ranks by mbcnt).
+__global__ __launch_bounds__(256) void k_sel_gather(const double* H, int64_t ns, SelState* st,
+                                                    unsigned long long* cand) {
+    const int j = blockIdx.y, lane = threadIdx.x & 63;
+    const long long n = st->n;
+    if (n == 0) return;                                  // uniform
+    const int lo = sel_shift(SEL_GATHER_PASSES - 1);
+    const unsigned long long prefix = st->prefix[j];
+    const double* Hj = H + j * ns;
+    unsigned long long* cj = cand + (int64_t)j * SEL_CAND_CAP;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i0 = (long long)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {   // uniform trip count
+        const long long i = i0 + threadIdx.x;
+        unsigned long long u = 0ull;
+        bool keep = false;
+        if (i < n) {
+            const double v = Hj[i];
+            u = v > 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
+            keep = ((u ^ prefix) >> lo) == 0ull;
+        }
+        const uint64_t m = __ballot(keep);
+        if (m == 0) continue;
+        const int first = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == first) base = atomicAdd(&st->n_cand[j], (unsigned)__popcll(m));
+        base = (uint32_t)__shfl((int)base, first);
+        const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (keep && slot < (uint32_t)SEL_CAND_CAP) cj[slot] = u;
     }
+}
+
+// The remaining digits in one workgroup of 256 threads per stain, over the gathered values (or over
+// all values when more than SEL_CAND_CAP were gathered), then the outputs.
+__global__ __launch_bounds__(256) void k_sel_finish(SelState* st, const unsigned long long* cand, const double* H,
+                                                    int64_t ns, float* p99_out, int32_t* flags_out,
+                                                    float* range_out) {
+    __shared__ uint32_t s_h[SEL_BINS];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ int s_g;
+    __shared__ uint32_t s_below;
+    __shared__ unsigned long long s_prefix;
+    __shared__ uint32_t s_r;
+    const int j = blockIdx.x, t = threadIdx.x;
+    const long long n = st->n;
+    if (n > 0) {
+        const uint32_t c = st->n_cand[j];
+        const bool gathered = c <= (uint32_t)SEL_CAND_CAP;
+        const long long m = gathered ? (long long)c : n;
+        const unsigned long long* cj = cand + (int64_t)j * SEL_CAND_CAP;
+        const double* Hj = H + j * ns;
+        if (t == 0) { s_prefix = st->prefix[j]; s_r = (uint32_t)st->r[j]; }
+        for (int pass = SEL_GATHER_PASSES; pass < SEL_PASSES; ++pass) {
+            for (int i = t; i < SEL_BINS; i += blockDim.x) s_h[i] = 0u;
+            __syncthreads();
+            const int shift = sel_shift(pass), hi = shift + sel_width(pass);
+            const unsigned long long prefix = s_prefix, dmask = (1ull << sel_width(pass)) - 1;
+            for (long long i = t; i < m; i += blockDim.x) {
+                unsigned long long u;
+                if (gathered) {
+                    u = cj[i];
+                } else {
+                    const double v = Hj[i];
+                    u = v > 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
+                }
+                if (((u ^ prefix) >> hi) == 0ull) atomicAdd(&s_h[(u >> shift) & dmask], 1u);
+            }
+            __syncthreads();
+            uint32_t digit = 0, r_left = 0;
+            sel_choose(s_h, s_r, s_wsum, &s_g, &s_below, digit, r_left);
+            if (t == 0) { s_prefix |= (unsigned long long)digit << shift; s_r = r_left; }
+            __syncthreads();
+        }
+        if (t == 0) { st->prefix[j] = s_prefix; st->r[j] = s_r; }
+    }
+    if (t == 0) sel_outputs(st, j, ns, p99_out, flags_out, range_out);
 }
 
 // ------------------------------------------------------------------ a batch of tiles
@@ -802,7 +914,6 @@ __global__ __launch_bounds__(TILE_THREADS) void k_nmf_tiles(TileArgs a) {
 
 // ------------------------------------------------------------------ launchers
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int64_t hmin(int64_t a, int64_t b) { return a < b ? a : b; }
 
 static int64_t round_candidates(int64_t n_s, int r) {
@@ -825,22 +936,29 @@ size_t basis_workspace_bytes(int64_t n_s) {
     b += align256((size_t)3 * kHistBins * sizeof(double));        // optical-density table
     b += align256(FIT_XCHG_BYTES);                                // the fit's exchange slots
     b += align256((size_t)2 * n_s * sizeof(double));              // fitted densities of the samples
-    b += align256(sizeof(SelState)) + align256((size_t)2 * SEL_BINS * sizeof(uint32_t));   // their percentile
+    b += sel_workspace_bytes();                                   // their percentile
     return b;
 }
 
 // Nearest-rank percentile of both stains of H [2][n_s] (the first bw->n_acc values of each row):
-// the selection state, then six digit passes.
-static void launch_select(const BasisWork* bw, const double* H, int64_t n_s, double q, SelState* sel, uint32_t* dhist,
-                          float* p99_out, int32_t* flags_out, const DevInfo& dev, hipStream_t s,
-                          float* range_out = nullptr) {
+// the selection state, two digit passes over all values, the gathering of the values that share
+// their prefix, the last digits in one workgroup per stain.  ws: sel_workspace_bytes().
+static void launch_select(const BasisWork* bw, const double* H, int64_t n_s, double q, uint8_t* ws, float* p99_out,
+                          int32_t* flags_out, const DevInfo& dev, hipStream_t s, float* range_out = nullptr) {
+    SelState* sel = reinterpret_cast<SelState*>(ws);
+    uint32_t* dhist = reinterpret_cast<uint32_t*>(ws + align256(sizeof(SelState)));
+    unsigned long long* cand = reinterpret_cast<unsigned long long*>(
+        ws + align256(sizeof(SelState)) + align256((size_t)2 * SEL_BINS * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(64), 0, s, bw, q, sel, dhist);
     const int64_t sel_want = hmin((n_s + 1023) / 1024, (int64_t)dev.cus);
     const unsigned sel_grid = (unsigned)(sel_want > 0 ? sel_want : 1);
-    for (int pass = 0; pass < SEL_PASSES; ++pass) {
+    for (int pass = 0; pass < SEL_GATHER_PASSES; ++pass) {
         hipLaunchKernelGGL(k_sel_digits, dim3(sel_grid, 2), dim3(256), 0, s, H, n_s, (const SelState*)sel, dhist, pass);
         hipLaunchKernelGGL(k_sel_pick, dim3(2), dim3(256), 0, s, sel, dhist, pass, n_s, p99_out, flags_out, range_out);
     }
+    hipLaunchKernelGGL(k_sel_gather, dim3(sel_grid, 2), dim3(256), 0, s, H, n_s, sel, cand);
+    hipLaunchKernelGGL(k_sel_finish, dim3(2), dim3(256), 0, s, sel, (const unsigned long long*)cand, H, n_s, p99_out,
+                       flags_out, range_out);
 }
 
 hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK& pk, float lambda_nmf,
@@ -859,8 +977,7 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     double* od = reinterpret_cast<double*>(p); p += align256((size_t)3 * kHistBins * sizeof(double));
     double* xchg = reinterpret_cast<double*>(p); p += align256(FIT_XCHG_BYTES);
     double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
-    SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
-    uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
+    uint8_t* sel_ws = p;
 
     const int64_t max_cand = 64 * n_s;
     hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, w_init, xchg, od, pk.i0[0], pk.i0[1],
@@ -879,7 +996,7 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     if (sample_p99 || range_out) {
         hipLaunchKernelGGL(k_nmf_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
                            (const BasisWork*)bw, (const double*)V, (double)lambda_nmf, H);
-        launch_select(bw, H, n_s, pk.q64, sel, dhist, sample_p99, nullptr, dev, s, range_out);
+        launch_select(bw, H, n_s, pk.q64, sel_ws, sample_p99, nullptr, dev, s, range_out);
     }
     return hipGetLastError();
 }
@@ -1000,8 +1117,7 @@ __global__ __launch_bounds__(256) void k_sample_dens(const uint8_t* img, const i
 
 size_t sample_pctl_workspace_bytes(int64_t n_s) {
     if (n_s <= 0) return 0;
-    return i0_workspace_bytes(n_s) + align256((size_t)2 * n_s * sizeof(double)) + align256(sizeof(SelState)) +
-           align256((size_t)2 * SEL_BINS * sizeof(uint32_t));
+    return i0_workspace_bytes(n_s) + align256((size_t)2 * n_s * sizeof(double)) + sel_workspace_bytes();
 }
 
 hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const float* w, const ParamsK& pk, int64_t n_s,
@@ -1014,8 +1130,7 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     int32_t* counts = reinterpret_cast<int32_t*>(p); p += align256((size_t)(nbmax + 1) * sizeof(int32_t));
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
     double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
-    SelState* sel = reinterpret_cast<SelState*>(p); p += align256(sizeof(SelState));
-    uint32_t* dhist = reinterpret_cast<uint32_t*>(p);
+    uint8_t* sel_ws = p;
     const int64_t max_cand = 64 * n_s;
     hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, (const float*)nullptr,
                        (double*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
@@ -1029,7 +1144,7 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     }
     hipLaunchKernelGGL(k_sample_dens, dim3((unsigned)hmin((n_s + 255) / 256, (int64_t)dev.cus * 4)), dim3(256), 0, s,
                        img, (const int64_t*)idx, (const BasisWork*)bw, w, pk.lambda, pk.i0[0], pk.i0[1], pk.i0[2], H);
-    launch_select(bw, H, n_s, pk.q64, sel, dhist, p99_out, flags_out, dev, s);
+    launch_select(bw, H, n_s, pk.q64, sel_ws, p99_out, flags_out, dev, s);
     return hipGetLastError();
 }
 

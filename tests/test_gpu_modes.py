@@ -76,6 +76,27 @@ def test_sample_percentile_matches_oracle(S, orc, seed, h, w, n_s):
     assert bool(flags.cpu().numpy()[0] & S.FLAG_SHORT) == (kept < n_s)
 
 
+@pytest.mark.parametrize("colours", [[(140, 80, 160)], [(140, 80, 160), (90, 60, 150)]])
+def test_sample_percentile_ties(S, orc, colours):
+    """Samples with many equal densities: one colour (all 40000 samples equal) or two colours in
+    halves, so more values share the first two selection digits than the gathering keeps and the
+    last digits are taken over all values; the result equals the oracle's nearest rank."""
+    h, w = 200, 300
+    img = torch.empty((h, w, 3), dtype=torch.uint8, device=DEV)
+    for k, c in enumerate(colours):
+        img[k * h // len(colours):(k + 1) * h // len(colours)] = torch.tensor(c, dtype=torch.uint8, device=DEV)
+    W = synth.reference_basis()
+    p = S.params()
+    for n_s in (40000, 5000):
+        P, flags = S.spcn_sample_percentile(img, S.as_basis(W, DEV), n_s, seed=5, p=p)
+        torch.cuda.synchronize()
+        o_P, kept, o_f = orc.sample_percentile(img.cpu().numpy(), orc.f32(orc.basis(W)), n_s, seed=5,
+                                               lam=orc.f32(p.lambda_))
+        g = P.cpu().numpy()
+        assert np.all(np.abs(g - o_P.astype(np.float32)) <= np.spacing(np.float32(o_P.max()))), (n_s, g, o_P)
+        assert kept == n_s and int(flags.cpu().numpy().max()) == 0
+
+
 def test_recolor_given_percentiles(S, orc):
     src = synth.make_image(0, 512, 640, device=DEV)
     tgt = synth.make_image(1, 256, 256, device=DEV)
