@@ -471,47 +471,55 @@ __device__ __forceinline__ void p1f_unit_sums(const P1FLds<WIDE>& S, const P1FLa
     }
 }
 
-// R + G + B of the four pixels of a unit (byte dot products).
+// R + G + B of the four pixels of a unit (byte dot products; pixels 1 and 2 from the same gathered
+// dwords as the wide layout's table addresses, which the compiler shares).
 __device__ __forceinline__ void p1f_white_sums(uint32_t X, uint32_t Y0, uint32_t Z, int32_t (&sum)[4]) {
     sum[0] = (int32_t)__builtin_amdgcn_udot4(X, 0x00010101u, 0u, false);
-    sum[1] = (int32_t)__builtin_amdgcn_udot4(Y0, 0x00000101u, __builtin_amdgcn_udot4(X, 0x01000000u, 0u, false), false);
-    sum[2] = (int32_t)__builtin_amdgcn_udot4(Z, 0x00000001u, __builtin_amdgcn_udot4(Y0, 0x01010000u, 0u, false), false);
+    sum[1] = (int32_t)__builtin_amdgcn_udot4(__builtin_amdgcn_perm(Y0, X, 0x0c050403u), 0x00010101u, 0u, false);
+    sum[2] = (int32_t)__builtin_amdgcn_udot4(__builtin_amdgcn_perm(Z, Y0, 0x0c040302u), 0x00010101u, 0u, false);
     sum[3] = (int32_t)__builtin_amdgcn_udot4(Z, 0x01010100u, 0u, false);
 }
 
-// Histogram adds of one unit per active lane from its white sums and fixed-point candidate sums;
-// returns the lanes with a near-edge non-white pixel (left out here, for p1f_settle).
+// Histogram bin address of a fixed-point candidate sum (shifted guard, see the layout comment).
+template <bool WIDE, bool U16>
+__device__ __forceinline__ uint32_t p1f_bin_addr(const P1FLds<WIDE>& S, int32_t y, uint32_t lh) {
+    return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
+               : p1f_hist_addr(min(max(y >> S.shift, 0), kHistBins - 1), lh);
+}
+
+// Histogram adds of one unit per active lane from its white sums and fixed-point candidate sums.
+// One edge test per unit: a unit with any of its 8 candidate sums near a bin edge is left out here
+// and settled whole by p1f_settle (rare); returns those lanes.
 template <bool WIDE, bool U16>
 __device__ __forceinline__ uint64_t p1f_bins(P1FLds<WIDE>& S, const P1FLane& L, const int32_t (&sum)[4],
                                              const int32_t (&y0)[4], const int32_t (&y1)[4], int32_t thr,
                                              uint32_t nmask, uint64_t valid_lanes) {
-    const int u = U16 ? 16 : S.shift;
     char* base = reinterpret_cast<char*>(S.mem);
-    auto bin_addr = [&](int32_t y, uint32_t lh) -> uint32_t {
-        return U16 ? __builtin_amdgcn_perm((uint32_t)min(max(y, 0), 0xFFFFFF), lh, perm_sel(2))
-                   : p1f_hist_addr(min(max(y >> u, 0), kHistBins - 1), lh);
-    };
-    uint64_t nearm = 0;
+    // k(y) is 0 exactly when y is near an edge (p1f_near), so the unit is near one iff the minimum is 0
+    const uint32_t nv = nmask & 0x7FFFFFFFu;
+    auto k = [&](int32_t y) { return ((uint32_t)y & nmask) ^ nv; };
+    const uint32_t m0 = min(min(k(y0[0]), k(y0[1])), min(k(y0[2]), k(y0[3])));
+    const uint32_t m1 = min(min(k(y1[0]), k(y1[1])), min(k(y1[2]), k(y1[3])));
+    const uint64_t nearm = __ballot(min(m0, m1) == 0u) & valid_lanes;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        // every lane predicate is a plain compare whose ballot is its scalar mask: the masks are
-        // combined in scalar registers and turned into the 0/1 increment by one select (a ballot
-        // of a combined predicate would cost two vector instructions per pixel)
+        // lane predicates are plain compares whose ballots are scalar masks, combined in scalar
+        // registers and turned into the 0/1 increment by one select
         const uint64_t white = __ballot(sum[q] >= thr);
-        const uint64_t nr = __ballot(p1f_near(y0[q], nmask)) | __ballot(p1f_near(y1[q], nmask));
-        nearm |= nr & ~white & valid_lanes;
-        const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nr)) ? 1u : 0u;
-        atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y0[q], L.lh)), inc);
-        atomicAdd(reinterpret_cast<uint32_t*>(base + bin_addr(y1[q], L.lh1)), inc);
+        const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nearm)) ? 1u : 0u;
+        atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y0[q], L.lh)), inc);
+        atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y1[q], L.lh1)), inc);
     }
     return nearm;
 }
 
-// Settles the near-edge non-white pixels of one unit per lane in FP64 (lanes in nearm; rare).
-template <bool WIDE>
+// Counts the non-white pixels of the units p1f_bins left out (lanes in nearm; rare): a pixel near a
+// bin edge in FP64, the others by their fixed-point bins.
+template <bool WIDE, bool U16>
 __device__ __forceinline__ void p1f_settle(P1FLds<WIDE>& S, const P1Params& pp, const P1FLane& L, uint32_t X,
                                            uint32_t Y0, uint32_t Z, uint64_t nearm, int32_t thr, uint32_t nmask) {
     if (nearm && __builtin_amdgcn_inverse_ballot_w64(nearm)) {
+        char* base = reinterpret_cast<char*>(S.mem);
         u32x3 un;
         un.x = X; un.y = Y0; un.z = Z;
         uint32_t px[4][3];
@@ -522,7 +530,12 @@ __device__ __forceinline__ void p1f_settle(P1FLds<WIDE>& S, const P1Params& pp, 
             if ((int32_t)(R + G + Bc) >= thr) continue;
             int32_t y0, y1;
             p1f_sums(S, R, G, Bc, L.r16, y0, y1);
-            if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) p1f_exact(S, pp, R, G, Bc, L.lh);
+            if (p1f_near(y0, nmask) | p1f_near(y1, nmask)) {
+                p1f_exact(S, pp, R, G, Bc, L.lh);
+            } else {
+                atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y0, L.lh)), 1u);
+                atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y1, L.lh1)), 1u);
+            }
         }
     }
 }
@@ -543,7 +556,7 @@ __device__ __forceinline__ void p1f_count(P1FLds<WIDE>& S, const P1Params& pp, c
         p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
         nearm = p1f_bins<WIDE, U16>(S, L, sum, y0, y1, thr, nmask, valid_lanes);
     }
-    p1f_settle(S, pp, L, X, Y0, Z, nearm, thr, nmask);
+    p1f_settle<WIDE, U16>(S, pp, L, X, Y0, Z, nearm, thr, nmask);
 }
 
 // Units with a non-white pixel waiting for a full wavefront of counting work (wide layout): lanes
@@ -1094,7 +1107,7 @@ __device__ void p1f_tiles_dens16(P1FLds<true>& S, const P1Params& pp, const uint
             const uint64_t tl = __ballot(tissue);
             uint64_t nearm = 0;
             if (tissue) nearm = p1f_bins<true, true>(S, L, sum, y0, y1, thr, nmask, tl);
-            p1f_settle(S, pp, L, X, Y0, Z, nearm, thr, nmask);
+            p1f_settle<true, true>(S, pp, L, X, Y0, Z, nearm, thr, nmask);
         }
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];

@@ -127,8 +127,9 @@ __global__ void k_zero_u64(uint64_t* p, int n) {
 }
 
 // Pass 1 with the FP32 densities of every pixel (Eq. 2 with W fixed), planar [2][n_px]: the exact
-// histogram of k_pass1g's wide layout and, from the same read of each unit, the densities from the
-// FP32 tables of the recolour pass, one 16-byte store per unit and stain (3 B/px read, 8 B/px
+// histogram of k_pass1g's wide layout and, from the same read of each unit, the densities -- from the
+// fixed-point candidate sums of the histogram when u = 16 (p1f_tiles_dens16), else from the FP32
+// tables of the recolour pass -- one 16-byte store per unit and stain (3 B/px read, 8 B/px
 // written).  One 1024-thread workgroup per CU, the tiles in the scattered order of k_pass1g.
 template <int UNROLL>
 __global__ __launch_bounds__(1024, 4) void k_pass1d(const P1Args a, float* h_out) {
