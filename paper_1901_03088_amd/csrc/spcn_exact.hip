@@ -224,7 +224,7 @@ __device__ __forceinline__ void refine_units(const P1FLds<true>& S, const P1Para
 template <bool U16>
 __device__ void refine_tiles(const P1FLds<true>& S, const RefineArgs& a, int kb0, int kb1) {
     const int tid = threadIdx.x;
-    const P1FLane L = p1f_lane<true>(tid);
+    const P1FLane L = p1f_lane<true>(tid, a.pp.white_sum);
     const int64_t tu = (int64_t)RF_THREADS * RF_UNROLL;
     const int64_t n_tiles = (a.units + tu - 1) / tu;
     unsigned long long* t0 = a.ws.table;

@@ -408,16 +408,21 @@ __device__ __forceinline__ void p1f_sums(const P1FLds<WIDE>& S, uint32_t R, uint
 // 8..15 of region 0, B in 4..11 of region 1).  la[k] holds the read's region and group, sel[k] the
 // perm selector of its channel's byte in a dword holding the pixel as (R, G, B) in bytes 0..2, selz[k]
 // in one holding it in bytes 1..3.
+// wa is 2^32 - thr (thr the white-sum threshold, 2^31 - 1 without one) for p1f_bins, kept in a vector
+// register for the whole run: the byte dot product that takes it has its weights in a scalar register
+// and can read only one scalar operand.
 struct P1FLane {
-    uint32_t lane, r16, la, lb, lh, lh1;
+    uint32_t lane, r16, la, lb, lh, lh1, wa;
     uint32_t lk[3], sel[3], selz[3];
 };
 
 template <bool WIDE>
-__device__ __forceinline__ P1FLane p1f_lane(int tid) {
+__device__ __forceinline__ P1FLane p1f_lane(int tid, int32_t white_sum) {
     using Y = P1FLayout<WIDE>;
     P1FLane L;
     L.lane = (uint32_t)(tid & 63);
+    L.wa = 0u - (uint32_t)(white_sum > 0 ? white_sum : 0x7FFFFFFF);
+    __asm__("" : "+v"(L.wa));
     L.r16 = (uint32_t)(tid & (Y::kCopies - 1)) << 4;
     L.la = L.r16;
     L.lb = Y::kBRegion | L.r16;
@@ -487,13 +492,16 @@ __device__ __forceinline__ uint32_t p1f_bin_addr(const P1FLds<WIDE>& S, int32_t 
                : p1f_hist_addr(min(max(y >> S.shift, 0), kHistBins - 1), lh);
 }
 
-// Histogram adds of one unit per active lane from its white sums and fixed-point candidate sums.
+// Histogram adds of one unit per active lane from its pixel dwords and fixed-point candidate sums.
 // One edge test per unit: a unit with any of its 8 candidate sums near a bin edge is left out here
-// and settled whole by p1f_settle (rare); returns those lanes.
+// (its lane skips the adds) and settled whole by p1f_settle (rare); returns those lanes.  A pixel's
+// increment is bit 31 of R + G + B + L.wa = R + G + B + 2^32 - thr (one byte dot product; with
+// 0 < thr < 2^31 and R + G + B <= 765 the sum wraps below 2^31 exactly when R + G + B >= thr, a white
+// pixel).
 template <bool WIDE, bool U16>
-__device__ __forceinline__ uint64_t p1f_bins(P1FLds<WIDE>& S, const P1FLane& L, const int32_t (&sum)[4],
-                                             const int32_t (&y0)[4], const int32_t (&y1)[4], int32_t thr,
-                                             uint32_t nmask, uint64_t valid_lanes) {
+__device__ __forceinline__ uint64_t p1f_bins(P1FLds<WIDE>& S, const P1FLane& L, uint32_t X, uint32_t Y0, uint32_t Z,
+                                             const int32_t (&y0)[4], const int32_t (&y1)[4], uint32_t nmask,
+                                             uint64_t valid_lanes) {
     char* base = reinterpret_cast<char*>(S.mem);
     // k(y) is 0 exactly when y is near an edge (p1f_near), so the unit is near one iff the minimum is 0
     const uint32_t nv = nmask & 0x7FFFFFFFu;
@@ -501,14 +509,18 @@ __device__ __forceinline__ uint64_t p1f_bins(P1FLds<WIDE>& S, const P1FLane& L, 
     const uint32_t m0 = min(min(k(y0[0]), k(y0[1])), min(k(y0[2]), k(y0[3])));
     const uint32_t m1 = min(min(k(y1[0]), k(y1[1])), min(k(y1[2]), k(y1[3])));
     const uint64_t nearm = __ballot(min(m0, m1) == 0u) & valid_lanes;
+    if (!__builtin_amdgcn_inverse_ballot_w64(nearm)) {
+        // the pixels as (R, G, B, 0) dwords (1 and 2 gathered as for the table addresses); pixel 3 is
+        // bytes 1..3 of Z
+        const uint32_t px[4] = {X, __builtin_amdgcn_perm(Y0, X, 0x0c050403u), __builtin_amdgcn_perm(Z, Y0, 0x0c040302u),
+                                Z};
+        const uint32_t wt[4] = {0x00010101u, 0x00010101u, 0x00010101u, 0x01010100u};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        // lane predicates are plain compares whose ballots are scalar masks, combined in scalar
-        // registers and turned into the 0/1 increment by one select
-        const uint64_t white = __ballot(sum[q] >= thr);
-        const uint32_t inc = __builtin_amdgcn_inverse_ballot_w64(valid_lanes & ~(white | nearm)) ? 1u : 0u;
-        atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y0[q], L.lh)), inc);
-        atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y1[q], L.lh1)), inc);
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t inc = __builtin_amdgcn_udot4(px[q], wt[q], L.wa, false) >> 31;
+            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y0[q], L.lh)), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(base + p1f_bin_addr<WIDE, U16>(S, y1[q], L.lh1)), inc);
+        }
     }
     return nearm;
 }
@@ -547,14 +559,12 @@ __device__ __forceinline__ void p1f_count(P1FLds<WIDE>& S, const P1Params& pp, c
                                           uint32_t Y0, uint32_t Z, bool valid) {
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(U16 ? 16 : S.shift);
-    int32_t sum[4];
-    p1f_white_sums(X, Y0, Z, sum);
     const uint64_t valid_lanes = __ballot(valid);
     uint64_t nearm = 0;       // lanes with a near-edge non-white pixel
     if (valid) {
         int32_t y0[4], y1[4];
         p1f_unit_sums(S, L, X, Y0, Z, y0, y1);
-        nearm = p1f_bins<WIDE, U16>(S, L, sum, y0, y1, thr, nmask, valid_lanes);
+        nearm = p1f_bins<WIDE, U16>(S, L, X, Y0, Z, y0, y1, nmask, valid_lanes);
     }
     p1f_settle<WIDE, U16>(S, pp, L, X, Y0, Z, nearm, thr, nmask);
 }
@@ -644,25 +654,33 @@ __device__ __forceinline__ void p1f_flush(P1FLds<WIDE>& S, const P1Params& pp, c
 }
 
 // Contiguous run of cnt units (buffer resource rs over its bytes): each thread takes units tid,
-// tid + nthreads, ..., UNROLL of them per iteration with one iteration of prefetch.
+// tid + nthreads, ..., UNROLL of them per iteration with one iteration of prefetch.  Nothing for
+// cnt <= 0.
 template <bool WIDE, int UNROLL, bool U16>
 __device__ void p1f_run(P1FLds<WIDE>& S, const P1Params& pp, __amdgpu_buffer_rsrc_t rs, int cnt, int tid,
                         int nthreads) {
-    const P1FLane L = p1f_lane<WIDE>(tid);
+    if (cnt <= 0) return;
+    const P1FLane L = p1f_lane<WIDE>(tid, pp.white_sum);
     const int stride = nthreads * UNROLL;
     P1FPend P = p1f_pend();
-    u32x3 cur[UNROLL];
-#pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
-    for (int b0 = 0; b0 < cnt; b0 += stride) {   // the same trip count in every lane
+    int b0 = 0;                                // the same trip count in every lane
+    // one iteration: the next iteration's loads into nxt (past the run they return zeros), then cur
+    auto step = [&](const u32x3 (&cur)[UNROLL], u32x3 (&nxt)[UNROLL]) {
         const int lb0 = b0 + tid;
-        u32x3 nxt[UNROLL];
 #pragma unroll
-        for (int j = 0; j < UNROLL; ++j)   // prefetch; past the run the loads return zeros
+        for (int j = 0; j < UNROLL; ++j)
             nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (lb0 + stride + j * nthreads), 0, kLoadStream);
         p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, lb0, cnt, nthreads, P);
+        b0 += stride;
+    };
+    u32x3 ua[UNROLL], ub[UNROLL];              // two buffers taking turns, so no register copies
 #pragma unroll
-        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
+    for (int j = 0; j < UNROLL; ++j) ua[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
+    for (;;) {
+        step(ua, ub);
+        if (b0 >= cnt) break;
+        step(ub, ua);
+        if (b0 >= cnt) break;
     }
     p1f_flush<WIDE, U16>(S, pp, L, P);
 }
@@ -676,7 +694,7 @@ __device__ void p1f_run(P1FLds<WIDE>& S, const P1Params& pp, __amdgpu_buffer_rsr
 template <bool WIDE, int UNROLL, bool U16>
 __device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* src, int64_t n_units, int tid,
                           int nthreads, int64_t scatter, int64_t step) {
-    const P1FLane L = p1f_lane<WIDE>(tid);
+    const P1FLane L = p1f_lane<WIDE>(tid, pp.white_sum);
     const int64_t tu = (int64_t)nthreads * UNROLL;
     const int64_t n_tiles = (n_units + tu - 1) / tu;
     int64_t t = blockIdx.x;
@@ -686,23 +704,28 @@ __device__ void p1f_tiles(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* sr
         const bool in = tt < n_tiles;
         return chunk_rsrc(src, in ? tile * tu : 0, in ? min(tu, n_units - tile * tu) : 0);
     };
-    __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
     P1FPend P = p1f_pend();
-    u32x3 cur[UNROLL];
-#pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
-    for (; t < n_tiles; t += gridDim.x) {
+    // one tile: the next tile's loads into nxt, then the units of cur
+    auto tile_step = [&](const u32x3 (&cur)[UNROLL], u32x3 (&nxt)[UNROLL]) {
         int64_t pn = ph + step;
         if (pn >= n_tiles) pn -= n_tiles;
         const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);   // empty past the end: loads return zeros
-        u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const int cnt = (int)min(tu, n_units - ph * tu);
         p1f_units<WIDE, UNROLL, U16>(S, pp, L, cur, tid, cnt, nthreads, P);
-#pragma unroll
-        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
         ph = pn;
+        t += gridDim.x;
+    };
+    u32x3 ua[UNROLL], ub[UNROLL];   // two buffers taking turns, so no register copies between tiles
+    const __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) ua[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
+    for (;;) {
+        tile_step(ua, ub);
+        if (t >= n_tiles) break;
+        tile_step(ub, ua);
+        if (t >= n_tiles) break;
     }
     p1f_flush<WIDE, U16>(S, pp, L, P);
 }
@@ -723,7 +746,7 @@ __device__ void p1f_tail(P1FLds<WIDE>& S, const P1Params& pp, const uint8_t* px,
     const int u = S.shift;
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(u);
-    const P1FLane L = p1f_lane<WIDE>(threadIdx.x);
+    const P1FLane L = p1f_lane<WIDE>(threadIdx.x, pp.white_sum);
     char* base = reinterpret_cast<char*>(S.mem);
     for (int i = 0; i < n; ++i) {
         const uint32_t R = px[3 * i], G = px[3 * i + 1], Bc = px[3 * i + 2];
@@ -989,7 +1012,7 @@ template <bool WIDE, int UNROLL, bool U16>
 __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const RecolourConsts& K, const P1Params& pp,
                                const uint8_t* src, int64_t n_units, float* h, int64_t n_px, int tid, int nthreads,
                                int64_t scatter, int64_t step) {
-    const P1FLane L = p1f_lane<WIDE>(tid);
+    const P1FLane L = p1f_lane<WIDE>(tid, pp.white_sum);
     const int64_t tu = (int64_t)nthreads * UNROLL;
     const int64_t n_tiles = (n_units + tu - 1) / tu;
     int64_t t = blockIdx.x;
@@ -1051,7 +1074,7 @@ __device__ void p1f_tiles_dens(P1FLds<WIDE>& S, const P2Lds<1>& T, const Recolou
 template <int UNROLL>
 __device__ void p1f_tiles_dens16(P1FLds<true>& S, const P1Params& pp, const uint8_t* src, int64_t n_units, float* h,
                                  int64_t n_px, int tid, int nthreads, int64_t scatter, int64_t step) {
-    const P1FLane L = p1f_lane<true>(tid);
+    const P1FLane L = p1f_lane<true>(tid, pp.white_sum);
     const int32_t thr = pp.white_sum > 0 ? pp.white_sum : 0x7FFFFFFF;
     const uint32_t nmask = p1f_nmask(16);
     const float c0 = (float)((double)pp.hist_hi[0] / 16777216.0), c1 = (float)((double)pp.hist_hi[1] / 16777216.0);
@@ -1071,15 +1094,11 @@ __device__ void p1f_tiles_dens16(P1FLds<true>& S, const P1Params& pp, const uint
         const int nb = __builtin_amdgcn_readfirstlane((int)(16 * min(tu, n_units - tile * tu)));
         return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, nb, kBufDword3);
     };
-    __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
-    u32x3 cur[UNROLL];
-#pragma unroll
-    for (int j = 0; j < UNROLL; ++j) cur[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
-    for (; t < n_tiles; t += gridDim.x) {
+    // one tile: the next tile's loads into nxt, then the densities and counts of cur's units
+    auto tile_step = [&](const u32x3 (&cur)[UNROLL], u32x3 (&nxt)[UNROLL]) {
         int64_t pn = ph + step;
         if (pn >= n_tiles) pn -= n_tiles;
         const __amdgpu_buffer_rsrc_t rn = tile_rs(t + gridDim.x, pn);
-        u32x3 nxt[UNROLL];
 #pragma unroll
         for (int j = 0; j < UNROLL; ++j) nxt[j] = __builtin_amdgcn_raw_buffer_load_b96(rn, 12 * (tid + j * nthreads), 0, kLoadStream);
         const int cnt = (int)min(tu, n_units - ph * tu);
@@ -1106,12 +1125,21 @@ __device__ void p1f_tiles_dens16(P1FLds<true>& S, const P1Params& pp, const uint
             const bool tissue = valid && min(min(sum[0], sum[1]), min(sum[2], sum[3])) < thr;
             const uint64_t tl = __ballot(tissue);
             uint64_t nearm = 0;
-            if (tissue) nearm = p1f_bins<true, true>(S, L, sum, y0, y1, thr, nmask, tl);
+            if (tissue) nearm = p1f_bins<true, true>(S, L, X, Y0, Z, y0, y1, nmask, tl);
             p1f_settle<true, true>(S, pp, L, X, Y0, Z, nearm, thr, nmask);
         }
-#pragma unroll
-        for (int j = 0; j < UNROLL; ++j) cur[j] = nxt[j];
         ph = pn;
+        t += gridDim.x;
+    };
+    u32x3 ua[UNROLL], ub[UNROLL];   // two buffers taking turns, so no register copies between tiles
+    const __amdgpu_buffer_rsrc_t rs = tile_rs(t, ph);
+#pragma unroll
+    for (int j = 0; j < UNROLL; ++j) ua[j] = __builtin_amdgcn_raw_buffer_load_b96(rs, 12 * (tid + j * nthreads), 0, kLoadStream);
+    for (;;) {
+        tile_step(ua, ub);
+        if (t >= n_tiles) break;
+        tile_step(ub, ua);
+        if (t >= n_tiles) break;
     }
 }
 

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(1024, 4) void k_pass1d(const P1Args a, float* h_out
         const int tail = (int)(a.n_px - 4 * n_units);
         const uint8_t* px = a.src + 12 * n_units;
         p1f_tail(S, pp, px, tail);
-        const P1FLane L = p1f_lane<true>(0);
+        const P1FLane L = p1f_lane<true>(0, pp.white_sum);
         for (int i = 0; i < tail; ++i) {
             float h0, h1;
             if (u16) {   // the densities from the fixed-point sums, as in the body
