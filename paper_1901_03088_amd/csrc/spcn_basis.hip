@@ -296,18 +296,20 @@ constexpr int FIT_MAX_BLOCKS = 64;               // kMaxBasisSamples / FIT_PER_B
 constexpr uint32_t FIT_SPIN_LIMIT = 1u << 20;
 static_assert(FIT_MAX_BLOCKS * FIT_PER_BLOCK >= kMaxBasisSamples, "fit grid must cover every sample");
 static_assert(FIT_MAX_BLOCKS <= 64, "one partial row per lane of the reducing wavefront");
-// Exchange slot of one workgroup and round parity: one 128-byte line with the 9 sums and, after
-// them, the sequence word (measured faster than sequence words packed side by side, which every
-// workgroup then writes into the same two lines).
-constexpr int FIT_SLOT = 16;                     // doubles per slot: 9 sums, the sequence word, padding
-constexpr size_t FIT_XCHG_BYTES = (size_t)2 * FIT_MAX_BLOCKS * FIT_SLOT * sizeof(double);
+// Exchange slot of one workgroup and round parity: one 128-byte line whose first 9 words hold the
+// workgroup's sums as FP64 bit patterns with the lowest mantissa bit replaced by the round's tag
+// (bit 1 of the round number).  A slot of parity p is rewritten two rounds after it was read, so a
+// word shows the tag of its round exactly when it holds that round's sum; the words start with tag 1
+// (rounds 0 and 1 expect 0).  Readers clear the tag bit, so a sum reaches the W-step with its lowest
+// mantissa bit cleared (within one unit in the last place; zero stays zero).
+constexpr int FIT_SLOT = 16;                     // 64-bit words per slot: 9 tagged sums, padding
+constexpr int FIT_SUMS = 9;
+constexpr size_t FIT_XCHG_BYTES = (size_t)2 * FIT_MAX_BLOCKS * FIT_SLOT * sizeof(uint64_t);
 
-__device__ __forceinline__ double* fit_slot(double* xchg, int parity, int b) {
+__device__ __forceinline__ uint64_t* fit_slot(uint64_t* xchg, int parity, int b) {
     return xchg + ((size_t)parity * FIT_MAX_BLOCKS + b) * FIT_SLOT;
 }
-__device__ __forceinline__ uint32_t* fit_seq(double* xchg, int parity, int b) {
-    return reinterpret_cast<uint32_t*>(fit_slot(xchg, parity, b) + 9);
-}
+__device__ __forceinline__ uint64_t fit_tag(int round) { return (uint64_t)((round >> 1) & 1); }
 
 struct SampleArgs {
     const uint8_t* img; int64_t n_px; int32_t white_sum; uint64_t seed;
@@ -427,16 +429,16 @@ static void launch_round(const SampleArgs& a, const DevInfo& dev, hipStream_t s)
 
 // Workspace state of a sampling run (one workgroup of 256 threads).  With od set, also the FP64
 // optical densities od[c][k] of Eq. 1 for the given i0, which the copy stores per kept sample; with
-// xchg set, the fit's sequence words start below every round number.
+// xchg set, the fit's exchange words start with a tag no round expects first.
 __global__ __launch_bounds__(256) void k_basis_init(BasisWork* bw, int64_t n_s, int64_t max_cand, const float* w_init,
-                                                    double* xchg, double* od, float i00, float i01, float i02) {
+                                                    uint64_t* xchg, double* od, float i00, float i01, float i02) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         bw->n_s = n_s; bw->max_cand = max_cand; bw->n_acc = 0; bw->base = 0; bw->flags = 0;
         initial_basis(w_init, bw->W);
     }
     if (xchg)
-        for (int i = threadIdx.x; i < 2 * FIT_MAX_BLOCKS; i += blockDim.x)
-            *fit_seq(xchg, i / FIT_MAX_BLOCKS, i % FIT_MAX_BLOCKS) = 0u;
+        for (int i = threadIdx.x; i < 2 * FIT_MAX_BLOCKS * FIT_SUMS; i += blockDim.x)
+            fit_slot(xchg, i / (FIT_MAX_BLOCKS * FIT_SUMS), (i / FIT_SUMS) % FIT_MAX_BLOCKS)[i % FIT_SUMS] = 1ull;
     if (od) {
         const float i0[3] = {i00, i01, i02};
         for (int k = threadIdx.x; k < kHistBins; k += blockDim.x)
@@ -446,22 +448,23 @@ __global__ __launch_bounds__(256) void k_basis_init(BasisWork* bw, int64_t n_s, 
 
 // The whole fit in one launch: every workgroup holds up to FIT_PER_BLOCK samples in registers for
 // all rounds.  Per round each workgroup publishes its FP64 partial sums in its own slot (double-
-// buffered by round parity), then the round number as its sequence word (a release store, no
-// read-modify-write); one wavefront polls every workgroup's word (a lane each) until all show the
-// round.  Then every workgroup reduces the same partials in the same fixed order and performs the
-// same W-step, so all hold bit-identical W.  The grid (at most 64 workgroups) is far below what
+// buffered by round parity) as tagged words (see fit_slot), each one relaxed 64-bit atomic store:
+// the data is its own signal, so no release or acquire fence and no separate sequence word is
+// needed.  One wavefront polls every workgroup's slot (a lane each) until all 9 words show the
+// round's tag.  Then every workgroup reduces the same partials in the same fixed order and performs
+// the same W-step, so all hold bit-identical W.  The grid (at most 64 workgroups) is far below what
 // the chip keeps resident at once, so all workgroups run concurrently; the wait is bounded
 // nonetheless and reports SPCN_FLAG_TIMEOUT.
 struct FitArgs {
     BasisWork* bw;
     const double* V;        // [3][n_s]
-    double* xchg;           // [2][FIT_MAX_BLOCKS][FIT_SLOT] slots (+ sequence words), FIT_XCHG_BYTES
+    uint64_t* xchg;         // [2][FIT_MAX_BLOCKS][FIT_SLOT] tagged words, FIT_XCHG_BYTES
     double lambda;
     int32_t n_iter;
 };
 
 __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
-    __shared__ double s_red[9 * 16];
+    __shared__ double s_red[FIT_SUMS * 16];
     __shared__ NmfBasis s_B;         // the H-step constants of the current W
     __shared__ int s_abort;
     BasisWork* bw = a.bw;
@@ -477,25 +480,42 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
     for (int i = 0; i < 6; ++i) W[i] = bw->W[i];
     if (threadIdx.x == 0) nmf_basis(W, a.lambda, s_B);
     __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = FIT_THREADS >> 6;
     for (int it = 0; it < a.n_iter; ++it) {
         const NmfBasis B = s_B;
-        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[FIT_SUMS] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         nmf_sums(B, v, acc);
         const int par = it & 1;
-        block_sums(acc, s_red, fit_slot(a.xchg, par, blockIdx.x));   // the totals go straight into the slot
-        const uint32_t want = (uint32_t)(it + 1);
-        if (threadIdx.x == 0)   // the release orders the workgroup's slot stores (after the barrier) before it
-            __hip_atomic_store(fit_seq(a.xchg, par, blockIdx.x), want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (threadIdx.x < 64) {  // one wavefront: lane b waits for workgroup b, then reads its sums
-            const int lane = threadIdx.x;
+        const uint64_t tag = fit_tag(it);
+        // the workgroup's sums (wavefront sums, then the waves in order), tagged, into its slot
+        for (int q = 0; q < FIT_SUMS; ++q) acc[q] = wave_sum_d(acc[q]);
+        if (lane == 0)
+            for (int q = 0; q < FIT_SUMS; ++q) s_red[q * 16 + wave] = acc[q];
+        __syncthreads();
+        if (threadIdx.x < FIT_SUMS) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w) t += s_red[threadIdx.x * 16 + w];
+            const uint64_t word = ((uint64_t)__double_as_longlong(t) & ~1ull) | tag;
+            __hip_atomic_store(fit_slot(a.xchg, par, blockIdx.x) + threadIdx.x, word, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (threadIdx.x < 64) {  // one wavefront: lane b waits for workgroup b's words of this round
             bool ready = lane >= (int)nblk;
+            uint64_t w[FIT_SUMS];
+            for (int q = 0; q < FIT_SUMS; ++q) w[q] = 0ull;
             uint32_t spins = 0;
             int abort = 0;
-            for (;;) {   // the sequence words and the abort flag are read together: one round trip per poll
-                const uint32_t sq =
-                    ready ? want : __hip_atomic_load(fit_seq(a.xchg, par, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (;;) {   // the slot's words and the abort flag are read together: one round trip per poll
+                if (!ready) {
+                    const uint64_t* src = fit_slot(a.xchg, par, lane);
+                    uint64_t all = 1ull;
+                    for (int q = 0; q < FIT_SUMS; ++q) {
+                        w[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        all &= ((w[q] & 1ull) == tag) ? 1ull : 0ull;
+                    }
+                    ready = all != 0ull;
+                }
                 const int stop = __hip_atomic_load(&bw->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-                ready = sq >= want;
                 if (__ballot(!ready) == 0ull) break;
                 if (++spins > FIT_SPIN_LIMIT || __builtin_amdgcn_readfirstlane(stop)) {
                     if (lane == 0) atomicOr(&bw->flags, SPCN_FLAG_TIMEOUT);
@@ -504,13 +524,10 @@ __global__ __launch_bounds__(FIT_THREADS) void k_nmf_fit(FitArgs a) {
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            double tot[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            if (!abort && lane < (int)nblk) {
-                const double* src = fit_slot(a.xchg, par, lane);
-                for (int q = 0; q < 9; ++q) tot[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            for (int q = 0; q < 9; ++q) tot[q] = wave_sum_d(tot[q]);
+            double tot[FIT_SUMS];
+            for (int q = 0; q < FIT_SUMS; ++q)
+                tot[q] = (!abort && lane < (int)nblk) ? __longlong_as_double((long long)(w[q] & ~1ull)) : 0.0;
+            for (int q = 0; q < FIT_SUMS; ++q) tot[q] = wave_sum_d(tot[q]);
             if (lane == 0) {       // every workgroup: the same update on the same sums
                 s_abort = abort;
                 if (!abort) {
@@ -975,7 +992,7 @@ hipError_t launch_estimate_basis(const uint8_t* img, int64_t n_px, const ParamsK
     int64_t* idx = reinterpret_cast<int64_t*>(p); p += align256((size_t)n_s * sizeof(int64_t));
     double* V = reinterpret_cast<double*>(p); p += align256((size_t)3 * n_s * sizeof(double));
     double* od = reinterpret_cast<double*>(p); p += align256((size_t)3 * kHistBins * sizeof(double));
-    double* xchg = reinterpret_cast<double*>(p); p += align256(FIT_XCHG_BYTES);
+    uint64_t* xchg = reinterpret_cast<uint64_t*>(p); p += align256(FIT_XCHG_BYTES);
     double* H = reinterpret_cast<double*>(p); p += align256((size_t)2 * n_s * sizeof(double));
     uint8_t* sel_ws = p;
 
@@ -1075,7 +1092,7 @@ hipError_t launch_estimate_i0(const uint8_t* img, int64_t n_px, int32_t white_su
     uint32_t* ghist = reinterpret_cast<uint32_t*>(p);
     const int64_t max_cand = 64 * n_s;
     hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, (const float*)nullptr,
-                       (double*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
+                       (uint64_t*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
     hipLaunchKernelGGL(k_i0_clear, dim3(1), dim3(256), 0, s, ghist);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
@@ -1133,7 +1150,7 @@ hipError_t launch_sample_percentile(const uint8_t* img, int64_t n_px, const floa
     uint8_t* sel_ws = p;
     const int64_t max_cand = 64 * n_s;
     hipLaunchKernelGGL(k_basis_init, dim3(1), dim3(256), 0, s, bw, n_s, max_cand, (const float*)nullptr,
-                       (double*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
+                       (uint64_t*)nullptr, (double*)nullptr, 0.0f, 0.0f, 0.0f);
     int64_t t0 = 0;
     for (int r = 0; r < MAX_ROUNDS && t0 < max_cand; ++r) {
         const int64_t rc = hmin(round_candidates(n_s, r), max_cand - t0);
