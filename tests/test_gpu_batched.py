@@ -145,8 +145,8 @@ def test_batched_pipeline_graph_replay(S, orc):
 def test_batched_full_size(S, orc):
     """The 512-tile workload (sides 256..2048 in steps of 64, 698 Mpixel) through the benchmark's
     pipeline: every tile's basis fit from 4096 samples against the oracle's fit on the same samples,
-    every tile's histogram bit-exact and its percentile and flags equal to the oracle's, and 2048
-    seeded output pixels per tile recoloured by the oracle one by one."""
+    every tile's histogram bit-exact and its percentile and flags equal to the oracle's, and every
+    output pixel against the oracle's recolouring of its tile (differences counted on the device)."""
     import math
     p = S.params()
     shapes = synth.tile_shapes(512)
@@ -167,8 +167,7 @@ def test_batched_full_size(S, orc):
     Wtn = orc.f32(orc.basis(tgt["W"]))
     H0 = np.array([0.65, 0.70, 0.29]); E0 = np.array([0.07, 0.99, 0.11])
     W_init = orc.f32(np.stack([H0 / np.linalg.norm(H0), E0 / np.linalg.norm(E0)], axis=1))
-    rng = np.random.default_rng(9)
-    worst_ang, n_px, n_off = 0.0, 0, 0
+    worst_ang, n_px, n_off, n_worse, worst = 0.0, 0, 0, 0, 0
     for t in range(len(shapes)):
         img = srcs[t].cpu().numpy()
         idx = orc.sample_tissue(img, 4096, 30000 + t, p.white_sum)
@@ -188,14 +187,13 @@ def test_batched_full_size(S, orc):
             P.append(Pj); fl.append(f | (orc.RANGE_RETRY if bits >> j & 1 else 0))
         assert np.array_equal(p99[t], np.array(P).astype(np.float32)), t
         assert np.array_equal(flags[t], np.array(fl)), t
-        flat = img.reshape(-1, 3)
-        sel = rng.integers(0, flat.shape[0], 2048)
-        o = orc.recolor_u8(flat[sel].reshape(-1, 1, 3), Wn, Wtn, scn, np.array(P), lam=orc.f32(p.lambda_))
-        g = outs[t].cpu().numpy().reshape(-1, 3)[sel]
-        d = np.abs(o.reshape(-1, 3).astype(np.int32) - g.astype(np.int32)).max(axis=1)
-        assert (d <= 1).all(), t
-        n_px += d.size; n_off += int((d > 0).sum())
-    print(f"\n[batched 512] worst basis angle {worst_ang:.2e} rad; sampled pixels {n_px}, off by one {n_off}",
-          flush=True)
+        o = orc.recolor_u8(img, Wn, Wtn, scn, np.array(P), lam=orc.f32(p.lambda_))
+        d = (torch.from_numpy(o).to(DEV).to(torch.int16) - outs[t].to(torch.int16)).abs().amax(dim=2)
+        n_px += d.numel(); n_off += int((d > 0).sum()); n_worse += int((d > 1).sum())
+        worst = max(worst, int(d.max()))
+    print(f"\n[batched 512] worst basis angle {worst_ang:.2e} rad; every output pixel ({n_px}): off by one or "
+          f"more {n_off}, by more than one {n_worse} (largest difference {worst})", flush=True)
     assert worst_ang < 1e-6
-    assert n_off / n_px <= 0.02
+    assert n_px == total
+    assert n_worse == 0                      # every pixel within one level (measured: 4.9e4 off by one)
+    assert n_off / n_px <= 1e-3

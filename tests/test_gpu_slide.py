@@ -4,7 +4,8 @@ times (the default kernel variants, which are the ones the autotuner picks there
 * Histogram counts bit-exact against the oracle, whose histogram is assembled slot by slot from
   the slide's own pixels (every slot is a field of its own seed).
 * Percentile and scale equal to the oracle's (same counts, same FP64 formula).
-* Output within one uint8 level on a seeded sample of 2M pixels, recoloured by the oracle one by one.
+* Every output pixel against the oracle's recolouring of the slide (band by band, the differences
+  counted on the device): all within one uint8 level, at most 0.1% off by one.
 * The basis fitted from 200k samples of the slide against the oracle's fit on the same samples.
 """
 import math
@@ -69,17 +70,22 @@ def test_slide_normalize_full_size(S, orc, slide):
     assert np.array_equal(st["p99_src"].cpu().numpy(), P.astype(np.float32))
     assert np.allclose(st["scale"].cpu().numpy(), sc / P, rtol=1e-7)
     assert (st["flags"].cpu().numpy() == 0).all()
-    # a seeded sample of output pixels, recoloured by the oracle one by one
-    rng = np.random.default_rng(77)
-    idx = torch.from_numpy(rng.integers(0, synth.SLIDE_H * synth.SLIDE_W, 2_000_000)).to(DEV)
-    src_s = img.view(-1, 3)[idx].cpu().numpy()
-    out_s = out.view(-1, 3)[idx].cpu().numpy()
-    o = orc.recolor_u8(src_s.reshape(-1, 1, 3), Wn, Wtn, sc, P, lam=orc.f32(p.lambda_)).reshape(-1, 3)
-    d = np.abs(o.astype(np.int32) - out_s.astype(np.int32)).max(axis=1)
-    print(f"[slide] sampled pixels {d.size}: exact {int((d == 0).sum())} off by 1 {int((d == 1).sum())} "
-          f"worse {int((d > 1).sum())}", flush=True)
-    assert (d <= 1).mean() >= 0.9999
-    assert (d == 0).mean() >= 0.98
+    # every output pixel: the oracle recolours the slide band by band (its OpenMP loops), and the
+    # per-pixel largest channel difference is counted on the device
+    rows = 2500
+    n_exact = n_one = n_worse = worst = 0
+    for r0 in range(0, synth.SLIDE_H, rows):
+        o = orc.recolor_u8(img[r0:r0 + rows].cpu().numpy(), Wn, Wtn, sc, P, lam=orc.f32(p.lambda_))
+        d = (torch.from_numpy(o).to(DEV).to(torch.int16) - out[r0:r0 + rows].to(torch.int16)).abs().amax(dim=2)
+        n_exact += int((d == 0).sum()); n_one += int((d == 1).sum()); n_worse += int((d > 1).sum())
+        worst = max(worst, int(d.max()))
+        del o, d
+    n_all = synth.SLIDE_H * synth.SLIDE_W
+    print(f"[slide] every output pixel ({n_all}): exact {n_exact} off by 1 {n_one} worse {n_worse} "
+          f"(largest difference {worst})", flush=True)
+    assert n_exact + n_one + n_worse == n_all
+    assert n_worse == 0                      # every pixel within one level (measured: 1.8e5 off by one)
+    assert n_one / n_all <= 1e-3
 
 
 def test_slide_basis_full_size(S, orc, slide):
