@@ -10,12 +10,13 @@
 // least-squares update u = w_j + (B_j - W A_j) / A_jj, with A = H H^T, B = V H^T).  The unit-norm
 // equality of Eq. (2) is imposed after the last round.  The fit is small (<= a few 10^5 samples), so
 // it runs in FP64 throughout (FP64 vector rate equals FP32 scalar rate on this chip); reductions
-// have a fixed order, so results are bitwise reproducible.
+// have a fixed order, so results are bitwise reproducible (the exchanged partial sums lose their
+// lowest mantissa bit to the round tag).
 //
 // Two layouts:
 //   * one image with many samples: one launch for all rounds, up to 64 workgroups holding 4096
-//     samples each in registers; per round FP64 partial sums per workgroup published with a
-//     sequence word, and the same fixed-order reduction and W-step in every workgroup;
+//     samples each in registers; per round FP64 partial sums per workgroup published as words
+//     tagged with the round, and the same fixed-order reduction and W-step in every workgroup;
 //   * a batch of tiles: one 256-thread workgroup per tile, samples held in registers, every round
 //     inside the workgroup.
 #include "spcn_internal.h"
