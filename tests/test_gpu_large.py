@@ -1,0 +1,124 @@
+"""Sizes past the 32-bit boundaries: an image of 2^33 + 5 pixels (25.8 GB, a ragged tail of one
+pixel after the last 4-pixel unit), made by repeating a 1024 x 1024 image pixel by pixel, through the
+hot path.  Pixel indices pass 2^33, unit indices 2^31 and byte offsets 2^34.
+
+* Histogram: exactly floor(n / S) times the small image's histogram plus that of its first n mod S
+  pixels, both the oracle's (S = 2^20 pixels of the small image).
+* Percentile and scale: the oracle's from that histogram.
+* Output: the first repetition within one level of the oracle's recolouring of the small image with
+  that percentile, every other repetition and the tail byte-identical to it (a pixel's output
+  depends only on its colour and the image's constants).
+* Basis: the fit from 200k samples of the whole image against the oracle's fit on the same samples
+  (the sampler draws pixel indices over all 2^33 pixels).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+SIDE = 1024
+S_PX = SIDE * SIDE
+N_PX = (1 << 33) + 5
+
+
+@pytest.fixture(scope="module")
+def S():
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_1901_03088_amd as s
+    return s
+
+
+@pytest.fixture(scope="module")
+def large():
+    d = synth.make_image(3, SIDE, SIDE, device=DEV)
+    small = d["img"]
+    reps, rem = divmod(N_PX, S_PX)
+    big = torch.empty((1, N_PX, 3), dtype=torch.uint8, device=DEV)
+    flat, sflat = big.view(-1), small.reshape(-1)
+    flat[:reps * S_PX * 3].view(reps, S_PX * 3).copy_(sflat.unsqueeze(0).expand(reps, -1))
+    flat[reps * S_PX * 3:].copy_(sflat[:rem * 3])
+    torch.cuda.synchronize()
+    print(f"\n[large] {N_PX} pixels ({N_PX * 3 / 1e9:.1f} GB): {reps} repetitions of {SIDE}x{SIDE} + {rem}",
+          flush=True)
+    yield {"big": big, "small": small, "W": d["W"], "reps": reps, "rem": rem}
+    del big, flat
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_large_normalize(S, orc, large):
+    big, small, reps, rem = large["big"], large["small"], large["reps"], large["rem"]
+    p = S.params(hist_hi=(8.0, 8.0), auto_range=False)
+    tgt = synth.target_image(device=DEV)
+    ws, wt = S.as_basis(large["W"], DEV), S.as_basis(tgt["W"], DEV)
+    _, _, scale_tgt, _ = S.spcn_densities(tgt["img"], wt, p, want_h=False)
+    out, st = S.spcn_normalize(big, ws, wt, scale_tgt, p)
+    torch.cuda.synchronize()
+    # the oracle: histogram of the small image and of its first rem pixels
+    Wn, Wtn = orc.f32(orc.basis(large["W"])), orc.f32(orc.basis(tgt["W"]))
+    sm = small.cpu().numpy()
+    H, m = orc.densities_u8(sm, Wn, list(p.i0), orc.f32(p.lambda_), p.white_sum)
+    h_all = orc.histogram(H, m, list(p.hist_hi), 256).astype(np.uint64)
+    head = sm.reshape(-1, 3)[:rem].reshape(1, rem, 3)
+    H2, m2 = orc.densities_u8(head, Wn, list(p.i0), orc.f32(p.lambda_), p.white_sum)
+    h_head = orc.histogram(H2, m2, list(p.hist_hi), 256).astype(np.uint64)
+    expect = h_all * np.uint64(reps) + h_head
+    ghist = st["hist"].cpu().numpy().astype(np.uint64)
+    print(f"[large] tissue pixels {int(expect[0].sum())}; abs count diff "
+          f"{int(np.abs(ghist.astype(np.int64) - expect.astype(np.int64)).sum())}", flush=True)
+    assert int(expect[0].sum()) > (1 << 32)
+    assert np.array_equal(ghist, expect)
+    P = []
+    for j in range(2):
+        Pj, f, _ = orc.percentile_hist(expect[j], float(p.hist_hi[j]), orc.q_of(p.percentile))
+        assert f == 0
+        P.append(Pj)
+    P = np.array(P)
+    sc = scale_tgt.cpu().numpy().astype(np.float64)
+    assert np.array_equal(st["p99_src"].cpu().numpy(), P.astype(np.float32))
+    assert np.allclose(st["scale"].cpu().numpy(), sc / P, rtol=1e-7)
+    assert (st["flags"].cpu().numpy() == 0).all()
+    # output: the first repetition against the oracle, the others and the tail against the first
+    ref = orc.recolor_u8(sm, Wn, Wtn, sc, P, lam=orc.f32(p.lambda_)).reshape(-1, 3)
+    oflat = out.view(-1)
+    first = oflat[:S_PX * 3]
+    d = (torch.from_numpy(ref).to(DEV).to(torch.int16).view(-1) - first.to(torch.int16)).abs().view(-1, 3).amax(dim=1)
+    n_one, n_worse = int((d == 1).sum()), int((d > 1).sum())
+    print(f"[large] first repetition: off by one {n_one}, worse {n_worse}", flush=True)
+    assert n_worse == 0
+    assert n_one / S_PX <= 1e-3
+    rows = oflat[:reps * S_PX * 3].view(reps, S_PX * 3)
+    step = 512
+    for k0 in range(0, reps, step):
+        assert bool((rows[k0:k0 + step] == first.unsqueeze(0)).all()), k0
+    assert torch.equal(oflat[reps * S_PX * 3:], first[:rem * 3])
+    del out, oflat, rows, first, d
+
+
+def test_large_basis(S, orc, large):
+    big = large["big"]
+    p = S.params()
+    w, sp, flags = S.spcn_estimate_basis(big, 200000, seed=4242, p=p, lambda_nmf=0.1, n_iter=50)
+    torch.cuda.synchronize()
+    host = big.cpu().numpy()
+    idx = orc.sample_tissue(host, 200000, 4242, p.white_sum)
+    V = orc.od_samples(host, idx, list(p.i0))
+    del host
+    print(f"\n[large basis] largest sampled pixel index {int(idx.max())}", flush=True)
+    assert int(idx.max()) >= (1 << 32)
+    H0 = np.array([0.65, 0.70, 0.29]); E0 = np.array([0.07, 0.99, 0.11])
+    W_init = orc.f32(np.stack([H0 / np.linalg.norm(H0), E0 / np.linalg.norm(E0)], axis=1))
+    Wo, spo, _ = orc.nmf(V, orc.f32(0.1), 50, W_init, p.percentile)
+    a = np.asarray(w.cpu().numpy(), np.float64).reshape(2, 3)
+    b = np.asarray(Wo, np.float64).reshape(2, 3)
+    ang = [math.acos(min(1.0, a[j] @ b[j] / (np.linalg.norm(a[j]) * np.linalg.norm(b[j])))) for j in range(2)]
+    print(f"[large basis] angle rad {ang}, p99 gpu {sp.cpu().numpy()} oracle {spo}", flush=True)
+    assert max(ang) < 1e-6
+    assert np.allclose(sp.cpu().numpy(), spo, rtol=1e-6, atol=1e-9)
+    assert (flags.cpu().numpy() == 0).all()
