@@ -10,6 +10,8 @@ hot path.  Pixel indices pass 2^33, unit indices 2^31 and byte offsets 2^34.
   depends only on its colour and the image's constants).
 * Basis: the fit from 200k samples of the whole image against the oracle's fit on the same samples
   (the sampler draws pixel indices over all 2^33 pixels).
+* Densities output (2 x 34 GB planes): the first repetition within the header's bound of the
+  oracle's densities, every other repetition bit-identical to it.
 """
 import math
 
@@ -122,3 +124,37 @@ def test_large_basis(S, orc, large):
     assert max(ang) < 1e-6
     assert np.allclose(sp.cpu().numpy(), spo, rtol=1e-6, atol=1e-9)
     assert (flags.cpu().numpy() == 0).all()
+
+
+def test_large_densities(S, orc, large):
+    """spcn_densities with both FP32 planes (2 x 34 GB): the histogram bit-exact as above, the first
+    repetition's densities within the header's bound of the oracle's, every other repetition and
+    the tail bit-identical to it."""
+    big, small, reps, rem = large["big"], large["small"], large["reps"], large["rem"]
+    p = S.params(hist_hi=(8.0, 8.0), auto_range=False)
+    w = S.as_basis(large["W"], DEV)
+    h, hist, p99, flags = S.spcn_densities(big, w, p)
+    torch.cuda.synchronize()
+    Wn = orc.f32(orc.basis(large["W"]))
+    sm = small.cpu().numpy()
+    H, m = orc.densities_u8(sm, Wn, list(p.i0), orc.f32(p.lambda_), p.white_sum)
+    h_all = orc.histogram(H, m, list(p.hist_hi), 256).astype(np.uint64)
+    head = sm.reshape(-1, 3)[:rem].reshape(1, rem, 3)
+    H2, m2 = orc.densities_u8(head, Wn, list(p.i0), orc.f32(p.lambda_), p.white_sum)
+    expect = h_all * np.uint64(reps) + orc.histogram(H2, m2, list(p.hist_hi), 256).astype(np.uint64)
+    assert np.array_equal(hist.cpu().numpy().astype(np.uint64), expect)
+    P = np.array([orc.percentile_hist(expect[j], float(p.hist_hi[j]), orc.q_of(p.percentile))[0] for j in range(2)])
+    assert np.array_equal(p99.cpu().numpy(), P.astype(np.float32))
+    assert (flags.cpu().numpy() == 0).all()
+    bound = 2e-6 * max(1.0, max(float(v) for v in p.hist_hi))
+    step = 256
+    for j in range(2):
+        first = h[j, :S_PX]
+        err = float((first.double() - torch.from_numpy(H[j]).to(DEV)).abs().max())
+        print(f"\n[large densities] stain {j}: largest error of the first repetition {err:.2e}", flush=True)
+        assert err <= bound
+        rows = h[j, :reps * S_PX].view(reps, S_PX)
+        for k0 in range(0, reps, step):
+            assert torch.equal(rows[k0:k0 + step], first.unsqueeze(0).expand(min(step, reps - k0), -1)), (j, k0)
+        assert torch.equal(h[j, reps * S_PX:], first[:rem])
+    del h, rows, first
