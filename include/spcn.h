@@ -64,6 +64,8 @@ typedef enum {
 #define SPCN_FLAG_NO_BACKGROUND 128 /* spcn_estimate_i0 found no background pixel: i0 set to 255    */
 #define SPCN_FLAG_RANGE_RETRY 256   /* the percentile fell in the last bin at the range given; the
                                        histogram was rebuilt at twice this stain's range (auto_range) */
+#define SPCN_FLAG_SCALE    512  /* uint8 normalisation: the stain's scale_tgt is not finite and
+                                   positive (NaN, infinite, zero or negative): scale kept at 1      */
 
 #define SPCN_HIST_BINS 256
 
@@ -142,7 +144,8 @@ typedef struct {
  * writes uint8 (round half to even, clamped to [0, 255]).
  *   src, out   uint8 HWC images of height*width pixels (out may not alias src)
  *   w_src      [6] source basis;  w_tgt [6] target basis
- *   scale_tgt  [2] target percentiles P99(H_tgt) (e.g. p99_out of spcn_densities on the target)
+ *   scale_tgt  [2] target percentiles P99(H_tgt) (e.g. p99_out of spcn_densities on the target);
+ *              a stain whose value is not finite and positive is left unscaled (SPCN_FLAG_SCALE)
  *   i0_out     host [3] intensity of Eq. (4), or NULL for p->i0
  *   st         host struct of optional device outputs, or NULL
  *   ws         spcn_workspace_size(SPCN_OP_NORMALIZE, 0, 0, 0) bytes: histogram, range and retry
@@ -257,7 +260,8 @@ spcn_status spcn_exact_percentile(const uint8_t* img, int64_t height, int64_t wi
 
 /* Pass 2 of spcn_normalize with the source percentiles given (device [2], from any of the modes
  * above or from the caller): s_j = scale_tgt_j / p99_src_j, or 1 (SPCN_FLAG_BIN0) where p99_src_j is
- * not > 0.  Other arguments as for spcn_normalize (out may not alias src).  scale_out [2] and
+ * not > 0 (SPCN_FLAG_SCALE where scale_tgt_j is not finite and positive).  Other arguments as for
+ * spcn_normalize (out may not alias src).  scale_out [2] and
  * flags_out [2] (device) may be NULL.  No workspace. */
 spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, const float* w_src,
                              const float* w_tgt, const float* scale_tgt, const float* i0_out,
@@ -331,7 +335,7 @@ spcn_status spcn_estimate_basis_batched(const spcn_tile* tiles, int32_t n_tiles,
  *   tiles    device array of n_tiles descriptors (1 <= n_tiles <= 8192), 4-byte aligned pointers
  *   total_px an upper bound of the tiles' total pixel count (sizes the workspace; if the tiles hold
  *            more, nothing is processed and every tile's flags get SPCN_FLAG_BATCH)
- *   w_src [n_tiles][6]; w_tgt [6]; scale_tgt [2]; i0_out host [3] or NULL;
+ *   w_src [n_tiles][6]; w_tgt [6]; scale_tgt [2] (as for spcn_normalize); i0_out host [3] or NULL;
  *   p99_out, scale_out [n_tiles][2] or NULL; flags_out [n_tiles][2] or NULL;
  *   hist_out [n_tiles][2][256] uint64 or NULL: each tile's non-white histogram (at its final range).
  * Tile t's histogram range is p->hist_hi_dev[2t .. 2t+1] when given, else p->hist_hi; with
@@ -347,7 +351,8 @@ spcn_status spcn_normalize_batched(const spcn_tile* tiles, int32_t n_tiles, int6
 /* Differentiable float path (extension: normalisation as a training-time augmentation layer).
  * x, y: [n][3][height][width] FP32 in [0, 1] (p->i0 is the input's i0, normally 1).  Per-sample
  * parameters are read at sample*stride (stride 0 broadcasts one value): w_src (stride in floats,
- * 6 per basis), w_tgt (6), scale_tgt (2).  The percentile is the EXACT nearest-rank order statistic
+ * 6 per basis), w_tgt (6), scale_tgt (2; used as given: a differentiable parameter is not refused,
+ * so a NaN propagates as in any layer).  The percentile is the EXACT nearest-rank order statistic
  * of each sample's non-white densities, k = max(1, ceil(q * n)); the selected pixel (smallest index
  * among equal values) is returned in sel_idx so the backward pass can route its gradient.
  *   i0_out   host [3] output intensity of Eq. (4), or NULL for p->i0

@@ -26,7 +26,7 @@ _L = C.CDLL(LIB_PATH)
 
 SPCN_OK, SPCN_E_ARG, SPCN_E_WORKSPACE, SPCN_E_HIP, SPCN_E_UNSUPPORTED = range(5)
 FLAG_NO_TISSUE, FLAG_RANGE, FLAG_BIN0, FLAG_BASIS, FLAG_SHORT, FLAG_BATCH, FLAG_TIMEOUT, FLAG_NO_BACKGROUND, \
-    FLAG_RANGE_RETRY = 1, 2, 4, 8, 16, 32, 64, 128, 256
+    FLAG_RANGE_RETRY, FLAG_SCALE = 1, 2, 4, 8, 16, 32, 64, 128, 256, 512
 OP_DENSITIES, OP_NORMALIZE, OP_ESTIMATE_BASIS, OP_NORMALIZE_BATCHED, OP_ESTIMATE_BATCHED, \
     OP_FORWARD_F32, OP_BACKWARD_F32, OP_ESTIMATE_I0, OP_SAMPLE_PERCENTILE, OP_BAND_PERCENTILES, \
     OP_STREAM_NORMALIZE, OP_EXACT_PERCENTILE, OP_BANDWIDTH_PROBE = range(13)

@@ -378,7 +378,8 @@ __global__ __launch_bounds__(256) void k_tiles_check(CheckArgs a) {
         double s[2];
         int fl[2];
         for (int j = 0; j < 2; ++j) {
-            fl[j] = stain_flags(F, j, I.ok) | (I.bad ? SPCN_FLAG_BATCH : 0) | ((prev >> j & 1) ? SPCN_FLAG_RANGE_RETRY : 0);
+            fl[j] = stain_flags(F, j, I.ok) | (I.bad ? SPCN_FLAG_BATCH : 0) | ((prev >> j & 1) ? SPCN_FLAG_RANGE_RETRY : 0) |
+                    scale_flag(a.scale_tgt[j]);
             s[j] = stain_scale((double)a.scale_tgt[j], F.P[j], fl[j]);
             if (a.p99_out) a.p99_out[2 * t + j] = (float)F.P[j];
             if (a.scale_out) a.scale_out[2 * t + j] = (float)s[j];

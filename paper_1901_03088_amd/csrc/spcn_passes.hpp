@@ -820,9 +820,15 @@ __device__ inline int stain_flags(const FinalShared& F, int j, bool basis_ok) {
     return fl;
 }
 
-// Scale of Eq. (3): no tissue or a percentile in bin 0 keeps the density unscaled.
+// A target scale that is not finite and positive (NaN fails both compares) is refused.
+__device__ inline int scale_flag(float scale_tgt) {
+    return (scale_tgt > 0.0f && scale_tgt < __builtin_huge_valf()) ? 0 : SPCN_FLAG_SCALE;
+}
+
+// Scale of Eq. (3): no tissue, a percentile in bin 0 or a refused target scale keeps the density
+// unscaled.
 __device__ inline double stain_scale(double scale_tgt, double P, int fl) {
-    if ((fl & (SPCN_FLAG_NO_TISSUE | SPCN_FLAG_BIN0)) || !(P > 0.0)) return 1.0;
+    if ((fl & (SPCN_FLAG_NO_TISSUE | SPCN_FLAG_BIN0 | SPCN_FLAG_SCALE)) || !(P > 0.0)) return 1.0;
     return scale_tgt / P;
 }
 

@@ -214,8 +214,9 @@ __device__ void p2_prologue(const P2Args& a, P2Lds<COPIES>& T, FinalShared& F, B
         int fl[2];
         for (int j = 0; j < 2; ++j) {
             // a given percentile that is not > 0 keeps the stain unscaled, like a bin-0 percentile
-            fl[j] = a.p99_in ? ((F.P[j] > 0.0 ? 0 : SPCN_FLAG_BIN0) | (B.ok ? 0 : SPCN_FLAG_BASIS))
-                             : stain_flags(F, j, B.ok) | retry_flag(a.retry, j);
+            fl[j] = (a.p99_in ? ((F.P[j] > 0.0 ? 0 : SPCN_FLAG_BIN0) | (B.ok ? 0 : SPCN_FLAG_BASIS))
+                              : stain_flags(F, j, B.ok) | retry_flag(a.retry, j)) |
+                    scale_flag(a.scale_tgt[j]);
             s[j] = stain_scale((double)a.scale_tgt[j], F.P[j], fl[j]);
         }
         make_recolour(K, a.w_tgt, s, a.i0_out, B);

@@ -351,11 +351,13 @@ def test_degenerate_basis_flag(S):
 @pytest.mark.parametrize("W", [
     [[0.65, -0.05], [0.70, 0.99], [0.29, 0.11]],    # a negative entry with a positive Gram cross term
     [[0.9, -0.3], [0.1, 0.9], [0.4, 0.3]],          # negative cross term g01 < 0
+    [[0.65, 0.07], [float("nan"), 0.99], [0.29, 0.11]],   # a NaN entry
+    [[0.65, 0.07], [0.70, float("inf")], [0.29, 0.11]],   # an infinite entry
 ])
 def test_negative_basis_refused(S, W):
     """Eq. 2 requires W >= 0 (the closed-form density solve relies on it): a basis with a negative
-    entry is refused on the device -- SPCN_FLAG_BASIS, every density 0, the normalisation leaves
-    every pixel unscaled -- instead of returning densities of another problem."""
+    or non-finite entry is refused on the device -- SPCN_FLAG_BASIS, every density 0, the
+    normalisation leaves every pixel unscaled -- instead of returning densities of another problem."""
     img = synth.make_image(4, 64, 96, device=DEV)["img"]
     W = np.array(W)
     h, hist, p99, flags = gpu_densities(S, img, W, S.params())
@@ -366,6 +368,40 @@ def test_negative_basis_refused(S, W):
                                torch.tensor([1.0, 1.0], device=DEV), S.params())
     torch.cuda.synchronize()
     assert (st["flags"].cpu().numpy() & S.FLAG_BASIS).all()
+
+
+@pytest.mark.parametrize("bad", [(float("nan"), float("inf")), (-1.0, 0.0)])
+def test_invalid_target_scale_refused(S, orc, bad):
+    """A target scale that is not finite and positive is refused per stain (SPCN_FLAG_SCALE) and the
+    stain keeps scale 1: the output is the oracle's recolouring with s = 1 (its target scale set to
+    the source percentile), the histogram and percentile as usual; the batched path flags the same."""
+    src = synth.make_image(0, 512, 512, device=DEV)
+    tgt = synth.make_image(1, 256, 256, device=DEV)
+    p = S.params()
+    ws, wt = S.as_basis(src["W"], DEV), S.as_basis(tgt["W"], DEV)
+    sc = torch.tensor(bad, dtype=torch.float32, device=DEV)
+    out, st = S.spcn_normalize(src["img"], ws, wt, sc, p)
+    torch.cuda.synchronize()
+    st = {k: v.cpu().numpy() for k, v in st.items()}
+    _, o_st, o_hist = oracle_normalize(orc, src["img"], src["W"], tgt["W"], np.ones(2), p)
+    assert np.array_equal(st["hist"].astype(np.uint64), o_hist)
+    assert np.array_equal(st["p99_src"], o_st["P"].astype(np.float32))
+    assert np.array_equal(st["flags"], o_st["flags"] | S.FLAG_SCALE)
+    assert (st["scale"] == 1.0).all()
+    P = np.asarray(o_st["P"], dtype=np.float64)
+    o = orc.recolor_u8(np_img(src["img"]), orc.f32(orc.basis(src["W"])), orc.f32(orc.basis(tgt["W"])), P, P,
+                       lam=orc.f32(p.lambda_))
+    px = report("scale refused", np_img(out), o)
+    assert (px <= 1).all()
+    assert (px == 0).mean() >= 0.98
+    tiles = [src["img"], tgt["img"]]
+    outs = [torch.empty_like(t) for t in tiles]
+    Wb = torch.stack([ws, S.as_basis(tgt["W"], DEV)])
+    bs = S.spcn_normalize_batched(S.tile_table(tiles, outs), 2, sum(t.shape[0] * t.shape[1] for t in tiles), Wb, wt,
+                                  sc, p)
+    torch.cuda.synchronize()
+    assert (bs["flags"].cpu().numpy() & S.FLAG_SCALE).all()
+    assert (bs["scale"].cpu().numpy() == 1.0).all()
 
 
 def test_config1_densities_full_size(S, orc):
