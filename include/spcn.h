@@ -274,7 +274,8 @@ spcn_status spcn_recolor_p99(const uint8_t* src, int64_t height, int64_t width, 
  * candidates in draw order, at most 64*n_samples candidates), then n_iter alternating exact
  * H-steps and block-coordinate W-steps on the non-negative unit ball, normalises the columns and
  * puts hematoxylin (larger red-minus-blue OD) first.
- *   lambda_nmf   Eq. (2) sparsity weight for the fit (0.1 in the paper)
+ *   lambda_nmf   Eq. (2) sparsity weight for the fit (0.1 in the paper), finite and >= 0
+ *   n_samples    1 .. 262144;  n_iter 0 .. 100000
  *   w_init       [6] initial basis, or NULL for the unit reference H&E vectors
  *                [0.65, 0.70, 0.29] and [0.07, 0.99, 0.11]
  *   w_out        [6] fitted basis;  sample_p99 [2] nearest-rank percentile (p->percentile) of the

@@ -184,6 +184,26 @@ def test_estimate_i0_rejects(lib, kw, frag):
     assert frag in lib._L.spcn_last_error().decode()
 
 
+@pytest.mark.parametrize("kw,frag", [
+    (dict(n=0), "n_samples"),
+    (dict(n=262145), "n_samples"),
+    (dict(lam=float("nan")), "lambda_nmf"),
+    (dict(lam=-0.5), "lambda_nmf"),
+    (dict(it=-1), "n_iter"),
+    (dict(wsn=16), "workspace"),
+])
+def test_estimate_basis_rejects(lib, kw, frag):
+    """Host-side validation of the basis fit's arguments: nothing is enqueued."""
+    a = dict(n=200000, lam=0.1, it=50, wsn=1 << 30)
+    a.update(kw)
+    p = lib.params()
+    st = lib._L.spcn_estimate_basis(C.c_void_p(1 << 20), 64, 64, C.byref(p), C.c_float(a["lam"]), a["n"], C.c_uint64(1),
+                                    a["it"], None, C.c_void_p(1 << 24), None, None, None, C.c_void_p(1 << 28),
+                                    a["wsn"], None)
+    assert st in (lib.SPCN_E_ARG, lib.SPCN_E_WORKSPACE)
+    assert frag in lib._L.spcn_last_error().decode()
+
+
 def test_estimate_i0_workspace_size(lib):
     assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, 100000) > 100000 * 8
     assert lib.workspace_size(lib.OP_ESTIMATE_I0, 0, 0, (1 << 20) + 1) == 0

@@ -72,17 +72,22 @@ def test_estimate_basis_short_and_white(S, orc):
     assert np.isfinite(w.cpu().numpy()).all()
 
 
-def test_estimate_basis_large_sample(S, orc):
-    """200k samples (the gigapixel configuration's sample size) on an 8-Mpixel tissue block."""
+@pytest.mark.parametrize("n_s", [200000, 262144])
+def test_estimate_basis_large_sample(S, orc, n_s):
+    """200k samples (the gigapixel configuration's sample size) and the largest count the entry
+    point takes (262144: 64 fitting workgroups, every lane of the polling wavefront waits for one)
+    on an 8-Mpixel tissue block."""
     d = synth.make_image(21, 2048, 4096, device=DEV)
     p = S.params()
-    w, sp, flags = S.spcn_estimate_basis(d["img"], 200000, seed=99, p=p, lambda_nmf=0.1, n_iter=50)
+    w, sp, flags = S.spcn_estimate_basis(d["img"], n_s, seed=99, p=p, lambda_nmf=0.1, n_iter=50)
     torch.cuda.synchronize()
-    Wo, spo, idx = oracle_fit(orc, d["img"].cpu().numpy(), 200000, 99, orc.f32(0.1), 50, p)
+    Wo, spo, idx = oracle_fit(orc, d["img"].cpu().numpy(), n_s, 99, orc.f32(0.1), 50, p)
+    assert len(idx) == n_s
     ang = col_angles(w.cpu().numpy(), Wo)
-    print(f"[basis 200k] angle rad {ang}", flush=True)
+    print(f"[basis {n_s}] angle rad {ang}", flush=True)
     assert ang.max() < 1e-6
     assert np.allclose(sp.cpu().numpy(), spo, rtol=1e-6)
+    assert (flags.cpu().numpy() == 0).all()
 
 
 def test_estimate_basis_batched_tiles(S, orc):
