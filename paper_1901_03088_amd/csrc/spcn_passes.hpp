@@ -296,7 +296,7 @@ __device__ void p1_merge(P1Lds<COPIES, COLS>& S, unsigned long long* ghist) {
 // An address is (value << 8) | (region << 16) | lane bits; the perm takes the value byte from the
 // pixel's dword and the lane/region bytes from a per-lane constant.  With 2^16 fixed-point units
 // (when the basis allows it, see table_shift) the bin is byte 2 of the clamped sum, so a bin
-// address is one med3 + one perm.  Near-edge pixels take the same FP64 path as before.
+// address is one med3 + one perm.  Near-edge pixels are settled in FP64 (p1f_exact).
 //
 // The tables of this layout carry the guard shifted down by 2 * kGuardUnits: a sum y = x - 4 (x as
 // in the other layout) is near an edge k >= 1 iff y >= 0 and its low u bits are >= 2^u - 4, i.e.
@@ -405,7 +405,7 @@ __device__ __forceinline__ void p1f_sums(const P1FLds<WIDE>& S, uint32_t R, uint
 //   q = 0: B in 4+j, R in j,    G in 8+j        q = 2: R in j,    B in 4+j, G in 12+j
 //   q = 1: B in 8+j, G in 12+j, R in 4+j        q = 3: G in 12+j, B in 8+j, R in j
 // In each read the 16 lanes of a cycle use groups 0..15 once (R copies live in groups 0..7 and G in
-// 8..15 of region 0, B in 4..11 of region 1).  la[k] holds the read's region and group, sel[k] the
+// 8..15 of region 0, B in 4..11 of region 1).  lk[k] holds the read's region and group, sel[k] the
 // perm selector of its channel's byte in a dword holding the pixel as (R, G, B) in bytes 0..2, selz[k]
 // in one holding it in bytes 1..3.
 // wa is 2^32 - thr (thr the white-sum threshold, 2^31 - 1 without one) for p1f_bins, kept in a vector
