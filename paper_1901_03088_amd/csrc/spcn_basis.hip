@@ -146,7 +146,10 @@ __device__ __forceinline__ void nmf_rhs(const NmfBasis& B, double v0, double v1,
     b1 = W[3] * v0; b1 = b1 + W[4] * v1; b1 = b1 + W[5] * v2; b1 = b1 - B.half_lambda;
 }
 
-// The regular case (B.ok): branch-free.
+// The regular case (B.ok): branch-free.  SUMS: for the W-step's sums only, where the minimum may be
+// the hardware one (v_min_f64, which may return -0 where the compare-select returns +0; a signed
+// zero density adds the same zero to every sum).
+template <bool SUMS = false>
 __device__ __forceinline__ void nmf_solve_regular(const NmfBasis& B, double v0, double v1, double v2, double& h0,
                                                   double& h1) {
     double b0, b1;
@@ -154,7 +157,14 @@ __device__ __forceinline__ void nmf_solve_regular(const NmfBasis& B, double v0, 
     double f0 = (B.g11 * b0 - B.g01 * b1) * B.r_det;
     double f1 = (B.g00 * b1 - B.g01 * b0) * B.r_det;
     double p0 = b0 * B.r00, p1 = b1 * B.r11;
-    double t0 = p0 < f0 ? p0 : f0, t1 = p1 < f1 ? p1 : f1;
+    double t0, t1;
+    if constexpr (SUMS) {
+        t0 = __builtin_fmin(p0, f0);
+        t1 = __builtin_fmin(p1, f1);
+    } else {
+        t0 = p0 < f0 ? p0 : f0;
+        t1 = p1 < f1 ? p1 : f1;
+    }
     h0 = t0 > 0.0 ? t0 : 0.0;
     h1 = t1 > 0.0 ? t1 : 0.0;
 }
@@ -190,7 +200,7 @@ __device__ __forceinline__ void nmf_sums(const NmfBasis& B, const double (&v)[K]
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double h0, h1;
-            nmf_solve_regular(B, v[k][0], v[k][1], v[k][2], h0, h1);
+            nmf_solve_regular<true>(B, v[k][0], v[k][1], v[k][2], h0, h1);
             add(v[k], h0, h1);
         }
     } else {
