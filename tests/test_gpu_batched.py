@@ -92,6 +92,44 @@ def test_batched_chunk_sizes_identical(S):
         S.set_option(S.OPT_BATCH_CHUNK, saved)
 
 
+def test_batched_random_shapes_stress(S):
+    """A seeded batch of 300 tiles of random shapes (1 x 1 to 700 x 700, thin and ragged ones
+    included, every 23rd all background) through the work queue at the smallest and largest item
+    sizes: every tile's bytes, percentile and flags equal to spcn_normalize of that tile alone."""
+    rng = np.random.default_rng(321)
+    p = S.params()
+    shapes = [(int(rng.integers(1, 701)), int(rng.integers(1, 701))) for _ in range(300)]
+    shapes[5], shapes[6], shapes[7] = (1, 1), (1, 700), (700, 1)
+    tiles, srcs, outs = make_batch(shapes, seed0=700)
+    for t in range(0, len(shapes), 23):
+        srcs[t].fill_(250)
+    tgt, wt, sc = target(S, p)
+    W = torch.stack([S.as_basis(d["W"], DEV) for d in tiles]).contiguous()
+    table = S.tile_table(srcs, outs)
+    total = sum(h * w for h, w in shapes)
+    refs = []
+    for t in range(len(shapes)):
+        ref, rst = S.spcn_normalize(srcs[t], W[t].contiguous(), wt, sc, p)
+        refs.append((ref, rst["p99_src"].cpu().numpy(), rst["flags"].cpu().numpy()))
+    torch.cuda.synchronize()
+    assert all(int(refs[t][2][0]) & S.FLAG_NO_TISSUE for t in range(0, len(shapes), 23))
+    saved = S.get_option(S.OPT_BATCH_CHUNK)
+    try:
+        for c in (12, 18):
+            S.set_option(S.OPT_BATCH_CHUNK, c)
+            for o in outs:
+                o.zero_()
+            st = S.spcn_normalize_batched(table, len(shapes), total, W, wt, sc, p)
+            torch.cuda.synchronize()
+            p99 = st["p99"].cpu().numpy(); flags = st["flags"].cpu().numpy()
+            for t in range(len(shapes)):
+                assert torch.equal(refs[t][0], outs[t]), (c, t, shapes[t])
+                assert np.array_equal(refs[t][1], p99[t]), (c, t)
+                assert np.array_equal(refs[t][2], flags[t]), (c, t)
+    finally:
+        S.set_option(S.OPT_BATCH_CHUNK, saved)
+
+
 def test_batched_bad_total_px_flags(S):
     p = S.params()
     tiles, srcs, outs = make_batch([(64, 64), (128, 64)])
